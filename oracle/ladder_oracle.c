@@ -1,0 +1,342 @@
+/*
+ * ladder_oracle.c -- plain, slow FP64 CPU oracle for the V^4 O^2 particle-particle
+ * ladder of Cholesky-decomposed CCSD and its adjoint.
+ *
+ * TEST INFRASTRUCTURE ONLY.  Nothing in the product library links, loads or
+ * calls this file; only the test-suite, the smoke check and the CPU-baseline leg
+ * of the benchmark do.  It shares no code, header, table or helper with the HIP
+ * path.
+ *
+ * What it computes (Schnack-Petersen, Koch, Coriani, Kjonstad, arXiv 2202.02019):
+ *
+ *   g_acbd  = sum_J L^J_ac L^J_bd                 Sec. II A: Cholesky expansion
+ *                                                 of the ERIs, (pq|rs) = sum_J L^J_pq L^J_rs
+ *   R_ij^ab = sum_cd g_acbd tau_ij^cd             the A2 (particle-particle ladder)
+ *                                                 term of Omega cited in Sec. II B
+ *   E       = sum_ijab tbar_ij^ab R_ij^ab         the V^4 part of sum_pqrs g_pqrs d_pqrs
+ *                                                 (Sec. II A energy expression) with the
+ *                                                 ground-state density d_abcd = O^(2)_abcd
+ *                                                 (Appendix A, R_0 = 1, L_2 = tbar)
+ *   X^J_pq  = dE/dL^J_pq
+ *           = sum_bd L^J_bd sum_ij ( w_ij^pb tau_ij^qd + w_ij^bp tau_ij^dq )
+ *                                                 the L-built three-index intermediate
+ *                                                 (2 W~^J_pq of Sec. II C) restricted to
+ *                                                 the V^4 density block of Sec. II B.
+ *
+ * The adjoint is written in its general form: it does NOT assume the pair
+ * symmetry tau_ij^ab = tau_ji^ba (Appendix A, d_pqrs = d_rspq), so a GPU path that
+ * relies on that symmetry is caught by a parity test fed asymmetric input.
+ *
+ * Layouts (row-major, FP64):
+ *   L    [v][v][n]   L[(a*v+c)*n+J]        = L^J_ac   (virtual-virtual block)
+ *   tau  [o][o][v][v] tau[((i*o+j)*v+c)*v+d] = tau_ij^cd  (also tbar, w, R)
+ *   X    [v][v][n]   like L
+ *   Lov  [o][v][n]   Lov[(i*v+a)*n+J]      = L^J_ia   (occupied-virtual block)
+ *   eps  [o+v]       occupied orbital energies first, then virtual
+ *
+ * Every function returns 0 on success and -1 on a bad argument.
+ */
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
+
+int oracle_num_threads(void) {
+#ifdef _OPENMP
+    return omp_get_max_threads();
+#else
+    return 1;
+#endif
+}
+
+void oracle_set_num_threads(int t) {
+#ifdef _OPENMP
+    if (t > 0) omp_set_num_threads(t);
+#else
+    (void)t;
+#endif
+}
+
+/* Neumaier's compensated summation: running sum s with correction c. */
+static void neumaier_add(double* s, double* c, double x) {
+    double t = *s + x;
+    if (fabs(*s) >= fabs(x))
+        *c += (*s - t) + x;
+    else
+        *c += (x - t) + *s;
+    *s = t;
+}
+
+static int bad_dims(int64_t o, int64_t v, int64_t n) {
+    return o < 1 || v < 1 || n < 1 || o > 100000 || v > 100000 || n > 1000000;
+}
+
+/*
+ * Forward ladder for the virtual range a in [a_lo, a_hi):
+ *   R[i][j][a][b] = sum_c sum_d g_a[c][b][d] tau[i][j][c][d],
+ *   g_a[c][b][d]  = sum_J L[a][c][J] L[b][d][J].
+ * Rows a outside the range are left untouched.  If tbar and E_part are given,
+ * E_part[a - a_lo] = sum_ijb tbar_ij^ab R_ij^ab (compensated) and *E (if given)
+ * receives the compensated sum of E_part in increasing a.
+ */
+int oracle_ladder_forward_range(int64_t o, int64_t v, int64_t n, const double* L,
+                                const double* tau, const double* tbar, int64_t a_lo,
+                                int64_t a_hi, double* R, double* E_part, double* E) {
+    if (bad_dims(o, v, n) || !L || !tau || !R || a_lo < 0 || a_hi > v || a_lo > a_hi)
+        return -1;
+    const int64_t oo = o * o, vv = v * v;
+    double* Ea = (double*)calloc((size_t)(a_hi - a_lo) + 1, sizeof(double));
+    if (!Ea) return -1;
+    int fail = 0;
+#pragma omp parallel
+    {
+        double* g = (double*)malloc((size_t)(v * vv) * sizeof(double));
+        if (!g) {
+#pragma omp atomic write
+            fail = 1;
+        }
+#pragma omp for schedule(dynamic, 1)
+        for (int64_t a = a_lo; a < a_hi; ++a) {
+            if (!g) continue;
+            /* g_a[c][b][d] = (ac|bd) */
+            for (int64_t c = 0; c < v; ++c) {
+                const double* Lac = L + (a * v + c) * n;
+                for (int64_t b = 0; b < v; ++b)
+                    for (int64_t d = 0; d < v; ++d) {
+                        const double* Lbd = L + (b * v + d) * n;
+                        double s = 0.0;
+                        for (int64_t J = 0; J < n; ++J) s += Lac[J] * Lbd[J];
+                        g[(c * v + b) * v + d] = s;
+                    }
+            }
+            /* R_ij^ab = sum_cd (ac|bd) tau_ij^cd */
+            double es = 0.0, ec = 0.0;
+            for (int64_t ij = 0; ij < oo; ++ij) {
+                const double* t = tau + ij * vv;
+                for (int64_t b = 0; b < v; ++b) {
+                    double s = 0.0;
+                    for (int64_t c = 0; c < v; ++c) {
+                        const double* gc = g + (c * v + b) * v;
+                        const double* tc = t + c * v;
+                        for (int64_t d = 0; d < v; ++d) s += gc[d] * tc[d];
+                    }
+                    R[ij * vv + a * v + b] = s;
+                    if (tbar) neumaier_add(&es, &ec, tbar[ij * vv + a * v + b] * s);
+                }
+            }
+            Ea[a - a_lo] = es + ec;
+        }
+        free(g);
+    }
+    if (!fail && tbar) {
+        double s = 0.0, c = 0.0;
+        for (int64_t a = a_lo; a < a_hi; ++a) {
+            if (E_part) E_part[a - a_lo] = Ea[a - a_lo];
+            neumaier_add(&s, &c, Ea[a - a_lo]);
+        }
+        if (E) *E = s + c;
+    }
+    free(Ea);
+    return fail ? -1 : 0;
+}
+
+int oracle_ladder_forward(int64_t o, int64_t v, int64_t n, const double* L, const double* tau,
+                          const double* tbar, double* R, double* E) {
+    return oracle_ladder_forward_range(o, v, n, L, tau, tbar, 0, v, R, NULL, E);
+}
+
+/*
+ * Adjoint for the range p in [p_lo, p_hi), general (no pair symmetry assumed):
+ *   D1[b][q][d] = sum_ij w_ij^pb tau_ij^qd
+ *   D2[b][d][q] = sum_ij w_ij^bp tau_ij^dq
+ *   X[p][q][J]  = sum_b sum_d (D1[b][q][d] + D2[b][d][q]) L[b][d][J].
+ */
+int oracle_ladder_adjoint_range(int64_t o, int64_t v, int64_t n, const double* L,
+                                const double* tau, const double* w, int64_t p_lo,
+                                int64_t p_hi, double* X) {
+    if (bad_dims(o, v, n) || !L || !tau || !w || !X || p_lo < 0 || p_hi > v || p_lo > p_hi)
+        return -1;
+    const int64_t oo = o * o, vv = v * v;
+    int fail = 0;
+#pragma omp parallel
+    {
+        double* D1 = (double*)malloc((size_t)(v * vv) * sizeof(double));
+        double* D2 = (double*)malloc((size_t)(v * vv) * sizeof(double));
+        if (!D1 || !D2) {
+#pragma omp atomic write
+            fail = 1;
+        }
+#pragma omp for schedule(dynamic, 1)
+        for (int64_t p = p_lo; p < p_hi; ++p) {
+            if (!D1 || !D2) continue;
+            memset(D1, 0, (size_t)(v * vv) * sizeof(double));
+            memset(D2, 0, (size_t)(v * vv) * sizeof(double));
+            for (int64_t ij = 0; ij < oo; ++ij) {
+                const double* t = tau + ij * vv;
+                const double* wi = w + ij * vv;
+                for (int64_t b = 0; b < v; ++b) {
+                    const double w1 = wi[p * v + b]; /* w_ij^pb */
+                    const double w2 = wi[b * v + p]; /* w_ij^bp */
+                    double* d1 = D1 + b * vv;
+                    double* d2 = D2 + b * vv;
+                    for (int64_t k = 0; k < vv; ++k) {
+                        d1[k] += w1 * t[k]; /* k = q*v+d : tau_ij^qd */
+                        d2[k] += w2 * t[k]; /* k = d*v+q : tau_ij^dq */
+                    }
+                }
+            }
+            for (int64_t q = 0; q < v; ++q) {
+                double* x = X + (p * v + q) * n;
+                for (int64_t J = 0; J < n; ++J) x[J] = 0.0;
+                for (int64_t b = 0; b < v; ++b)
+                    for (int64_t d = 0; d < v; ++d) {
+                        const double coef = D1[(b * v + q) * v + d] + D2[(b * v + d) * v + q];
+                        const double* Lbd = L + (b * v + d) * n;
+                        for (int64_t J = 0; J < n; ++J) x[J] += coef * Lbd[J];
+                    }
+            }
+        }
+        free(D1);
+        free(D2);
+    }
+    return fail ? -1 : 0;
+}
+
+int oracle_ladder_adjoint(int64_t o, int64_t v, int64_t n, const double* L, const double* tau,
+                          const double* w, double* X) {
+    return oracle_ladder_adjoint_range(o, v, n, L, tau, w, 0, v, X);
+}
+
+/*
+ * Sampled forward: for each requested pair (a,b), out[k*o*o + ij] = R_ij^ab.
+ * g_ab[c][d] = sum_J L^J_ac L^J_bd is formed for that pair only.
+ */
+int oracle_ladder_R_sample(int64_t o, int64_t v, int64_t n, const double* L, const double* tau,
+                           int64_t npairs, const int64_t* ab, double* out) {
+    if (bad_dims(o, v, n) || !L || !tau || !ab || !out || npairs < 0) return -1;
+    for (int64_t k = 0; k < npairs; ++k)
+        if (ab[2 * k] < 0 || ab[2 * k] >= v || ab[2 * k + 1] < 0 || ab[2 * k + 1] >= v) return -1;
+    const int64_t oo = o * o, vv = v * v;
+    int fail = 0;
+#pragma omp parallel
+    {
+        double* g = (double*)malloc((size_t)vv * sizeof(double));
+        if (!g) {
+#pragma omp atomic write
+            fail = 1;
+        }
+#pragma omp for schedule(dynamic, 1)
+        for (int64_t k = 0; k < npairs; ++k) {
+            if (!g) continue;
+            const int64_t a = ab[2 * k], b = ab[2 * k + 1];
+            for (int64_t c = 0; c < v; ++c)
+                for (int64_t d = 0; d < v; ++d) {
+                    const double* Lac = L + (a * v + c) * n;
+                    const double* Lbd = L + (b * v + d) * n;
+                    double s = 0.0;
+                    for (int64_t J = 0; J < n; ++J) s += Lac[J] * Lbd[J];
+                    g[c * v + d] = s;
+                }
+            for (int64_t ij = 0; ij < oo; ++ij) {
+                const double* t = tau + ij * vv;
+                double s = 0.0;
+                for (int64_t cd = 0; cd < vv; ++cd) s += g[cd] * t[cd];
+                out[k * oo + ij] = s;
+            }
+        }
+        free(g);
+    }
+    return fail ? -1 : 0;
+}
+
+/*
+ * Sampled adjoint: for each requested pair (p,q), out[k*n + J] = X^J_pq in the
+ * general form of oracle_ladder_adjoint_range.
+ */
+int oracle_ladder_X_sample(int64_t o, int64_t v, int64_t n, const double* L, const double* tau,
+                           const double* w, int64_t npairs, const int64_t* pq, double* out) {
+    if (bad_dims(o, v, n) || !L || !tau || !w || !pq || !out || npairs < 0) return -1;
+    for (int64_t k = 0; k < npairs; ++k)
+        if (pq[2 * k] < 0 || pq[2 * k] >= v || pq[2 * k + 1] < 0 || pq[2 * k + 1] >= v) return -1;
+    const int64_t oo = o * o, vv = v * v;
+    int fail = 0;
+#pragma omp parallel
+    {
+        double* D = (double*)malloc((size_t)vv * sizeof(double));
+        if (!D) {
+#pragma omp atomic write
+            fail = 1;
+        }
+#pragma omp for schedule(dynamic, 1)
+        for (int64_t k = 0; k < npairs; ++k) {
+            if (!D) continue;
+            const int64_t p = pq[2 * k], q = pq[2 * k + 1];
+            /* D[b][d] = sum_ij (w_ij^pb tau_ij^qd + w_ij^bp tau_ij^dq) */
+            for (int64_t bd = 0; bd < vv; ++bd) D[bd] = 0.0;
+            for (int64_t ij = 0; ij < oo; ++ij) {
+                const double* t = tau + ij * vv;
+                const double* wi = w + ij * vv;
+                for (int64_t b = 0; b < v; ++b) {
+                    const double w1 = wi[p * v + b], w2 = wi[b * v + p];
+                    for (int64_t d = 0; d < v; ++d)
+                        D[b * v + d] += w1 * t[q * v + d] + w2 * t[d * v + q];
+                }
+            }
+            double* x = out + k * n;
+            for (int64_t J = 0; J < n; ++J) x[J] = 0.0;
+            for (int64_t bd = 0; bd < vv; ++bd) {
+                const double* Lbd = L + bd * n;
+                for (int64_t J = 0; J < n; ++J) x[J] += D[bd] * Lbd[J];
+            }
+        }
+        free(D);
+    }
+    return fail ? -1 : 0;
+}
+
+/*
+ * First-order (MP2-like) doubles amplitudes, the synthetic stand-in for CCSD T2:
+ *   t_ij^ab = (ia|jb) / (eps_i + eps_j - eps_a - eps_b),  (ia|jb) = sum_J L^J_ia L^J_jb
+ * with the Cholesky expansion of Sec. II A.  The denominator is formed as
+ * (eps_i + eps_j) - (eps_a + eps_b) so that t_ij^ab = t_ji^ba holds bitwise.
+ */
+int oracle_mp2_amplitudes(int64_t o, int64_t v, int64_t n, const double* Lov, const double* eps,
+                          double* t) {
+    if (bad_dims(o, v, n) || !Lov || !eps || !t) return -1;
+#pragma omp parallel for collapse(2) schedule(static)
+    for (int64_t i = 0; i < o; ++i)
+        for (int64_t j = 0; j < o; ++j)
+            for (int64_t a = 0; a < v; ++a)
+                for (int64_t b = 0; b < v; ++b) {
+                    const double* Lia = Lov + (i * v + a) * n;
+                    const double* Ljb = Lov + (j * v + b) * n;
+                    double s = 0.0;
+                    for (int64_t J = 0; J < n; ++J) s += Lia[J] * Ljb[J];
+                    const double den = (eps[i] + eps[j]) - (eps[o + a] + eps[o + b]);
+                    t[((i * o + j) * v + a) * v + b] = s / den;
+                }
+    return 0;
+}
+
+/*
+ * One Jacobi (diagonal-denominator) amplitude update, the standard quasi-Newton
+ * step for the amplitude equations Omega = 0 (Sec. II A):
+ *   t_ij^ab <- t_ij^ab + R_ij^ab / (eps_i + eps_j - eps_a - eps_b)
+ * with the same denominator association as oracle_mp2_amplitudes.
+ */
+int oracle_amplitude_update(int64_t o, int64_t v, const double* eps, const double* R, double* t) {
+    if (o < 1 || v < 1 || !eps || !R || !t) return -1;
+#pragma omp parallel for collapse(2) schedule(static)
+    for (int64_t i = 0; i < o; ++i)
+        for (int64_t j = 0; j < o; ++j)
+            for (int64_t a = 0; a < v; ++a)
+                for (int64_t b = 0; b < v; ++b) {
+                    const int64_t k = ((i * o + j) * v + a) * v + b;
+                    const double den = (eps[i] + eps[j]) - (eps[o + a] + eps[o + b]);
+                    t[k] = t[k] + R[k] / den;
+                }
+    return 0;
+}

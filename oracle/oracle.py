@@ -1,0 +1,173 @@
+"""ctypes binding of the C oracle in ladder_oracle.c plus the oracle-side input recipe.
+
+See ladder_oracle.c for the definitions and their citations.  ``build()`` compiles
+the C file with gcc (-O2, OpenMP, strict IEEE: no -ffast-math).
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+import time
+
+import numpy as np
+
+import synthetic
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+SRC = os.path.join(HERE, "ladder_oracle.c")
+LIB = os.path.join(HERE, "liboracle.so")
+
+__all__ = [
+    "build", "load", "forward", "adjoint", "forward_range", "adjoint_range", "R_sample",
+    "X_sample", "mp2_amplitudes", "amplitude_update", "make_inputs", "num_threads",
+    "set_num_threads", "flops_forward", "flops_adjoint",
+]
+
+_lib = None
+
+
+def build(force: bool = True) -> str:
+    """Compile liboracle.so with gcc; returns the path."""
+    if force or not os.path.exists(LIB) or os.path.getmtime(LIB) < os.path.getmtime(SRC):
+        tmp = LIB + ".tmp%d" % os.getpid()
+        cmd = ["gcc", "-O2", "-march=x86-64-v3", "-ffp-contract=off", "-fno-fast-math",
+               "-fopenmp", "-fPIC", "-shared", "-std=c11", "-Wall", "-Wextra", "-o", tmp, SRC, "-lm"]
+        subprocess.run(cmd, check=True)
+        os.replace(tmp, LIB)
+    return LIB
+
+
+def load():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB):
+            build()
+        lib = ctypes.CDLL(LIB)
+        i64, dp, vp = ctypes.c_int64, ctypes.c_void_p, ctypes.c_void_p
+        lib.oracle_ladder_forward_range.argtypes = [i64, i64, i64, dp, dp, dp, i64, i64, dp, dp, dp]
+        lib.oracle_ladder_adjoint_range.argtypes = [i64, i64, i64, dp, dp, dp, i64, i64, dp]
+        lib.oracle_ladder_R_sample.argtypes = [i64, i64, i64, dp, dp, i64, vp, dp]
+        lib.oracle_ladder_X_sample.argtypes = [i64, i64, i64, dp, dp, dp, i64, vp, dp]
+        lib.oracle_mp2_amplitudes.argtypes = [i64, i64, i64, dp, dp, dp]
+        lib.oracle_amplitude_update.argtypes = [i64, i64, dp, dp, dp]
+        lib.oracle_num_threads.restype = ctypes.c_int
+        lib.oracle_set_num_threads.argtypes = [ctypes.c_int]
+        for f in ("oracle_ladder_forward_range", "oracle_ladder_adjoint_range", "oracle_ladder_R_sample",
+                  "oracle_ladder_X_sample", "oracle_mp2_amplitudes", "oracle_amplitude_update"):
+            getattr(lib, f).restype = ctypes.c_int
+        _lib = lib
+    return _lib
+
+
+def _p(a):
+    return None if a is None else a.ctypes.data_as(ctypes.c_void_p)
+
+
+def _f64(a, shape=None):
+    a = np.ascontiguousarray(a, dtype=np.float64)
+    if shape is not None and a.size != int(np.prod(shape)):
+        raise ValueError("array of size %d where %s was expected" % (a.size, shape))
+    return a
+
+
+def num_threads() -> int:
+    return int(load().oracle_num_threads())
+
+
+def set_num_threads(t: int) -> None:
+    load().oracle_set_num_threads(int(t))
+
+
+def forward_range(o, v, n, L, tau, tbar, a_lo, a_hi, R=None):
+    """R rows a in [a_lo,a_hi) (other rows of R untouched), per-a energies and their sum."""
+    L = _f64(L, (v, v, n)); tau = _f64(tau, (o, o, v, v))
+    tbar = None if tbar is None else _f64(tbar, (o, o, v, v))
+    if R is None:
+        R = np.zeros((o, o, v, v))
+    Ep = np.zeros(max(1, a_hi - a_lo)); E = np.zeros(1)
+    rc = load().oracle_ladder_forward_range(o, v, n, _p(L), _p(tau), _p(tbar), a_lo, a_hi, _p(R), _p(Ep), _p(E))
+    if rc != 0:
+        raise RuntimeError("oracle_ladder_forward_range failed")
+    return R, Ep[: a_hi - a_lo], float(E[0])
+
+
+def forward(o, v, n, L, tau, tbar=None):
+    """Returns (R [o][o][v][v], E) with E = sum tbar*R (0.0 if tbar is None)."""
+    R, _, E = forward_range(o, v, n, L, tau, tbar, 0, v)
+    return R, E
+
+
+def adjoint_range(o, v, n, L, tau, w, p_lo, p_hi, X=None):
+    L = _f64(L, (v, v, n)); tau = _f64(tau, (o, o, v, v)); w = _f64(w, (o, o, v, v))
+    if X is None:
+        X = np.zeros((v, v, n))
+    rc = load().oracle_ladder_adjoint_range(o, v, n, _p(L), _p(tau), _p(w), p_lo, p_hi, _p(X))
+    if rc != 0:
+        raise RuntimeError("oracle_ladder_adjoint_range failed")
+    return X
+
+
+def adjoint(o, v, n, L, tau, w):
+    """X [v][v][n] = dE/dL with E = sum w * R(L, tau), general (no symmetry assumed)."""
+    return adjoint_range(o, v, n, L, tau, w, 0, v)
+
+
+def R_sample(o, v, n, L, tau, ab):
+    """R_ij^ab for pairs ab (k x 2 int array): returns [k][o*o]."""
+    L = _f64(L, (v, v, n)); tau = _f64(tau, (o, o, v, v))
+    ab = np.ascontiguousarray(ab, dtype=np.int64).reshape(-1, 2)
+    out = np.zeros((ab.shape[0], o * o))
+    if load().oracle_ladder_R_sample(o, v, n, _p(L), _p(tau), ab.shape[0], _p(ab), _p(out)) != 0:
+        raise RuntimeError("oracle_ladder_R_sample failed")
+    return out
+
+
+def X_sample(o, v, n, L, tau, w, pq):
+    """X^J_pq for pairs pq (k x 2): returns [k][n]."""
+    L = _f64(L, (v, v, n)); tau = _f64(tau, (o, o, v, v)); w = _f64(w, (o, o, v, v))
+    pq = np.ascontiguousarray(pq, dtype=np.int64).reshape(-1, 2)
+    out = np.zeros((pq.shape[0], n))
+    if load().oracle_ladder_X_sample(o, v, n, _p(L), _p(tau), _p(w), pq.shape[0], _p(pq), _p(out)) != 0:
+        raise RuntimeError("oracle_ladder_X_sample failed")
+    return out
+
+
+def mp2_amplitudes(o, v, n, Lov, eps):
+    Lov = _f64(Lov, (o, v, n)); eps = _f64(eps, (o + v,))
+    t = np.empty((o, o, v, v))
+    if load().oracle_mp2_amplitudes(o, v, n, _p(Lov), _p(eps), _p(t)) != 0:
+        raise RuntimeError("oracle_mp2_amplitudes failed")
+    return t
+
+
+def amplitude_update(o, v, eps, R, t):
+    """Returns a new array t + R/(eps_i+eps_j-eps_a-eps_b)."""
+    eps = _f64(eps, (o + v,)); R = _f64(R, (o, o, v, v)); t = np.array(t, dtype=np.float64, copy=True)
+    if load().oracle_amplitude_update(o, v, _p(eps), _p(R), _p(t)) != 0:
+        raise RuntimeError("oracle_amplitude_update failed")
+    return t
+
+
+def make_inputs(o, v, n, seed):
+    """The oracle-side inputs of the synthetic recipe: (L_vv, tau, tbar, L_ov, eps).
+
+    tau = t with t the first-order amplitudes built by the oracle from the draws,
+    tbar = t + 1e-2 * xi with the pair-symmetric noise xi.
+    """
+    Lvv = synthetic.draw_L_vv(seed, o, v, n)
+    Lov = synthetic.draw_L_ov(seed, o, v, n)
+    eps = synthetic.draw_eps(seed, o, v)
+    t = mp2_amplitudes(o, v, n, Lov, eps)
+    tbar = t + synthetic.NOISE_SCALE * synthetic.draw_noise_full(seed, o, v)
+    return Lvv, t, tbar, Lov, eps
+
+
+def flops_forward(o, v, n):
+    """Algorithmic dense flops of g (2 n v^4), R (2 o^2 v^4) and E (2 o^2 v^2)."""
+    return 2.0 * n * v ** 4 + 2.0 * o * o * v ** 4 + 2.0 * o * o * v * v
+
+
+def flops_adjoint(o, v, n):
+    """Algorithmic dense flops of D (2 o^2 v^4) and X (2 n v^4), pair-symmetric form."""
+    return 2.0 * o * o * v ** 4 + 2.0 * n * v ** 4

@@ -1,0 +1,255 @@
+"""Pins of the CPU oracle against facts fixed by the paper and by mathematics.
+
+None of these re-types the oracle's loops: each checks it against an independent
+route (hand-derived example, exact integer brute force, a matrix-product closed
+form, invariants of the definitions, finite differences) chosen so that a dropped
+term, a wrong index or a transposed operand in the oracle fails at least one.
+"""
+import json
+import os
+
+import numpy as np
+import pytest
+
+import synthetic
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+def rnd(seed, *shape):
+    return np.random.default_rng(seed).standard_normal(shape)
+
+
+def pair_sym(x):
+    """(x_ij^ab + x_ji^ba)/2: pair-symmetric part."""
+    return 0.5 * (x + x.transpose(1, 0, 3, 2))
+
+
+# ---------------------------------------------------------------- worked example
+def test_micro_example(oracle_lib):
+    g = json.load(open(os.path.join(GOLDEN, "micro_example.json")))
+    o, v, n = g["o"], g["v"], g["n"]
+    L = np.array(g["L"]); tau = np.array(g["tau"]); tbar = np.array(g["tbar"])
+    R, E = oracle_lib.forward(o, v, n, L, tau, tbar)
+    X = oracle_lib.adjoint(o, v, n, L, tau, tbar)
+    assert np.array_equal(R, np.array(g["R"]))
+    assert E == g["E"]
+    assert np.array_equal(X, np.array(g["X"]))
+
+
+# ---------------------------------------------------------------- exact brute force
+def _brute_int(o, v, n, L, tau, w):
+    """Six nested loops over the full 4-index g in exact Python integers."""
+    g = [[[[sum(L[a][c][J] * L[b][d][J] for J in range(n)) for d in range(v)] for c in range(v)]
+          for b in range(v)] for a in range(v)]  # g[a][b][c][d] = (ac|bd)
+    R = [[[[sum(g[a][b][c][d] * tau[i][j][c][d] for c in range(v) for d in range(v))
+            for b in range(v)] for a in range(v)] for j in range(o)] for i in range(o)]
+    E = sum(w[i][j][a][b] * R[i][j][a][b] for i in range(o) for j in range(o) for a in range(v) for b in range(v))
+    # X^J_pq = dE/dL^J_pq by the product rule on g_acbd = sum_J L^J_ac L^J_bd:
+    # L^J_pq enters as the first factor when (a,c) = (p,q) and as the second when (b,d) = (p,q).
+    X = [[[0] * n for _ in range(v)] for _ in range(v)]
+    for i in range(o):
+        for j in range(o):
+            for a in range(v):
+                for b in range(v):
+                    for c in range(v):
+                        for d in range(v):
+                            f = w[i][j][a][b] * tau[i][j][c][d]
+                            if f == 0:
+                                continue
+                            for J in range(n):
+                                X[a][c][J] += f * L[b][d][J]
+                                X[b][d][J] += f * L[a][c][J]
+    return R, E, X
+
+
+@pytest.mark.parametrize("seed,o,v,n", [(11, 2, 3, 2), (12, 1, 4, 3), (13, 3, 2, 1)])
+def test_integer_exact_brute_force(oracle_lib, seed, o, v, n):
+    rng = np.random.default_rng(seed)
+    L = rng.integers(-7, 8, size=(v, v, n))
+    tau = rng.integers(-7, 8, size=(o, o, v, v))
+    w = rng.integers(-7, 8, size=(o, o, v, v))  # deliberately neither symmetric
+    R_ref, E_ref, X_ref = _brute_int(o, v, n, L.tolist(), tau.tolist(), w.tolist())
+    R, E = oracle_lib.forward(o, v, n, L.astype(float), tau.astype(float), w.astype(float))
+    X = oracle_lib.adjoint(o, v, n, L.astype(float), tau.astype(float), w.astype(float))
+    assert np.array_equal(R, np.array(R_ref, dtype=float))
+    assert E == float(E_ref)
+    assert np.array_equal(X, np.array(X_ref, dtype=float))
+
+
+# ---------------------------------------------------------------- matrix closed forms
+def test_matrix_closed_form(oracle_lib):
+    o, v, n = 3, 7, 5
+    L, tau, w = rnd(1, v, v, n), rnd(2, o, o, v, v), rnd(3, o, o, v, v)
+    R, E = oracle_lib.forward(o, v, n, L, tau, w)
+    X = oracle_lib.adjoint(o, v, n, L, tau, w)
+    Lj = [np.ascontiguousarray(L[:, :, J]) for J in range(n)]
+    R_ref = np.zeros_like(R)
+    X_ref = np.zeros_like(X)
+    for i in range(o):
+        for j in range(o):
+            T, W = tau[i, j], w[i, j]
+            for J in range(n):
+                R_ref[i, j] += Lj[J] @ T @ Lj[J].T                  # R_ij = sum_J L^J T_ij L^J^T
+                X_ref[:, :, J] += W @ Lj[J] @ T.T + W.T @ Lj[J] @ T  # X^J = sum_ij W L T^T + W^T L T
+    np.testing.assert_allclose(R, R_ref, rtol=0, atol=1e-13 * np.abs(R_ref).max())
+    np.testing.assert_allclose(X, X_ref, rtol=0, atol=1e-13 * np.abs(X_ref).max())
+    assert abs(E - np.sum(w * R_ref)) <= 1e-13 * np.sum(np.abs(w * R_ref))
+
+
+def test_rank_one(oracle_lib):
+    """n=1, L_ac = u_a y_c:  R_ij^ab = u_a u_b (y^T T_ij y)."""
+    o, v = 2, 6
+    u, y = rnd(4, v), rnd(5, v)
+    L = np.einsum("a,c->ac", u, y)[:, :, None]
+    tau = rnd(6, o, o, v, v)
+    R, _ = oracle_lib.forward(o, v, 1, L, tau)
+    ref = np.einsum("a,b,ijcd,c,d->ijab", u, u, tau, y, y)
+    np.testing.assert_allclose(R, ref, rtol=0, atol=1e-13 * np.abs(ref).max())
+
+
+def test_zero_inputs(oracle_lib):
+    o, v, n = 2, 4, 3
+    L, tau = rnd(7, v, v, n), rnd(8, o, o, v, v)
+    R, E = oracle_lib.forward(o, v, n, L, np.zeros_like(tau), tau)
+    assert not R.any() and E == 0.0
+    R, E = oracle_lib.forward(o, v, n, np.zeros_like(L), tau, tau)
+    assert not R.any() and E == 0.0
+    assert not oracle_lib.adjoint(o, v, n, L, tau, np.zeros_like(tau)).any()
+
+
+# ---------------------------------------------------------------- invariants
+def test_pair_symmetry_of_R(oracle_lib):
+    """tau_ij^ab = tau_ji^ba  =>  R_ij^ab = R_ji^ba for any L (even asymmetric in ac)."""
+    o, v, n = 3, 6, 4
+    L, tau = rnd(9, v, v, n), pair_sym(rnd(10, o, o, v, v))
+    R, _ = oracle_lib.forward(o, v, n, L, tau)
+    np.testing.assert_allclose(R, R.transpose(1, 0, 3, 2), rtol=0, atol=1e-14 * np.abs(R).max())
+    # and the relation is not automatic: it fails for an asymmetric tau
+    R2, _ = oracle_lib.forward(o, v, n, L, rnd(10, o, o, v, v))
+    assert np.abs(R2 - R2.transpose(1, 0, 3, 2)).max() > 1e-3 * np.abs(R2).max()
+
+
+def test_euler_homogeneity(oracle_lib):
+    """E is homogeneous of degree 2 in L: sum_{J,ac} L^J_ac X^J_ac = 2E."""
+    o, v, n = 3, 5, 4
+    L, tau, w = rnd(11, v, v, n), rnd(12, o, o, v, v), rnd(13, o, o, v, v)
+    _, E = oracle_lib.forward(o, v, n, L, tau, w)
+    X = oracle_lib.adjoint(o, v, n, L, tau, w)
+    assert abs(np.sum(L * X) - 2 * E) <= 1e-13 * np.sum(np.abs(L * X))
+
+
+def test_scaling_and_bilinearity(oracle_lib):
+    o, v, n = 2, 5, 3
+    L, tau, tau2, w, w2 = rnd(14, v, v, n), rnd(15, o, o, v, v), rnd(16, o, o, v, v), rnd(17, o, o, v, v), rnd(18, o, o, v, v)
+    R, E = oracle_lib.forward(o, v, n, L, tau, w)
+    X = oracle_lib.adjoint(o, v, n, L, tau, w)
+    Rs, Es = oracle_lib.forward(o, v, n, 2.0 * L, tau, w)
+    Xs = oracle_lib.adjoint(o, v, n, 2.0 * L, tau, w)
+    # E is quadratic in L, so its gradient X is linear in L (degree 1, not 3)
+    assert np.array_equal(Rs, 4.0 * R) and Es == 4.0 * E and np.array_equal(Xs, 2.0 * X)
+    _, Ea = oracle_lib.forward(o, v, n, L, tau + 3.0 * tau2, w)
+    _, Eb = oracle_lib.forward(o, v, n, L, tau2, w)
+    _, Ec = oracle_lib.forward(o, v, n, L, tau, w2)
+    _, Ed = oracle_lib.forward(o, v, n, L, tau, w - 0.5 * w2)
+    scale = np.abs(R).sum() * np.abs(w).max() * 8
+    assert abs(Ea - (E + 3.0 * Eb)) <= 1e-13 * scale
+    assert abs(Ed - (E - 0.5 * Ec)) <= 1e-13 * scale
+
+
+def test_density_route_equals_residual_route(oracle_lib):
+    """E = sum_abcd (ac|bd) O2_{..} with the V^4 density O^(2) of Appendix A.
+
+    With d_abcd = O^(2)_abcd(L_2, C_2) = L_ij^ac C_ij^bd (Sec. II B, Appendix A;
+    R_0 = 1, L_2 = tbar, C_2 = tau) and g_pqrs = (pq|rs) = sum_J L^J_pq L^J_rs,
+    the V^4 part of sum_pqrs g_pqrs d_pqrs must equal sum tbar R.
+    """
+    o, v, n = 3, 5, 4
+    L, tau, w = rnd(19, v, v, n), rnd(20, o, o, v, v), rnd(21, o, o, v, v)
+    _, E = oracle_lib.forward(o, v, n, L, tau, w)
+    g = np.einsum("pqJ,rsJ->pqrs", L, L)        # (pq|rs), Mulliken
+    d = np.einsum("ijpr,ijqs->pqrs", w, tau)     # O2_pqrs = tbar_ij^pr tau_ij^qs
+    E_density = np.einsum("pqrs,pqrs->", g, d)
+    assert abs(E - E_density) <= 1e-13 * np.einsum("pqrs,pqrs->", np.abs(g), np.abs(d))
+
+
+def test_factor_two_form_under_pair_symmetry(oracle_lib):
+    """d_pqrs = d_rspq (Appendix A): with pair-symmetric tbar and tau,
+    X^J_ac = 2 sum_bd L^J_bd D_{ab,cd}, D_{ab,cd} = sum_ij tbar_ij^ab tau_ij^cd."""
+    o, v, n = 3, 5, 4
+    L, tau, w = rnd(22, v, v, n), pair_sym(rnd(23, o, o, v, v)), pair_sym(rnd(24, o, o, v, v))
+    X = oracle_lib.adjoint(o, v, n, L, tau, w)
+    D = np.einsum("ijab,ijcd->abcd", w, tau)
+    X2 = 2.0 * np.einsum("abcd,bdJ->acJ", D, L)
+    np.testing.assert_allclose(X, X2, rtol=0, atol=1e-13 * np.abs(X2).max())
+    # without pair symmetry the factor-2 form is wrong, and the oracle must not use it
+    wa = rnd(25, o, o, v, v)
+    Xa = oracle_lib.adjoint(o, v, n, L, tau, wa)
+    Xa2 = 2.0 * np.einsum("abcd,bdJ->acJ", np.einsum("ijab,ijcd->abcd", wa, tau), L)
+    assert np.abs(Xa - Xa2).max() > 1e-3 * np.abs(Xa).max()
+
+
+# ---------------------------------------------------------------- finite differences
+@pytest.mark.parametrize("symmetric", [True, False])
+def test_finite_differences(oracle_lib, symmetric):
+    """E is exactly quadratic along any single L entry, so the central difference
+    has zero truncation error and must match X to rounding."""
+    o, v, n = 2, 5, 3
+    L, tau, w = rnd(26, v, v, n), rnd(27, o, o, v, v), rnd(28, o, o, v, v)
+    if symmetric:
+        tau, w = pair_sym(tau), pair_sym(w)
+    X = oracle_lib.adjoint(o, v, n, L, tau, w)
+    h = 1e-3
+    for (a, c, J) in [(0, 0, 0), (1, 3, 2), (4, 2, 1), (2, 2, 0), (3, 0, 2)]:
+        Lp, Lm = L.copy(), L.copy()
+        Lp[a, c, J] += h
+        Lm[a, c, J] -= h
+        fd = (oracle_lib.forward(o, v, n, Lp, tau, w)[1] - oracle_lib.forward(o, v, n, Lm, tau, w)[1]) / (2 * h)
+        assert abs(fd - X[a, c, J]) <= 1e-9 * max(1.0, abs(X).max()), (a, c, J, fd, X[a, c, J])
+
+
+# ---------------------------------------------------------------- ranges and samples
+def test_ranges_and_samples_agree_with_full(oracle_lib):
+    o, v, n = 2, 7, 4
+    L, tau, w = rnd(29, v, v, n), rnd(30, o, o, v, v), rnd(31, o, o, v, v)
+    R, E = oracle_lib.forward(o, v, n, L, tau, w)
+    X = oracle_lib.adjoint(o, v, n, L, tau, w)
+    Rr, Ep, Er = oracle_lib.forward_range(o, v, n, L, tau, w, 2, 5)
+    assert np.array_equal(Rr[:, :, 2:5], R[:, :, 2:5]) and not Rr[:, :, :2].any()
+    Xr = oracle_lib.adjoint_range(o, v, n, L, tau, w, 3, 6)
+    assert np.array_equal(Xr[3:6], X[3:6])
+    ab = np.array([[0, 0], [6, 1], [3, 3], [2, 5]])
+    Rs = oracle_lib.R_sample(o, v, n, L, tau, ab)
+    for k, (a, b) in enumerate(ab):
+        np.testing.assert_allclose(Rs[k], R[:, :, a, b].ravel(), rtol=0, atol=1e-14 * np.abs(R).max())
+    Xs = oracle_lib.X_sample(o, v, n, L, tau, w, ab)
+    for k, (p, q) in enumerate(ab):
+        np.testing.assert_allclose(Xs[k], X[p, q], rtol=0, atol=1e-14 * np.abs(X).max())
+
+
+def test_bad_arguments_raise(oracle_lib):
+    with pytest.raises(ValueError):
+        oracle_lib.forward(2, 3, 4, np.zeros(5), np.zeros(36), None)
+    with pytest.raises(RuntimeError):
+        oracle_lib.R_sample(1, 2, 1, np.zeros(4), np.zeros(4), [[0, 2]])
+
+
+# ---------------------------------------------------------------- amplitude recipe
+def test_mp2_amplitudes_and_update(oracle_lib):
+    o, v, n, seed = 2, 3, 4, 9
+    Lov = synthetic.draw_L_ov(seed, o, v, n)
+    eps = synthetic.draw_eps(seed, o, v)
+    t = oracle_lib.mp2_amplitudes(o, v, n, Lov, eps)
+    for i in range(o):
+        for j in range(o):
+            for a in range(v):
+                for b in range(v):
+                    iajb = float(np.dot(Lov[i, a], Lov[j, b]))
+                    den = eps[i] + eps[j] - eps[o + a] - eps[o + b]
+                    scale = float(np.dot(np.abs(Lov[i, a]), np.abs(Lov[j, b]))) / abs(den)
+                    assert abs(t[i, j, a, b] - iajb / den) <= 1e-15 * scale
+    assert np.array_equal(t, t.transpose(1, 0, 3, 2))  # bitwise pair symmetry
+    R = rnd(32, o, o, v, v)
+    t2 = oracle_lib.amplitude_update(o, v, eps, R, t)
+    den = (eps[:o, None, None, None] + eps[None, :o, None, None]) - (eps[None, None, o:, None] + eps[None, None, None, o:])
+    np.testing.assert_allclose((t2 - t) * den, R, rtol=1e-12, atol=0)
