@@ -1,0 +1,201 @@
+/*
+ * ladder.h -- C ABI of libladder.so: the V^4 O^2 particle-particle ladder of
+ * Cholesky-decomposed CCSD and its adjoint, on one AMD Instinct MI355X (gfx950).
+ *
+ * Quantities (Schnack-Petersen, Koch, Coriani, Kjonstad, arXiv 2202.02019):
+ *   L^J_pq   Cholesky vectors, (pq|rs) = sum_J L^J_pq L^J_rs          (Sec. II A)
+ *   g_acbd = sum_J L^J_ac L^J_bd, the (ac|bd) integrals, formed per virtual
+ *            batch on the device and never stored whole                (Sec. II B)
+ *   R_ij^ab = sum_cd g_acbd tau_ij^cd, the A2 ladder term of Omega       (Sec. II B)
+ *   E       = sum_ijab tbar_ij^ab R_ij^ab, the V^4 part of sum g d with the
+ *             ground-state density d_abcd = O^(2)_abcd(L_2 = tbar, C_2 = tau)
+ *                                                                     (Appendix A)
+ *   X^J_ac  = dE/dL^J_ac = 2 sum_bd L^J_bd D_{ab,cd},  D_{ab,cd} = sum_ij tbar_ij^ab tau_ij^cd,
+ *             i.e. 2 W~^J_ac (Sec. II C) restricted to the V^4 density block
+ *             (Sec. II B); the factor 2 is d_pqrs = d_rspq (Appendix A).
+ *
+ * Index ranges: i,j < o (occupied), a,b,c,d < v (virtual), J < n (Cholesky).
+ *
+ * Layouts (row-major FP64, all DEVICE pointers owned by the caller):
+ *   L, X      [v][v][n]     L[(a*v + c)*n + J]            = L^J_ac
+ *   tau, tbar, R, w
+ *             [o][o][v][v]  tau[((i*o + j)*v + c)*v + d]  = tau_ij^cd
+ *   Lov       [o][v][n]     Lov[(i*v + a)*n + J]           = L^J_ia
+ *   eps       [o + v]       occupied orbital energies first, then virtual ones
+ *   E         one double on the device
+ *
+ * Conventions.
+ *   * Every call is asynchronous on `stream` (a hipStream_t; NULL = the null
+ *     stream).  Results are valid once the stream has been synchronised.
+ *   * The library never allocates device memory in these calls: scratch space is
+ *     the caller's `ws` buffer (device memory of `ws_bytes` bytes, 256-byte
+ *     aligned), sized with ladder_workspace_size().  It holds only per-batch
+ *     tiles of g or D (n_abatch * v^3 doubles), never the whole v^4 array.
+ *   * Pair symmetry: the adjoint assumes tau_ij^ab = tau_ji^ba and
+ *     tbar_ij^ab = tbar_ji^ba (true for closed-shell CCSD amplitudes) unless
+ *     LADDER_FLAG_GENERAL is set, which adds the second density term explicitly.
+ *   * L need not be symmetric in (a,c) (T1-transformed vectors are not).
+ *   * Results are deterministic: no floating-point atomics; the same inputs and
+ *     options give bitwise identical R, E and X.
+ *
+ * Errors.  Every entry point validates all arguments on the host before any
+ * launch and returns LADDER_OK (0) or a negative code; on error nothing has been
+ * launched and no output has been touched.  ladder_strerror() names a code,
+ * ladder_last_error() gives the message of the last failure on this thread
+ * (including the HIP error string for LADDER_EHIP).
+ */
+#ifndef LADDER_H
+#define LADDER_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define LADDER_OK 0
+#define LADDER_EINVAL (-1)       /* null pointer, non-positive or too-large size, misalignment, aliasing */
+#define LADDER_EWORKSPACE (-2)   /* ws too small for the requested batch */
+#define LADDER_EUNSUPPORTED (-3) /* option value outside the supported range */
+#define LADDER_EHIP (-4)         /* HIP launch or runtime failure */
+
+/* Arithmetic of the four contraction stages. */
+#define LADDER_FP64 0       /* FP64 MFMA (v_mfma_f64_16x16x4_f64) throughout */
+#define LADDER_SPLIT_BF16 1 /* exponent-aligned BF16 slices on BF16 MFMA, exact FP32 chunk sums, FP64 combine */
+
+/* Option flags. */
+#define LADDER_FLAG_GENERAL 1u /* adjoint: do not assume pair symmetry of tau and tbar */
+
+typedef struct {
+    int32_t precision; /* LADDER_FP64 or LADDER_SPLIT_BF16 */
+    int32_t n_slices;  /* split mode: BF16 slices per operand, 0 = default (see ladder.c docs) */
+    int64_t n_abatch;  /* virtual indices a per batch, 0 = automatic */
+    uint32_t flags;    /* LADDER_FLAG_* */
+    uint32_t reserved; /* must be 0 */
+} ladder_options;
+
+/* Defaults: precision FP64, automatic batch, no flags.  `opts` may be NULL in
+ * every call below, meaning these defaults. */
+void ladder_default_options(ladder_options* opts);
+
+/*
+ * Bytes of device workspace that ladder_forward / ladder_adjoint need for the
+ * shape (o, v, n) and options (the larger of the two).  With n_abatch = 0 the
+ * batch is the largest that keeps the per-batch g/D tile at or below
+ * LADDER_DEFAULT_TILE_BYTES and covers at most half of the virtual range
+ * (ceil(v/2)), so the full v^4 array is never held.
+ */
+#define LADDER_DEFAULT_TILE_BYTES ((size_t)16 << 30)
+int ladder_workspace_size(int64_t o, int64_t v, int64_t n, const ladder_options* opts, size_t* bytes);
+
+/*
+ * Forward ladder (A2 term, Sec. II B) and its energy.
+ *   R = beta * R + ladder(L, tau)        R_ij^ab (+)= sum_cd (sum_J L^J_ac L^J_bd) tau_ij^cd
+ *   *E = sum_ijab tbar_ij^ab * ladder(L, tau)_ij^ab   (if E != NULL; needs tbar)
+ * With beta == 0, R is not read (it may hold NaN).  tbar may be NULL only when E
+ * is NULL.  R must not overlap L, tau, tbar or ws.
+ */
+int ladder_forward(int64_t o, int64_t v, int64_t n, const double* L, const double* tau,
+                   const double* tbar, double beta, double* R, double* E, void* ws,
+                   size_t ws_bytes, const ladder_options* opts, void* stream);
+
+/*
+ * Adjoint: the L-built three-index intermediate of the V^4 block.
+ *   X = beta * X + alpha * d/dL [ sum_ijab w_ij^ab ladder(L, tau)_ij^ab ]
+ *     = beta * X + alpha * 2 sum_bd L^J_bd sum_ij w_ij^ab tau_ij^cd      (pair-symmetric)
+ * With w = tbar this is dE/dL (Sec. II B V^4 density O^(2), Sec. II C W~).  With
+ * LADDER_FLAG_GENERAL the second term sum_ij w_ij^ba tau_ij^dc is formed
+ * explicitly instead of being folded into the factor 2 (costs one more density
+ * GEMM and 2*o^2*v^2 doubles of extra workspace).  With beta == 0, X is not read.
+ * X must not overlap L, tau, w or ws.
+ */
+int ladder_adjoint(int64_t o, int64_t v, int64_t n, const double* L, const double* tau,
+                   const double* w, double alpha, double beta, double* X, void* ws,
+                   size_t ws_bytes, const ladder_options* opts, void* stream);
+
+/*
+ * First-order doubles amplitudes from the occupied-virtual Cholesky block (the
+ * synthetic stand-in for converged T2; Cholesky expansion of Sec. II A):
+ *   t_ij^ab = (sum_J L^J_ia L^J_jb) / ((eps_i + eps_j) - (eps_a + eps_b)).
+ * FP64 throughout.  t must not overlap Lov or eps.
+ */
+int ladder_mp2_amplitudes(int64_t o, int64_t v, int64_t n, const double* Lov, const double* eps,
+                          double* t, void* stream);
+
+/*
+ * Orbital-energy-denominator (Jacobi) amplitude update, FP64:
+ *   t_ij^ab += R_ij^ab / ((eps_i + eps_j) - (eps_a + eps_b)).
+ * R may equal t only if the caller wants t <- t + t/den.
+ */
+int ladder_amplitude_update(int64_t o, int64_t v, const double* eps, const double* R, double* t,
+                            void* stream);
+
+/* One instance of a ragged batch (all device pointers; tbar/E and X optional). */
+typedef struct {
+    int64_t o, v, n;
+    const double* L;
+    const double* tau;
+    const double* tbar;
+    double* R; /* forward output (overwritten), may be NULL if not LADDER_DO_FORWARD */
+    double* E; /* energy (device scalar), may be NULL */
+    double* X; /* adjoint output (overwritten), may be NULL if not LADDER_DO_ADJOINT */
+} ladder_instance;
+
+#define LADDER_DO_FORWARD 1u
+#define LADDER_DO_ADJOINT 2u
+
+/* Workspace for ladder_batched over `count` instances. */
+int ladder_batched_workspace_size(int count, const ladder_instance* inst, uint32_t what,
+                                  const ladder_options* opts, size_t* bytes);
+
+/*
+ * Many independent instances of uneven (o, v, n): forward (R = ladder, E) and/or
+ * adjoint (X = dE/dL with w = tbar, pair-symmetric) for each, in one launch
+ * sequence captured once into a hipGraph and replayed on later calls with the
+ * same shapes, pointers and options.  `inst` is a host array.
+ */
+int ladder_batched(int count, const ladder_instance* inst, uint32_t what, void* ws, size_t ws_bytes,
+                   const ladder_options* opts, void* stream);
+
+/*
+ * Per-stage timing with HIP events (for measurement, off by default).
+ * ladder_profile_start() clears the record and makes every later kernel launch
+ * of this library bracketed by two hipEvents recorded on the launch stream.
+ * ladder_profile_stop() synchronises those events, fills up to `max_stages`
+ * entries of `out` (one per stage that ran; *n_out receives the count) and
+ * turns recording off.  Stage ids are LADDER_STAGE_*; `flops` and `bytes` are
+ * the algorithmic work of all launches of the stage (2*M*N*K for a GEMM; for
+ * bytes, each operand element read once and each result written once).
+ */
+#define LADDER_STAGE_GEMM_B 0   /* g tile, K = n */
+#define LADDER_STAGE_GEMM_C 1   /* R update, K = v^2 */
+#define LADDER_STAGE_ENERGY 2   /* energy partial reduction */
+#define LADDER_STAGE_GEMM_E 3   /* D tile, K = o^2 */
+#define LADDER_STAGE_GEMM_F 4   /* X update, K = v^2 */
+#define LADDER_STAGE_SWAP 5     /* pair swap (general adjoint) */
+#define LADDER_STAGE_MP2 6      /* first-order amplitudes */
+#define LADDER_STAGE_UPDATE 7   /* amplitude update */
+#define LADDER_STAGE_SLICE 8    /* split mode: FP64 -> BF16 slices */
+#define LADDER_NUM_STAGES 9
+typedef struct {
+    int32_t stage;
+    int32_t launches;
+    double total_ms;
+    double flops;
+    double bytes;
+} ladder_stage_stats;
+int ladder_profile_start(void);
+int ladder_profile_stop(ladder_stage_stats* out, int max_stages, int* n_out);
+
+/* Name of an error code; never NULL. */
+const char* ladder_strerror(int code);
+/* Message of the last failing call on this thread ("" if none). */
+const char* ladder_last_error(void);
+/* Frees host-side caches (instantiated graphs).  Safe to call more than once. */
+void ladder_shutdown(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* LADDER_H */

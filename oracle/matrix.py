@@ -1,0 +1,55 @@
+"""Second oracle implementation: the same definitions with numpy matrix products.
+
+Same quantities and citations as ladder_oracle.c (Sec. II A Cholesky expansion,
+Sec. II B A2 ladder and V^4 density O^(2), Sec. II C W~, Appendix A pair symmetry
+of d), written per virtual index a with library matrix products as steps, so that
+the medium workload (o=20, v=150, n=600) finishes in seconds.  Test
+infrastructure only; pinned by the same tests as the C version.
+"""
+from __future__ import annotations
+
+import math
+
+import numpy as np
+
+
+def forward(o, v, n, L, tau, tbar=None, a_range=None):
+    """R [o][o][v][v] and E = sum tbar*R (exactly rounded sum of the products).
+
+    With a_range = (a_lo, a_hi) only the rows a in that range are formed; R is then
+    [o][o][a_hi-a_lo][v] and E covers those rows only.
+    """
+    L = np.ascontiguousarray(L, dtype=np.float64).reshape(v, v, n)
+    T = np.ascontiguousarray(tau, dtype=np.float64).reshape(o * o, v * v)  # [ij, (c,d)]
+    Lbd = L.reshape(v * v, n)                                              # [(b,d), J]
+    a_lo, a_hi = (0, v) if a_range is None else a_range
+    R = np.empty((o * o, a_hi - a_lo, v))
+    for a in range(a_lo, a_hi):
+        g = L[a] @ Lbd.T                                   # g[c, (b,d)] = sum_J L^J_ac L^J_bd
+        g = g.reshape(v, v, v).transpose(1, 0, 2).reshape(v, v * v)  # g[b, (c,d)]
+        R[:, a - a_lo, :] = T @ g.T                        # R_ij^ab = sum_cd (ac|bd) tau_ij^cd
+    R = R.reshape(o, o, a_hi - a_lo, v)
+    E = 0.0
+    if tbar is not None:
+        tb = np.asarray(tbar, dtype=np.float64).reshape(o, o, v, v)[:, :, a_lo:a_hi, :]
+        E = math.fsum((tb * R).ravel())
+    return R, E
+
+
+def adjoint(o, v, n, L, tau, w, p_range=None):
+    """X^J_pq = sum_bd L^J_bd sum_ij (w_ij^pb tau_ij^qd + w_ij^bp tau_ij^dq), general form.
+
+    With p_range = (p_lo, p_hi) only those rows are formed ([p_hi-p_lo][v][n]).
+    """
+    L = np.ascontiguousarray(L, dtype=np.float64).reshape(v, v, n)
+    T = np.ascontiguousarray(tau, dtype=np.float64).reshape(o * o, v * v)  # [ij, (q,d)] or [ij, (d,q)]
+    W = np.ascontiguousarray(w, dtype=np.float64).reshape(o * o, v, v)
+    Lbd = L.reshape(v * v, n)
+    p_lo, p_hi = (0, v) if p_range is None else p_range
+    X = np.empty((p_hi - p_lo, v, n))
+    for p in range(p_lo, p_hi):
+        D1 = np.ascontiguousarray(W[:, p, :]).T @ T   # D1[b, (q,d)] = sum_ij w_ij^pb tau_ij^qd
+        D2 = np.ascontiguousarray(W[:, :, p]).T @ T   # D2[b, (d,q)] = sum_ij w_ij^bp tau_ij^dq
+        C = D1.reshape(v, v, v).transpose(1, 0, 2) + D2.reshape(v, v, v).transpose(2, 0, 1)  # C[q, b, d]
+        X[p - p_lo] = C.reshape(v, v * v) @ Lbd
+    return X

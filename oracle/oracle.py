@@ -14,6 +14,8 @@ import numpy as np
 
 import synthetic
 
+from . import matrix
+
 HERE = os.path.dirname(os.path.abspath(__file__))
 SRC = os.path.join(HERE, "ladder_oracle.c")
 LIB = os.path.join(HERE, "liboracle.so")
@@ -21,7 +23,7 @@ LIB = os.path.join(HERE, "liboracle.so")
 __all__ = [
     "build", "load", "forward", "adjoint", "forward_range", "adjoint_range", "R_sample",
     "X_sample", "mp2_amplitudes", "amplitude_update", "make_inputs", "num_threads",
-    "set_num_threads", "flops_forward", "flops_adjoint",
+    "set_num_threads", "flops_forward", "flops_adjoint", "matrix",
 ]
 
 _lib = None

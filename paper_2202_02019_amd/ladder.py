@@ -1,0 +1,302 @@
+"""ctypes binding of libladder.so with the names of the C ABI (include/ladder.h).
+
+Argument marshalling only: every step of the ladder runs in the library's HIP
+kernels.  Tensors must be float64, contiguous and on the current HIP device.
+Workspace and outputs are allocated with torch when the caller does not pass them
+(device memory is the only thing torch provides here).
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from dataclasses import dataclass
+
+import torch
+
+PKG = os.path.dirname(os.path.abspath(__file__))
+_LIB_PATH = os.path.join(PKG, "libladder.so")
+
+FP64 = 0
+SPLIT_BF16 = 1
+FLAG_GENERAL = 1
+DO_FORWARD = 1
+DO_ADJOINT = 2
+
+EXPORTS = (
+    "ladder_default_options", "ladder_workspace_size", "ladder_forward", "ladder_adjoint",
+    "ladder_mp2_amplitudes", "ladder_amplitude_update", "ladder_batched_workspace_size",
+    "ladder_batched", "ladder_strerror", "ladder_last_error", "ladder_shutdown",
+    "ladder_profile_start", "ladder_profile_stop",
+)
+
+STAGE_NAMES = ("gemm_b", "gemm_c", "energy", "gemm_e", "gemm_f", "swap", "mp2", "update", "slice")
+
+
+class LadderError(RuntimeError):
+    def __init__(self, code: int, message: str):
+        super().__init__("%s (%d): %s" % (_strerror(code), code, message))
+        self.code = code
+
+
+class _COptions(ctypes.Structure):
+    _fields_ = [("precision", ctypes.c_int32), ("n_slices", ctypes.c_int32), ("n_abatch", ctypes.c_int64),
+                ("flags", ctypes.c_uint32), ("reserved", ctypes.c_uint32)]
+
+
+class _CStageStats(ctypes.Structure):
+    _fields_ = [("stage", ctypes.c_int32), ("launches", ctypes.c_int32), ("total_ms", ctypes.c_double),
+                ("flops", ctypes.c_double), ("bytes", ctypes.c_double)]
+
+
+class _CInstance(ctypes.Structure):
+    _fields_ = [("o", ctypes.c_int64), ("v", ctypes.c_int64), ("n", ctypes.c_int64),
+                ("L", ctypes.c_void_p), ("tau", ctypes.c_void_p), ("tbar", ctypes.c_void_p),
+                ("R", ctypes.c_void_p), ("E", ctypes.c_void_p), ("X", ctypes.c_void_p)]
+
+
+@dataclass
+class Options:
+    precision: int = FP64
+    n_slices: int = 0
+    n_abatch: int = 0
+    flags: int = 0
+
+    def c(self) -> _COptions:
+        return _COptions(self.precision, self.n_slices, self.n_abatch, self.flags, 0)
+
+
+_lib = None
+
+
+def library_path() -> str:
+    return _LIB_PATH
+
+
+def _load():
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(_LIB_PATH):
+        raise RuntimeError("libladder.so is not built (%s); run __graft_entry__.build() or "
+                           "python -m paper_2202_02019_amd.build" % _LIB_PATH)
+    lib = ctypes.CDLL(_LIB_PATH)
+    i64, vp, dbl, sz = ctypes.c_int64, ctypes.c_void_p, ctypes.c_double, ctypes.c_size_t
+    op = ctypes.POINTER(_COptions)
+    lib.ladder_default_options.argtypes = [op]
+    lib.ladder_default_options.restype = None
+    lib.ladder_workspace_size.argtypes = [i64, i64, i64, op, ctypes.POINTER(sz)]
+    lib.ladder_forward.argtypes = [i64, i64, i64, vp, vp, vp, dbl, vp, vp, vp, sz, op, vp]
+    lib.ladder_adjoint.argtypes = [i64, i64, i64, vp, vp, vp, dbl, dbl, vp, vp, sz, op, vp]
+    lib.ladder_mp2_amplitudes.argtypes = [i64, i64, i64, vp, vp, vp, vp]
+    lib.ladder_amplitude_update.argtypes = [i64, i64, vp, vp, vp, vp]
+    lib.ladder_batched_workspace_size.argtypes = [ctypes.c_int, ctypes.POINTER(_CInstance), ctypes.c_uint32, op,
+                                                  ctypes.POINTER(sz)]
+    lib.ladder_batched.argtypes = [ctypes.c_int, ctypes.POINTER(_CInstance), ctypes.c_uint32, vp, sz, op, vp]
+    for f in ("ladder_workspace_size", "ladder_forward", "ladder_adjoint", "ladder_mp2_amplitudes",
+              "ladder_amplitude_update", "ladder_batched_workspace_size", "ladder_batched"):
+        getattr(lib, f).restype = ctypes.c_int
+    lib.ladder_strerror.argtypes = [ctypes.c_int]
+    lib.ladder_strerror.restype = ctypes.c_char_p
+    lib.ladder_last_error.argtypes = []
+    lib.ladder_last_error.restype = ctypes.c_char_p
+    lib.ladder_shutdown.argtypes = []
+    lib.ladder_shutdown.restype = None
+    lib.ladder_profile_start.argtypes = []
+    lib.ladder_profile_start.restype = ctypes.c_int
+    lib.ladder_profile_stop.argtypes = [ctypes.POINTER(_CStageStats), ctypes.c_int, ctypes.POINTER(ctypes.c_int)]
+    lib.ladder_profile_stop.restype = ctypes.c_int
+    _lib = lib
+    return lib
+
+
+def exported_symbols():
+    """Loads the library and returns the C entry points (no GPU call is made)."""
+    lib = _load()
+    return {name: getattr(lib, name) for name in EXPORTS}
+
+
+def _strerror(code: int) -> str:
+    try:
+        return _load().ladder_strerror(code).decode()
+    except Exception:  # pragma: no cover
+        return "error"
+
+
+def _check(rc: int):
+    if rc != 0:
+        raise LadderError(rc, _load().ladder_last_error().decode())
+
+
+def _opts(opts) -> _COptions:
+    if opts is None:
+        return Options().c()
+    if isinstance(opts, _COptions):
+        return opts
+    return opts.c()
+
+
+def _ptr(t):
+    return None if t is None else ctypes.c_void_p(t.data_ptr())
+
+
+def _stream(stream):
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return ctypes.c_void_p(stream.cuda_stream)
+
+
+def _need(t, name, shape=None):
+    if t is None:
+        raise ValueError("%s is required" % name)
+    if not t.is_cuda or t.dtype != torch.float64 or not t.is_contiguous():
+        raise ValueError("%s must be a contiguous float64 tensor on the GPU" % name)
+    if shape is not None and t.numel() != int(torch.Size(shape).numel()):
+        raise ValueError("%s has %d elements, %s expected" % (name, t.numel(), tuple(shape)))
+    return t
+
+
+def workspace_size(o: int, v: int, n: int, opts=None) -> int:
+    b = ctypes.c_size_t(0)
+    _check(_load().ladder_workspace_size(o, v, n, ctypes.byref(_opts(opts)), ctypes.byref(b)))
+    return b.value
+
+
+def _workspace(nbytes, device, ws):
+    if ws is not None:
+        if ws.numel() * ws.element_size() < nbytes:
+            raise ValueError("workspace too small: %d < %d bytes" % (ws.numel() * ws.element_size(), nbytes))
+        return ws
+    return torch.empty(max(nbytes, 256), dtype=torch.uint8, device=device)
+
+
+def forward(L, tau, tbar=None, *, o, v, n, R=None, E=None, beta=0.0, want_energy=True, ws=None, opts=None,
+            stream=None):
+    """R = beta*R + ladder(L, tau); E = sum tbar*ladder (if tbar given).  Returns (R, E or None)."""
+    _need(L, "L", (v, v, n)); _need(tau, "tau", (o, o, v, v))
+    if tbar is not None:
+        _need(tbar, "tbar", (o, o, v, v))
+    dev = L.device
+    if R is None:
+        R = torch.empty((o, o, v, v), dtype=torch.float64, device=dev)
+    _need(R, "R", (o, o, v, v))
+    if want_energy and tbar is not None and E is None:
+        E = torch.empty((), dtype=torch.float64, device=dev)
+    if not want_energy or tbar is None:
+        E = None
+    c = _opts(opts)
+    w = _workspace(workspace_size(o, v, n, c), dev, ws)
+    _check(_load().ladder_forward(o, v, n, _ptr(L), _ptr(tau), _ptr(tbar), float(beta), _ptr(R), _ptr(E), _ptr(w),
+                                  w.numel() * w.element_size(), ctypes.byref(c), _stream(stream)))
+    return R, E
+
+
+def adjoint(L, tau, w, *, o, v, n, X=None, alpha=1.0, beta=0.0, ws=None, opts=None, stream=None):
+    """X = beta*X + alpha * d/dL sum(w * ladder(L, tau))."""
+    _need(L, "L", (v, v, n)); _need(tau, "tau", (o, o, v, v)); _need(w, "w", (o, o, v, v))
+    if X is None:
+        X = torch.empty((v, v, n), dtype=torch.float64, device=L.device)
+    _need(X, "X", (v, v, n))
+    c = _opts(opts)
+    wsb = _workspace(workspace_size(o, v, n, c), L.device, ws)
+    _check(_load().ladder_adjoint(o, v, n, _ptr(L), _ptr(tau), _ptr(w), float(alpha), float(beta), _ptr(X), _ptr(wsb),
+                                  wsb.numel() * wsb.element_size(), ctypes.byref(c), _stream(stream)))
+    return X
+
+
+def mp2_amplitudes(Lov, eps, *, o, v, n, t=None, stream=None):
+    _need(Lov, "Lov", (o, v, n)); _need(eps, "eps", (o + v,))
+    if t is None:
+        t = torch.empty((o, o, v, v), dtype=torch.float64, device=Lov.device)
+    _need(t, "t", (o, o, v, v))
+    _check(_load().ladder_mp2_amplitudes(o, v, n, _ptr(Lov), _ptr(eps), _ptr(t), _stream(stream)))
+    return t
+
+
+def amplitude_update(eps, R, t, *, o, v, stream=None):
+    """In place: t += R / ((eps_i+eps_j) - (eps_a+eps_b))."""
+    _need(eps, "eps", (o + v,)); _need(R, "R", (o, o, v, v)); _need(t, "t", (o, o, v, v))
+    _check(_load().ladder_amplitude_update(o, v, _ptr(eps), _ptr(R), _ptr(t), _stream(stream)))
+    return t
+
+
+def _instances(insts):
+    arr = (_CInstance * len(insts))()
+    for k, d in enumerate(insts):
+        arr[k] = _CInstance(d["o"], d["v"], d["n"], d["L"].data_ptr(), d["tau"].data_ptr(),
+                            d["tbar"].data_ptr() if d.get("tbar") is not None else None,
+                            d["R"].data_ptr() if d.get("R") is not None else None,
+                            d["E"].data_ptr() if d.get("E") is not None else None,
+                            d["X"].data_ptr() if d.get("X") is not None else None)
+    return arr
+
+
+def batched_workspace_size(insts, what=DO_FORWARD | DO_ADJOINT, opts=None) -> int:
+    arr = _instances(insts)
+    b = ctypes.c_size_t(0)
+    _check(_load().ladder_batched_workspace_size(len(insts), arr, what, ctypes.byref(_opts(opts)), ctypes.byref(b)))
+    return b.value
+
+
+def batched(insts, what=DO_FORWARD | DO_ADJOINT, *, ws=None, opts=None, stream=None):
+    """insts: list of dicts with o, v, n, L, tau, tbar, R, E, X (device tensors)."""
+    arr = _instances(insts)
+    c = _opts(opts)
+    b = ctypes.c_size_t(0)
+    _check(_load().ladder_batched_workspace_size(len(insts), arr, what, ctypes.byref(c), ctypes.byref(b)))
+    dev = insts[0]["L"].device
+    w = _workspace(b.value, dev, ws)
+    _check(_load().ladder_batched(len(insts), arr, what, _ptr(w), w.numel() * w.element_size(), ctypes.byref(c),
+                                  _stream(stream)))
+
+
+def profile_start():
+    """Start bracketing every library launch with HIP events on its stream."""
+    _check(_load().ladder_profile_start())
+
+
+def profile_stop():
+    """Stop recording; returns {stage name: dict(launches, total_ms, avg_ms, flops, bytes)}."""
+    arr = (_CStageStats * 16)()
+    k = ctypes.c_int(0)
+    _check(_load().ladder_profile_stop(arr, 16, ctypes.byref(k)))
+    out = {}
+    for i in range(k.value):
+        s = arr[i]
+        out[STAGE_NAMES[s.stage]] = dict(launches=s.launches, total_ms=s.total_ms,
+                                         avg_ms=s.total_ms / max(1, s.launches), flops=s.flops, bytes=s.bytes)
+    return out
+
+
+class LadderEnergy(torch.autograd.Function):
+    """E(L, tau, tbar) = sum tbar * ladder(L, tau) with the library adjoint as backward.
+
+    backward gives dE/dL = X (hand-written adjoint, g recomputed per batch, nothing
+    of the forward kept but the inputs) and dE/dtbar = R.  dE/dtau (the transposed
+    ladder) is not provided: asking for it raises.
+    """
+
+    @staticmethod
+    def forward(ctx, L, tau, tbar, dims, opts=None):
+        o, v, n = dims
+        R, E = forward(L, tau, tbar, o=o, v=v, n=n, opts=opts)
+        ctx.dims, ctx.opts = dims, opts
+        ctx.save_for_backward(L, tau, tbar, R if tbar.requires_grad else None)
+        return E
+
+    @staticmethod
+    def backward(ctx, gE):
+        L, tau, tbar, R = ctx.saved_tensors
+        o, v, n = ctx.dims
+        if ctx.needs_input_grad[1]:
+            raise NotImplementedError("dE/dtau (the transposed ladder) is not implemented")
+        gL = gt = None
+        if ctx.needs_input_grad[0]:
+            X = adjoint(L, tau, tbar, o=o, v=v, n=n, opts=ctx.opts)
+            gL = X * gE
+        if ctx.needs_input_grad[2]:
+            gt = R * gE
+        return gL, None, gt, None, None
+
+
+def ladder_energy(L, tau, tbar, dims, opts=None):
+    return LadderEnergy.apply(L, tau, tbar, tuple(dims), opts)

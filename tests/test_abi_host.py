@@ -1,0 +1,114 @@
+"""The C ABI on the host: every declared symbol is exported, and argument
+validation rejects bad calls before any HIP call (so these run without a GPU)."""
+import ctypes
+import os
+import re
+
+import pytest
+
+import paper_2202_02019_amd as P
+from paper_2202_02019_amd import ladder as B
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "ladder.h")
+
+EINVAL, EWORKSPACE, EUNSUPPORTED = -1, -2, -3
+FAKE = 1 << 20  # a 256-aligned non-NULL address that is never dereferenced on these paths
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(ladder_[a-z_0-9]+)\s*\(", text)))
+
+
+def test_header_symbols_exported():
+    names = declared_functions()
+    assert len(names) >= 10
+    lib = ctypes.CDLL(P.library_path())
+    for name in names:
+        assert hasattr(lib, name), name
+    assert set(names) == set(B.EXPORTS)
+
+
+def _lib():
+    return B._load()
+
+
+def _opts(**kw):
+    o = B.Options(**kw).c()
+    return ctypes.byref(o)
+
+
+def fwd(o=2, v=3, n=4, L=FAKE, tau=2 * FAKE, tbar=3 * FAKE, beta=0.0, R=4 * FAKE, E=None, ws=8 * FAKE, wsb=1 << 40,
+        opts=None):
+    return _lib().ladder_forward(o, v, n, L, tau, tbar, beta, R, E, ws, wsb, opts or _opts(), None)
+
+
+def test_forward_validation():
+    assert fwd(o=0) == EINVAL
+    assert fwd(v=-1) == EINVAL
+    assert fwd(n=0) == EINVAL
+    assert fwd(o=1 << 21) == EINVAL
+    assert fwd(L=None) == EINVAL
+    assert fwd(tau=None) == EINVAL
+    assert fwd(R=None) == EINVAL
+    assert fwd(ws=None) == EINVAL
+    assert fwd(tbar=None, E=5 * FAKE) == EINVAL                 # energy needs tbar
+    assert fwd(L=FAKE + 4) == EINVAL                             # misaligned
+    assert fwd(ws=8 * FAKE + 8) == EINVAL                        # ws needs 256-byte alignment
+    assert fwd(wsb=16) == EWORKSPACE
+    assert "workspace" in _lib().ladder_last_error().decode()
+    assert fwd(R=2 * FAKE) == EINVAL                             # R aliases tau
+    assert fwd(R=8 * FAKE) == EINVAL                             # R inside the workspace
+    assert fwd(opts=_opts(precision=7)) == EUNSUPPORTED
+    assert fwd(opts=_opts(flags=1 << 9)) == EUNSUPPORTED
+    assert fwd(opts=_opts(n_abatch=-2)) == EINVAL
+    assert "n_abatch" in _lib().ladder_last_error().decode()
+
+
+def test_adjoint_validation():
+    lib = _lib()
+    ok = dict(o=2, v=3, n=4)
+
+    def adj(L=FAKE, tau=2 * FAKE, w=3 * FAKE, X=4 * FAKE, ws=8 * FAKE, wsb=1 << 40, opts=None, **kw):
+        d = dict(ok, **kw)
+        return lib.ladder_adjoint(d["o"], d["v"], d["n"], L, tau, w, 1.0, 0.0, X, ws, wsb, opts or _opts(), None)
+
+    assert adj(o=-3) == EINVAL
+    assert adj(w=None) == EINVAL
+    assert adj(X=FAKE) == EINVAL                                 # X aliases L
+    assert adj(X=4 * FAKE + 2) == EINVAL
+    assert adj(wsb=0) == EWORKSPACE
+    assert adj(opts=_opts(precision=-1)) == EUNSUPPORTED
+
+
+def test_amplitude_entry_validation():
+    lib = _lib()
+    assert lib.ladder_mp2_amplitudes(0, 2, 2, FAKE, 2 * FAKE, 3 * FAKE, None) == EINVAL
+    assert lib.ladder_mp2_amplitudes(2, 2, 2, FAKE, 2 * FAKE, None, None) == EINVAL
+    assert lib.ladder_mp2_amplitudes(2, 2, 2, FAKE, 2 * FAKE, FAKE, None) == EINVAL  # t overlaps Lov
+    assert lib.ladder_amplitude_update(2, 2, None, FAKE, 2 * FAKE, None) == EINVAL
+    assert lib.ladder_amplitude_update(2, 2, 3 * FAKE, FAKE + 8, FAKE, None) == EINVAL  # partial overlap
+
+
+def test_strerror_and_options():
+    lib = _lib()
+    for code in (0, -1, -2, -3, -4, -99):
+        assert lib.ladder_strerror(code)
+    o = B._COptions()
+    o.precision = 9
+    lib.ladder_default_options(ctypes.byref(o))
+    assert o.precision == 0 and o.n_abatch == 0 and o.flags == 0
+    with pytest.raises(P.LadderError):
+        P.workspace_size(0, 1, 1)
+
+
+@pytest.mark.parametrize("o,v,n", [(78, 657, 2200), (40, 350, 1200), (20, 150, 600), (4, 20, 60)])
+def test_workspace_never_holds_full_v4(o, v, n):
+    """The V^4 arrays g and D are only ever held as batch tiles (Sec. II B, Appendix A storage policy)."""
+    ws = P.workspace_size(o, v, n)
+    if v > 20:
+        assert ws < 8 * v ** 4
+    ws1 = P.workspace_size(o, v, n, P.Options(n_abatch=1))
+    assert ws1 < 8 * v ** 3 + (1 << 24) + 8 * o * o * v * v

@@ -1,0 +1,208 @@
+"""Parity of the HIP ladder (libladder.so, through its C ABI) with the CPU oracle.
+
+Tolerances for the FP64 path: both sides sum the same products in different
+orders, so each output differs by rounding only, bounded by about K*u*sum|terms|
+with K = n for g and K = v^2 for R (u = 2^-53).  For these inputs that is below
+1e-13 of max|R| (max|X|); the tests use 1e-11, which still sits three orders of
+magnitude under the 1e-8 accuracy target.  Integer inputs whose sums stay below
+2^53 are exact on both sides, so those compare bitwise.
+"""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import paper_2202_02019_amd as P
+from helpers import err_norm, err_rel, gaussian_inputs, integer_inputs
+
+pytestmark = pytest.mark.gpu
+
+TOL = 1e-11
+
+
+@pytest.fixture(scope="module")
+def dev():
+    assert torch.cuda.is_available(), "GPU tests need a ROCm GPU"
+    oracle.build(force=False)
+    return torch.device("cuda:0")
+
+
+def g(x, dev):
+    return torch.from_numpy(np.ascontiguousarray(x)).to(dev)
+
+
+def run(dev, o, v, n, L, tau, w, opts=None):
+    Lg, tg, wg = g(L, dev), g(tau, dev), g(w, dev)
+    R, E = P.forward(Lg, tg, wg, o=o, v=v, n=n, opts=opts)
+    X = P.adjoint(Lg, tg, wg, o=o, v=v, n=n, opts=opts)
+    torch.cuda.synchronize()
+    return R.cpu().numpy(), float(E.cpu()), X.cpu().numpy()
+
+
+@pytest.mark.parametrize("o,v,n,seed", [(2, 5, 3, 1), (3, 4, 2, 2), (1, 3, 1, 3)])
+def test_integer_inputs_bitwise(dev, o, v, n, seed):
+    L, tau, w = integer_inputs(seed, o, v, n)
+    R, E, X = run(dev, o, v, n, L, tau, w)
+    Rr, Er = oracle.forward(o, v, n, L, tau, w)
+    Xr = oracle.adjoint(o, v, n, L, tau, w)
+    assert np.array_equal(R, Rr)
+    assert E == Er
+    assert np.array_equal(X, Xr)
+
+
+def test_micro_example(dev):
+    import json, os
+    gd = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "micro_example.json")))
+    L, tau, w = np.array(gd["L"]), np.array(gd["tau"]), np.array(gd["tbar"])
+    R, E, X = run(dev, 1, 2, 1, L, tau, w, P.Options(flags=P.FLAG_GENERAL))
+    assert np.array_equal(R.ravel(), np.array(gd["R"]).ravel()) and E == gd["E"]
+    assert np.array_equal(X.ravel(), np.array(gd["X"]).ravel())
+
+
+def test_tiny_workload(dev):
+    o, v, n = 4, 20, 60
+    L, tau, tbar, _, _ = oracle.make_inputs(o, v, n, 1)
+    R, E, X = run(dev, o, v, n, L, tau, tbar)
+    Rr, Er = oracle.forward(o, v, n, L, tau, tbar)
+    Xr = oracle.adjoint(o, v, n, L, tau, tbar)
+    print("tiny: err_R %.3e err_E %.3e err_X %.3e" % (err_norm(R, Rr), err_rel(E, Er), err_norm(X, Xr)))
+    assert err_norm(R, Rr) <= TOL and err_rel(E, Er) <= TOL and err_norm(X, Xr) <= TOL
+
+
+@pytest.mark.parametrize("o,v,n,nA", [(5, 37, 70, 4), (3, 41, 130, 0), (7, 19, 257, 19), (2, 129, 17, 64)])
+def test_ragged_tiles_and_batches(dev, o, v, n, nA):
+    """Shapes whose M, N, K are not tile multiples, several batches with a ragged last one."""
+    L, tau, w = gaussian_inputs(100 + v, o, v, n)
+    R, E, X = run(dev, o, v, n, L, tau, w, P.Options(n_abatch=nA))
+    Rr, Er = oracle.forward(o, v, n, L, tau, w)
+    Xr = oracle.adjoint(o, v, n, L, tau, w)
+    assert err_norm(R, Rr) <= TOL and err_rel(E, Er) <= TOL and err_norm(X, Xr) <= TOL
+
+
+def test_general_flag_on_asymmetric_input(dev):
+    o, v, n = 3, 23, 40
+    L, tau, w = gaussian_inputs(7, o, v, n, symmetric=False)
+    R, E, X = run(dev, o, v, n, L, tau, w, P.Options(flags=P.FLAG_GENERAL, n_abatch=5))
+    Rr, Er = oracle.forward(o, v, n, L, tau, w)
+    Xr = oracle.adjoint(o, v, n, L, tau, w)
+    assert err_norm(R, Rr) <= TOL and err_rel(E, Er) <= TOL and err_norm(X, Xr) <= TOL
+    # the default (pair-symmetric) adjoint must differ here: the flag matters
+    _, _, Xs = run(dev, o, v, n, L, tau, w, P.Options(n_abatch=5))
+    assert err_norm(Xs, Xr) > 1e-3
+
+
+def test_alpha_beta_accumulation(dev):
+    o, v, n = 3, 17, 33
+    L, tau, w = gaussian_inputs(8, o, v, n)
+    R0 = np.random.default_rng(1).standard_normal((o, o, v, v))
+    X0 = np.random.default_rng(2).standard_normal((v, v, n))
+    Lg, tg, wg = g(L, dev), g(tau, dev), g(w, dev)
+    R = g(R0, dev)
+    X = g(X0, dev)
+    P.forward(Lg, tg, wg, o=o, v=v, n=n, R=R, beta=0.5)
+    P.adjoint(Lg, tg, wg, o=o, v=v, n=n, X=X, alpha=-2.0, beta=1.5)
+    Rr, _ = oracle.forward(o, v, n, L, tau, w)
+    Xr = oracle.adjoint(o, v, n, L, tau, w)
+    assert err_norm(R.cpu().numpy(), 0.5 * R0 + Rr) <= TOL
+    assert err_norm(X.cpu().numpy(), 1.5 * X0 - 2.0 * Xr) <= TOL
+
+
+def test_beta_zero_ignores_nan_in_output(dev):
+    o, v, n = 2, 9, 11
+    L, tau, w = gaussian_inputs(9, o, v, n)
+    Lg, tg, wg = g(L, dev), g(tau, dev), g(w, dev)
+    R = torch.full((o, o, v, v), float("nan"), dtype=torch.float64, device=dev)
+    X = torch.full((v, v, n), float("nan"), dtype=torch.float64, device=dev)
+    P.forward(Lg, tg, wg, o=o, v=v, n=n, R=R, beta=0.0)
+    P.adjoint(Lg, tg, wg, o=o, v=v, n=n, X=X, beta=0.0)
+    assert torch.isfinite(R).all() and torch.isfinite(X).all()
+
+
+def test_nan_input_propagates_to_energy(dev):
+    o, v, n = 2, 9, 11
+    L, tau, w = gaussian_inputs(10, o, v, n)
+    tau[1, 0, 3, 4] = np.nan
+    _, E, _ = run(dev, o, v, n, L, tau, w)
+    assert np.isnan(E)
+
+
+def test_deterministic_bitwise(dev):
+    o, v, n = 6, 45, 90
+    L, tau, w = gaussian_inputs(11, o, v, n)
+    a = run(dev, o, v, n, L, tau, w, P.Options(n_abatch=7))
+    b = run(dev, o, v, n, L, tau, w, P.Options(n_abatch=7))
+    assert np.array_equal(a[0], b[0]) and a[1] == b[1] and np.array_equal(a[2], b[2])
+
+
+def test_workspace_too_small_raises(dev):
+    o, v, n = 2, 5, 3
+    L, tau, w = gaussian_inputs(12, o, v, n)
+    ws = torch.empty(512, dtype=torch.uint8, device=dev)
+    Lg, tg, wg = g(L, dev), g(tau, dev), g(w, dev)
+    R = torch.empty((o, o, v, v), dtype=torch.float64, device=dev)
+    with pytest.raises(ValueError):
+        P.forward(Lg, tg, wg, o=o, v=v, n=n, R=R, ws=ws)
+
+
+def test_medium_workload(dev):
+    """o=20, v=150, n=600, seed 2: every element of R and X and E against the oracle."""
+    o, v, n = 20, 150, 600
+    L, tau, tbar, _, _ = oracle.make_inputs(o, v, n, 2)
+    R, E, X = run(dev, o, v, n, L, tau, tbar)
+    Rr, Er = oracle.matrix.forward(o, v, n, L, tau, tbar)
+    Xr = oracle.matrix.adjoint(o, v, n, L, tau, tbar)
+    print("medium: E %.17g (oracle %.17g) err_R %.3e err_E %.3e err_X %.3e"
+          % (E, Er, err_norm(R, Rr), err_rel(E, Er), err_norm(X, Xr)))
+    assert err_norm(R, Rr) <= TOL and err_rel(E, Er) <= TOL and err_norm(X, Xr) <= TOL
+
+
+@pytest.mark.parametrize("o,v,n,seed", [(4, 20, 60, 1), (6, 53, 70, 21)])
+def test_amplitudes_and_update(dev, o, v, n, seed):
+    import synthetic
+    Lov = synthetic.draw_L_ov(seed, o, v, n)
+    eps = synthetic.draw_eps(seed, o, v)
+    t_ref = oracle.mp2_amplitudes(o, v, n, Lov, eps)
+    t = P.mp2_amplitudes(g(Lov, dev), g(eps, dev), o=o, v=v, n=n)
+    assert err_norm(t.cpu().numpy(), t_ref) <= 1e-13
+    tn = t.cpu().numpy()
+    assert np.array_equal(tn, tn.transpose(1, 0, 3, 2))  # pair symmetry is kept bitwise
+    R = np.random.default_rng(seed).standard_normal((o, o, v, v)) * 1e-3
+    t2_ref = oracle.amplitude_update(o, v, eps, R, t_ref)
+    tg = g(t_ref, dev)
+    P.amplitude_update(g(eps, dev), g(R, dev), tg, o=o, v=v)
+    assert err_norm(tg.cpu().numpy(), t2_ref) <= 1e-15
+
+
+def test_autograd_backward_matches_oracle(dev):
+    o, v, n = 3, 21, 25
+    L, tau, w = gaussian_inputs(13, o, v, n)
+    Lg = g(L, dev).requires_grad_(True)
+    wg = g(w, dev).requires_grad_(True)
+    E = P.ladder_energy(Lg, g(tau, dev), wg, (o, v, n))
+    E.backward()
+    Rr, Er = oracle.forward(o, v, n, L, tau, w)
+    Xr = oracle.adjoint(o, v, n, L, tau, w)
+    assert err_rel(float(E), Er) <= TOL
+    assert err_norm(Lg.grad.cpu().numpy(), Xr) <= TOL
+    assert err_norm(wg.grad.cpu().numpy(), Rr) <= TOL
+
+
+def test_autograd_finite_differences(dev):
+    """E is quadratic along one L entry: the central difference has no truncation error."""
+    o, v, n = 4, 30, 40
+    L, tau, w = gaussian_inputs(14, o, v, n)
+    Lg, tg, wg = g(L, dev), g(tau, dev), g(w, dev)
+    X = P.adjoint(Lg, tg, wg, o=o, v=v, n=n).cpu().numpy()
+    rng = np.random.default_rng(3)
+    h = 1e-6
+    worst = 0.0
+    for _ in range(200):
+        a, c, J = rng.integers(v), rng.integers(v), rng.integers(n)
+        Lp = Lg.clone(); Lp[a, c, J] += h
+        Lm = Lg.clone(); Lm[a, c, J] -= h
+        Ep = P.forward(Lp, tg, wg, o=o, v=v, n=n)[1]
+        Em = P.forward(Lm, tg, wg, o=o, v=v, n=n)[1]
+        fd = float((Ep - Em).cpu()) / (2 * h)
+        worst = max(worst, abs(fd - X[a, c, J]) / np.abs(X).max())
+    print("finite differences: worst |fd - X| / max|X| = %.3e" % worst)
+    assert worst < 1e-7

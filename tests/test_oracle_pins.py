@@ -16,6 +16,29 @@ import synthetic
 GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
 
 
+class _Matrix:
+    """The numpy matrix-product implementation behind the same interface."""
+
+    def __init__(self, c):
+        import oracle
+        self._m = oracle.matrix
+        self._c = c
+
+    def forward(self, o, v, n, L, tau, tbar=None):
+        return self._m.forward(o, v, n, L, tau, tbar)
+
+    def adjoint(self, o, v, n, L, tau, w):
+        return self._m.adjoint(o, v, n, L, tau, w)
+
+    def __getattr__(self, name):
+        return getattr(self._c, name)
+
+
+@pytest.fixture(params=["c", "matrix"])
+def impl(request, oracle_lib):
+    return oracle_lib if request.param == "c" else _Matrix(oracle_lib)
+
+
 def rnd(seed, *shape):
     return np.random.default_rng(seed).standard_normal(shape)
 
@@ -26,12 +49,12 @@ def pair_sym(x):
 
 
 # ---------------------------------------------------------------- worked example
-def test_micro_example(oracle_lib):
+def test_micro_example(impl):
     g = json.load(open(os.path.join(GOLDEN, "micro_example.json")))
     o, v, n = g["o"], g["v"], g["n"]
     L = np.array(g["L"]); tau = np.array(g["tau"]); tbar = np.array(g["tbar"])
-    R, E = oracle_lib.forward(o, v, n, L, tau, tbar)
-    X = oracle_lib.adjoint(o, v, n, L, tau, tbar)
+    R, E = impl.forward(o, v, n, L, tau, tbar)
+    X = impl.adjoint(o, v, n, L, tau, tbar)
     assert np.array_equal(R, np.array(g["R"]))
     assert E == g["E"]
     assert np.array_equal(X, np.array(g["X"]))
@@ -64,25 +87,25 @@ def _brute_int(o, v, n, L, tau, w):
 
 
 @pytest.mark.parametrize("seed,o,v,n", [(11, 2, 3, 2), (12, 1, 4, 3), (13, 3, 2, 1)])
-def test_integer_exact_brute_force(oracle_lib, seed, o, v, n):
+def test_integer_exact_brute_force(impl, seed, o, v, n):
     rng = np.random.default_rng(seed)
     L = rng.integers(-7, 8, size=(v, v, n))
     tau = rng.integers(-7, 8, size=(o, o, v, v))
     w = rng.integers(-7, 8, size=(o, o, v, v))  # deliberately neither symmetric
     R_ref, E_ref, X_ref = _brute_int(o, v, n, L.tolist(), tau.tolist(), w.tolist())
-    R, E = oracle_lib.forward(o, v, n, L.astype(float), tau.astype(float), w.astype(float))
-    X = oracle_lib.adjoint(o, v, n, L.astype(float), tau.astype(float), w.astype(float))
+    R, E = impl.forward(o, v, n, L.astype(float), tau.astype(float), w.astype(float))
+    X = impl.adjoint(o, v, n, L.astype(float), tau.astype(float), w.astype(float))
     assert np.array_equal(R, np.array(R_ref, dtype=float))
     assert E == float(E_ref)
     assert np.array_equal(X, np.array(X_ref, dtype=float))
 
 
 # ---------------------------------------------------------------- matrix closed forms
-def test_matrix_closed_form(oracle_lib):
+def test_matrix_closed_form(impl):
     o, v, n = 3, 7, 5
     L, tau, w = rnd(1, v, v, n), rnd(2, o, o, v, v), rnd(3, o, o, v, v)
-    R, E = oracle_lib.forward(o, v, n, L, tau, w)
-    X = oracle_lib.adjoint(o, v, n, L, tau, w)
+    R, E = impl.forward(o, v, n, L, tau, w)
+    X = impl.adjoint(o, v, n, L, tau, w)
     Lj = [np.ascontiguousarray(L[:, :, J]) for J in range(n)]
     R_ref = np.zeros_like(R)
     X_ref = np.zeros_like(X)
@@ -97,67 +120,67 @@ def test_matrix_closed_form(oracle_lib):
     assert abs(E - np.sum(w * R_ref)) <= 1e-13 * np.sum(np.abs(w * R_ref))
 
 
-def test_rank_one(oracle_lib):
+def test_rank_one(impl):
     """n=1, L_ac = u_a y_c:  R_ij^ab = u_a u_b (y^T T_ij y)."""
     o, v = 2, 6
     u, y = rnd(4, v), rnd(5, v)
     L = np.einsum("a,c->ac", u, y)[:, :, None]
     tau = rnd(6, o, o, v, v)
-    R, _ = oracle_lib.forward(o, v, 1, L, tau)
+    R, _ = impl.forward(o, v, 1, L, tau)
     ref = np.einsum("a,b,ijcd,c,d->ijab", u, u, tau, y, y)
     np.testing.assert_allclose(R, ref, rtol=0, atol=1e-13 * np.abs(ref).max())
 
 
-def test_zero_inputs(oracle_lib):
+def test_zero_inputs(impl):
     o, v, n = 2, 4, 3
     L, tau = rnd(7, v, v, n), rnd(8, o, o, v, v)
-    R, E = oracle_lib.forward(o, v, n, L, np.zeros_like(tau), tau)
+    R, E = impl.forward(o, v, n, L, np.zeros_like(tau), tau)
     assert not R.any() and E == 0.0
-    R, E = oracle_lib.forward(o, v, n, np.zeros_like(L), tau, tau)
+    R, E = impl.forward(o, v, n, np.zeros_like(L), tau, tau)
     assert not R.any() and E == 0.0
-    assert not oracle_lib.adjoint(o, v, n, L, tau, np.zeros_like(tau)).any()
+    assert not impl.adjoint(o, v, n, L, tau, np.zeros_like(tau)).any()
 
 
 # ---------------------------------------------------------------- invariants
-def test_pair_symmetry_of_R(oracle_lib):
+def test_pair_symmetry_of_R(impl):
     """tau_ij^ab = tau_ji^ba  =>  R_ij^ab = R_ji^ba for any L (even asymmetric in ac)."""
     o, v, n = 3, 6, 4
     L, tau = rnd(9, v, v, n), pair_sym(rnd(10, o, o, v, v))
-    R, _ = oracle_lib.forward(o, v, n, L, tau)
+    R, _ = impl.forward(o, v, n, L, tau)
     np.testing.assert_allclose(R, R.transpose(1, 0, 3, 2), rtol=0, atol=1e-14 * np.abs(R).max())
     # and the relation is not automatic: it fails for an asymmetric tau
-    R2, _ = oracle_lib.forward(o, v, n, L, rnd(10, o, o, v, v))
+    R2, _ = impl.forward(o, v, n, L, rnd(10, o, o, v, v))
     assert np.abs(R2 - R2.transpose(1, 0, 3, 2)).max() > 1e-3 * np.abs(R2).max()
 
 
-def test_euler_homogeneity(oracle_lib):
+def test_euler_homogeneity(impl):
     """E is homogeneous of degree 2 in L: sum_{J,ac} L^J_ac X^J_ac = 2E."""
     o, v, n = 3, 5, 4
     L, tau, w = rnd(11, v, v, n), rnd(12, o, o, v, v), rnd(13, o, o, v, v)
-    _, E = oracle_lib.forward(o, v, n, L, tau, w)
-    X = oracle_lib.adjoint(o, v, n, L, tau, w)
+    _, E = impl.forward(o, v, n, L, tau, w)
+    X = impl.adjoint(o, v, n, L, tau, w)
     assert abs(np.sum(L * X) - 2 * E) <= 1e-13 * np.sum(np.abs(L * X))
 
 
-def test_scaling_and_bilinearity(oracle_lib):
+def test_scaling_and_bilinearity(impl):
     o, v, n = 2, 5, 3
     L, tau, tau2, w, w2 = rnd(14, v, v, n), rnd(15, o, o, v, v), rnd(16, o, o, v, v), rnd(17, o, o, v, v), rnd(18, o, o, v, v)
-    R, E = oracle_lib.forward(o, v, n, L, tau, w)
-    X = oracle_lib.adjoint(o, v, n, L, tau, w)
-    Rs, Es = oracle_lib.forward(o, v, n, 2.0 * L, tau, w)
-    Xs = oracle_lib.adjoint(o, v, n, 2.0 * L, tau, w)
+    R, E = impl.forward(o, v, n, L, tau, w)
+    X = impl.adjoint(o, v, n, L, tau, w)
+    Rs, Es = impl.forward(o, v, n, 2.0 * L, tau, w)
+    Xs = impl.adjoint(o, v, n, 2.0 * L, tau, w)
     # E is quadratic in L, so its gradient X is linear in L (degree 1, not 3)
     assert np.array_equal(Rs, 4.0 * R) and Es == 4.0 * E and np.array_equal(Xs, 2.0 * X)
-    _, Ea = oracle_lib.forward(o, v, n, L, tau + 3.0 * tau2, w)
-    _, Eb = oracle_lib.forward(o, v, n, L, tau2, w)
-    _, Ec = oracle_lib.forward(o, v, n, L, tau, w2)
-    _, Ed = oracle_lib.forward(o, v, n, L, tau, w - 0.5 * w2)
+    _, Ea = impl.forward(o, v, n, L, tau + 3.0 * tau2, w)
+    _, Eb = impl.forward(o, v, n, L, tau2, w)
+    _, Ec = impl.forward(o, v, n, L, tau, w2)
+    _, Ed = impl.forward(o, v, n, L, tau, w - 0.5 * w2)
     scale = np.abs(R).sum() * np.abs(w).max() * 8
     assert abs(Ea - (E + 3.0 * Eb)) <= 1e-13 * scale
     assert abs(Ed - (E - 0.5 * Ec)) <= 1e-13 * scale
 
 
-def test_density_route_equals_residual_route(oracle_lib):
+def test_density_route_equals_residual_route(impl):
     """E = sum_abcd (ac|bd) O2_{..} with the V^4 density O^(2) of Appendix A.
 
     With d_abcd = O^(2)_abcd(L_2, C_2) = L_ij^ac C_ij^bd (Sec. II B, Appendix A;
@@ -166,45 +189,45 @@ def test_density_route_equals_residual_route(oracle_lib):
     """
     o, v, n = 3, 5, 4
     L, tau, w = rnd(19, v, v, n), rnd(20, o, o, v, v), rnd(21, o, o, v, v)
-    _, E = oracle_lib.forward(o, v, n, L, tau, w)
+    _, E = impl.forward(o, v, n, L, tau, w)
     g = np.einsum("pqJ,rsJ->pqrs", L, L)        # (pq|rs), Mulliken
     d = np.einsum("ijpr,ijqs->pqrs", w, tau)     # O2_pqrs = tbar_ij^pr tau_ij^qs
     E_density = np.einsum("pqrs,pqrs->", g, d)
     assert abs(E - E_density) <= 1e-13 * np.einsum("pqrs,pqrs->", np.abs(g), np.abs(d))
 
 
-def test_factor_two_form_under_pair_symmetry(oracle_lib):
+def test_factor_two_form_under_pair_symmetry(impl):
     """d_pqrs = d_rspq (Appendix A): with pair-symmetric tbar and tau,
     X^J_ac = 2 sum_bd L^J_bd D_{ab,cd}, D_{ab,cd} = sum_ij tbar_ij^ab tau_ij^cd."""
     o, v, n = 3, 5, 4
     L, tau, w = rnd(22, v, v, n), pair_sym(rnd(23, o, o, v, v)), pair_sym(rnd(24, o, o, v, v))
-    X = oracle_lib.adjoint(o, v, n, L, tau, w)
+    X = impl.adjoint(o, v, n, L, tau, w)
     D = np.einsum("ijab,ijcd->abcd", w, tau)
     X2 = 2.0 * np.einsum("abcd,bdJ->acJ", D, L)
     np.testing.assert_allclose(X, X2, rtol=0, atol=1e-13 * np.abs(X2).max())
     # without pair symmetry the factor-2 form is wrong, and the oracle must not use it
     wa = rnd(25, o, o, v, v)
-    Xa = oracle_lib.adjoint(o, v, n, L, tau, wa)
+    Xa = impl.adjoint(o, v, n, L, tau, wa)
     Xa2 = 2.0 * np.einsum("abcd,bdJ->acJ", np.einsum("ijab,ijcd->abcd", wa, tau), L)
     assert np.abs(Xa - Xa2).max() > 1e-3 * np.abs(Xa).max()
 
 
 # ---------------------------------------------------------------- finite differences
 @pytest.mark.parametrize("symmetric", [True, False])
-def test_finite_differences(oracle_lib, symmetric):
+def test_finite_differences(impl, symmetric):
     """E is exactly quadratic along any single L entry, so the central difference
     has zero truncation error and must match X to rounding."""
     o, v, n = 2, 5, 3
     L, tau, w = rnd(26, v, v, n), rnd(27, o, o, v, v), rnd(28, o, o, v, v)
     if symmetric:
         tau, w = pair_sym(tau), pair_sym(w)
-    X = oracle_lib.adjoint(o, v, n, L, tau, w)
+    X = impl.adjoint(o, v, n, L, tau, w)
     h = 1e-3
     for (a, c, J) in [(0, 0, 0), (1, 3, 2), (4, 2, 1), (2, 2, 0), (3, 0, 2)]:
         Lp, Lm = L.copy(), L.copy()
         Lp[a, c, J] += h
         Lm[a, c, J] -= h
-        fd = (oracle_lib.forward(o, v, n, Lp, tau, w)[1] - oracle_lib.forward(o, v, n, Lm, tau, w)[1]) / (2 * h)
+        fd = (impl.forward(o, v, n, Lp, tau, w)[1] - impl.forward(o, v, n, Lm, tau, w)[1]) / (2 * h)
         assert abs(fd - X[a, c, J]) <= 1e-9 * max(1.0, abs(X).max()), (a, c, J, fd, X[a, c, J])
 
 
