@@ -155,7 +155,8 @@ __global__ __launch_bounds__(F64_THREADS) void gemm_f64_kernel(GemmShape s, Epi 
         __syncthreads();
     }
 
-    // D layout of v_mfma_f64_16x16x4_f64: lane l holds rows 4*(l/16)+r, column l%16.
+    // D layout of v_mfma_f64_16x16x4_f64 on gfx950 (measured): lane l, element r holds
+    // row (l/16) + 4r, column l%16.
     typename Epi::Local loc = epi.begin();
 #pragma unroll
     for (int i = 0; i < 4; ++i)
@@ -163,7 +164,7 @@ __global__ __launch_bounds__(F64_THREADS) void gemm_f64_kernel(GemmShape s, Epi 
         for (int j = 0; j < 4; ++j)
 #pragma unroll
             for (int r = 0; r < 4; ++r) {
-                const int64_t m = m0 + wm * 64 + 16 * i + 4 * lk + r;
+                const int64_t m = m0 + wm * 64 + 16 * i + lk + 4 * r;
                 const int64_t n = n0 + wn * 64 + 16 * j + lr;
                 if (m < s.M && n < s.N) epi.put(loc, m, n, acc[i][j][r]);
             }

@@ -38,6 +38,9 @@ def integer_inputs(seed, o, v, n, symmetric=True, lim=7):
         # make x_ji^ba = x_ij^ab exactly, keeping integers
         for x in (tau, w):
             for i in range(o):
-                for j in range(i + 1):
+                for j in range(i):
                     x[j, i] = x[i, j].T
+                U = np.triu(x[i, i])
+                x[i, i] = U + np.triu(U, 1).T
+        assert np.array_equal(tau, tau.transpose(1, 0, 3, 2)) and np.array_equal(w, w.transpose(1, 0, 3, 2))
     return L, tau, w
