@@ -121,6 +121,13 @@ def main():
     roofline = {"bound": "mfma", "kernel": dom_name, "achieved": achieved, "peak": PEAK[dtype_peak],
                 "unit": "TFLOP/s", "frac": achieved / PEAK[dtype_peak], "traffic": None,
                 "avg_launch_ms": dom["avg_ms"], "launches_per_step": dom["launches"] / steps}
+    if args.precision == "split":
+        S = args.slices or 5
+        prods = S * (S + 1) // 2
+        # BF16 MFMA work actually issued: every slice pair (p, q) with p + q < S
+        roofline["slice_products"] = prods
+        roofline["executed_bf16_tflops"] = achieved * prods
+        roofline["frac_executed"] = achieved * prods / PEAK["bf16"]
     stage_summary = {k: {"ms_per_step": s["total_ms"] / steps, "launches_per_step": s["launches"] / steps,
                          "tflops": (s["flops"] / (s["total_ms"] * 1e-3) / 1e12) if s["total_ms"] > 0 else None}
                      for k, s in stages.items()}

@@ -13,6 +13,13 @@
 //           (the V^4 density O^(2) of Sec. II B as a batch tile only)
 //   GEMM-F  X[(a,c),J] = beta X + 2 alpha sum_(bd) D_A[(a,c),(bd)] L[(bd),J]  M = nA*v, N = n, K = v^2
 //           (2 W~ of Sec. II C; the factor 2 is d_pqrs = d_rspq, Appendix A)
+//
+// Precision LADDER_FP64 runs the four GEMMs on v_mfma_f64_16x16x4_f64.
+// Precision LADDER_SPLIT_BF16 first cuts every GEMM operand into S exponent-
+// aligned BF16 slices along its contraction index (inputs once per call, the g
+// and D tiles once per batch) and runs the GEMMs on BF16 MFMA with exact FP32
+// chunk sums folded into FP64 (split_bf16.hpp); R, E and X are accumulated and
+// stored in FP64.
 #include <hip/hip_runtime.h>
 
 #include <stdarg.h>
@@ -27,6 +34,7 @@
 
 #include "../../include/ladder.h"
 #include "gemm_f64.hpp"
+#include "split_bf16.hpp"
 
 using namespace ladder;
 
@@ -51,6 +59,7 @@ int hip_check(hipError_t e, const char* what) {
 }
 
 constexpr int64_t MAX_DIM = int64_t(1) << 20;
+constexpr int DEFAULT_SLICES = 5;
 
 // ------------------------------------------------------------ stage timing
 struct StageRec {
@@ -84,8 +93,9 @@ struct StageTimer {
     }
 };
 
-double gemm_bytes(int64_t M, int64_t N, int64_t K) { return 8.0 * ((double)M * K + (double)K * N + (double)M * N); }
 double gemm_flops(int64_t M, int64_t N, int64_t K) { return 2.0 * (double)M * (double)N * (double)K; }
+// Algorithmic bytes of an FP64 GEMM: both operands read once, the result written once.
+double gemm_bytes(int64_t M, int64_t N, int64_t K) { return 8.0 * ((double)M * K + (double)K * N + (double)M * N); }
 
 bool mul_ok(int64_t a, int64_t b, int64_t& out) {
     if (a < 0 || b < 0) return false;
@@ -99,10 +109,11 @@ struct Sizes {
 };
 
 int check_dims(int64_t o, int64_t v, int64_t n, Sizes& s) {
-    if (o < 1 || v < 1 || n < 1) return fail(LADDER_EINVAL, "dimensions must be >= 1 (o=%lld v=%lld n=%lld)", (long long)o, (long long)v, (long long)n);
+    if (o < 1 || v < 1 || n < 1)
+        return fail(LADDER_EINVAL, "dimensions must be >= 1 (o=%lld v=%lld n=%lld)", (long long)o, (long long)v, (long long)n);
     if (o > MAX_DIM || v > MAX_DIM || n > MAX_DIM) return fail(LADDER_EINVAL, "dimension above 2^20");
     if (!mul_ok(o, o, s.oo) || !mul_ok(v, v, s.vv) || !mul_ok(s.oo, s.vv, s.ovv_elems) || !mul_ok(s.vv, n, s.vvn) ||
-        !mul_ok(s.vv, v, s.vvv) || s.ovv_elems > INT64_MAX / 8 || s.vvn > INT64_MAX / 8)
+        !mul_ok(s.vv, v, s.vvv) || s.ovv_elems > INT64_MAX / 16 || s.vvn > INT64_MAX / 16 || s.vvv > INT64_MAX / 16)
         return fail(LADDER_EINVAL, "array sizes overflow 64-bit byte counts");
     return LADDER_OK;
 }
@@ -120,8 +131,12 @@ int get_opts(const ladder_options* in, ladder_options& o) {
     if (in) o = *in;
     if (o.precision != LADDER_FP64 && o.precision != LADDER_SPLIT_BF16)
         return fail(LADDER_EUNSUPPORTED, "unknown precision %d", (int)o.precision);
-    if (o.precision == LADDER_SPLIT_BF16)
-        return fail(LADDER_EUNSUPPORTED, "split-BF16 precision is not built into this library yet");
+    if (o.precision == LADDER_SPLIT_BF16) {
+        if (o.n_slices == 0) o.n_slices = DEFAULT_SLICES;
+        if (o.n_slices < 2 || o.n_slices > SPLIT_MAX_S)
+            return fail(LADDER_EUNSUPPORTED, "n_slices must be 0 (default %d) or in [2, %d], got %d", DEFAULT_SLICES,
+                        SPLIT_MAX_S, (int)o.n_slices);
+    }
     if (o.n_abatch < 0) return fail(LADDER_EINVAL, "n_abatch must be >= 0");
     if (o.flags & ~LADDER_FLAG_GENERAL) return fail(LADDER_EUNSUPPORTED, "unknown flag bits 0x%x", o.flags);
     if (o.reserved != 0) return fail(LADDER_EINVAL, "reserved option field must be 0");
@@ -132,22 +147,59 @@ constexpr size_t ALIGN = 256;
 size_t align_up(size_t x) { return (x + ALIGN - 1) / ALIGN * ALIGN; }
 
 int64_t tiles(int64_t M, int64_t N) { return ((M + F64_BM - 1) / F64_BM) * ((N + F64_BN - 1) / F64_BN); }
+static_assert(F64_BM == SPLIT_BM && F64_BN == SPLIT_BN, "energy partial slots assume one tile size");
 
-// Batch plan and workspace layout shared by forward and adjoint.
+// Bump allocator over the caller's workspace (offsets only; sizes 256-aligned).
+struct Arena {
+    size_t top = 0;
+    size_t take(size_t bytes) {
+        const size_t off = top;
+        top += align_up(bytes);
+        return off;
+    }
+};
+
+// One sliced operand: S slices of R rows x Kp, and nch x R exponents.
+struct SlicedBuf {
+    size_t s_off = 0, e_off = 0;
+    int64_t R = 0, K = 0;
+};
+size_t slice_bytes(int S, int64_t R, int64_t K) { return (size_t)S * (size_t)R * (size_t)split_kpad(K) * 2; }
+size_t exp_bytes(int64_t R, int64_t K) { return (size_t)split_nchunk(K) * (size_t)R * 4; }
+SlicedBuf take_sliced(Arena& a, int S, int64_t R, int64_t K) {
+    SlicedBuf b;
+    b.R = R;
+    b.K = K;
+    b.s_off = a.take(slice_bytes(S, R, K));
+    b.e_off = a.take(exp_bytes(R, K));
+    return b;
+}
+
+// Batch plan and workspace layout.  The batch region (g or D tile, and its
+// slices in split mode) is shared by forward and adjoint; the rest holds the
+// per-call data of one direction (slices of the inputs, energy partials, the
+// pair-swapped copies of the general adjoint), and both directions start at the
+// same offset.
 struct Plan {
-    int64_t nA, nbatch;
-    size_t tile_off, tile_bytes;      // g_A or D_A
-    size_t part_off, part_per_batch;  // energy partials (doubles per batch)
-    size_t swap_off, swap_bytes;      // pair-swapped w and tau (general adjoint)
-    size_t total;
+    int S = 0;  // 0: FP64
+    int64_t nA = 0, nbatch = 0;
+    size_t tile_off = 0;                 // FP64 g_A or D_A, nA*v^3 doubles
+    SlicedBuf tile_sl;                   // split: slices of the tile (rows nA*v, K = v^2)
+    size_t part_off = 0, part_per_batch = 0;
+    SlicedBuf L_J, tau_cd;               // split forward: L along J, tau along (cd)
+    SlicedBuf w_ij, tau_ij, L_bd;        // split adjoint: w and tau along (ij) (rows (ab)/(cd)), L along (bd) (rows J)
+    size_t swap_off = 0;                 // general adjoint: P w and P tau, FP64
+    SlicedBuf pw_ij, ptau_ij;            // general split adjoint: their slices
+    size_t fwd_total = 0, adj_total = 0, total = 0;
 };
 
 Plan make_plan(int64_t o, int64_t v, int64_t n, const ladder_options& op, const Sizes& s) {
-    (void)n;
-    Plan p{};
+    Plan p;
+    p.S = op.precision == LADDER_SPLIT_BF16 ? op.n_slices : 0;
     int64_t nA = op.n_abatch;
     if (nA == 0) {
-        const int64_t per_a = s.vvv * 8;
+        int64_t per_a = s.vvv * 8;
+        if (p.S) per_a += (int64_t)(slice_bytes(p.S, v, s.vv) + exp_bytes(v, s.vv));
         nA = (int64_t)(LADDER_DEFAULT_TILE_BYTES / (size_t)per_a);
         // at least two batches, so the whole v^4 array is never held at once
         nA = std::min(nA, (v + 1) / 2);
@@ -156,25 +208,110 @@ Plan make_plan(int64_t o, int64_t v, int64_t n, const ladder_options& op, const 
     if (nA > v) nA = v;
     p.nA = nA;
     p.nbatch = (v + nA - 1) / nA;
-    p.tile_off = 0;
-    p.tile_bytes = align_up((size_t)(nA * s.vvv) * 8);
-    p.part_off = p.tile_bytes;
+
+    Arena a;
+    p.tile_off = a.take((size_t)(nA * s.vvv) * 8);
+    if (p.S) p.tile_sl = take_sliced(a, p.S, nA * v, s.vv);
+    const size_t common = a.top;
+
+    Arena f = a;  // forward-only part
     p.part_per_batch = (size_t)tiles(s.oo, nA * v);
-    const size_t part_bytes = align_up(p.part_per_batch * (size_t)p.nbatch * 8);
-    p.swap_off = p.part_off + part_bytes;
-    p.swap_bytes = (op.flags & LADDER_FLAG_GENERAL) ? align_up((size_t)s.ovv_elems * 8) * 2 : 0;
-    p.total = p.swap_off + p.swap_bytes;
+    p.part_off = f.take(p.part_per_batch * (size_t)p.nbatch * 8);
+    if (p.S) {
+        p.L_J = take_sliced(f, p.S, s.vv, n);
+        p.tau_cd = take_sliced(f, p.S, s.oo, s.vv);
+    }
+    p.fwd_total = f.top;
+
+    Arena d = a;  // adjoint-only part
+    const bool general = (op.flags & LADDER_FLAG_GENERAL) != 0;
+    if (general) p.swap_off = d.take((size_t)s.ovv_elems * 16);
+    if (p.S) {
+        p.w_ij = take_sliced(d, p.S, s.vv, s.oo);
+        p.tau_ij = take_sliced(d, p.S, s.vv, s.oo);
+        p.L_bd = take_sliced(d, p.S, n, s.vv);
+        if (general) {
+            p.pw_ij = take_sliced(d, p.S, s.vv, s.oo);
+            p.ptau_ij = take_sliced(d, p.S, s.vv, s.oo);
+        }
+    }
+    p.adj_total = d.top;
+    (void)common;
     (void)o;
+    p.total = std::max(p.fwd_total, p.adj_total);
     return p;
 }
 
+// ---------------------------------------------------------------- launches
 template <bool AK, bool BK, class Epi>
 hipError_t launch_gemm(const double* A, int64_t lda, const double* B, int64_t ldb, int64_t M, int64_t N, int64_t K,
                        const Epi& epi, hipStream_t st) {
     GemmShape sh{A, lda, B, ldb, M, N, K};
-    const int64_t T = tiles(M, N);
-    hipLaunchKernelGGL((gemm_f64_kernel<AK, BK, Epi>), dim3((unsigned)T), dim3(F64_THREADS), 0, st, sh, epi);
+    hipLaunchKernelGGL((gemm_f64_kernel<AK, BK, Epi>), dim3((unsigned)tiles(M, N)), dim3(F64_THREADS), 0, st, sh, epi);
     return hipGetLastError();
+}
+
+// A view of rows [row0, row0 + rows) of a sliced buffer.
+SplitOperand view(char* ws, const SlicedBuf& b, int64_t row0) {
+    SplitOperand v;
+    const int64_t Kp = split_kpad(b.K);
+    v.s = (const unsigned short*)(ws + b.s_off) + row0 * Kp;
+    v.slice_stride = b.R * Kp;
+    v.ld = Kp;
+    v.e = (const int*)(ws + b.e_off) + row0;
+    v.e_ld = b.R;
+    return v;
+}
+
+template <int S, class Epi>
+hipError_t launch_split_s(const SplitShape& sh, const Epi& epi, hipStream_t st) {
+    hipLaunchKernelGGL((gemm_split_kernel<S, Epi>), dim3((unsigned)tiles(sh.M, sh.N)), dim3(SPLIT_THREADS), 0, st, sh, epi);
+    return hipGetLastError();
+}
+
+template <class Epi>
+hipError_t launch_split(int S, const SplitShape& sh, const Epi& epi, hipStream_t st) {
+    switch (S) {
+        case 2: return launch_split_s<2>(sh, epi, st);
+        case 3: return launch_split_s<3>(sh, epi, st);
+        case 4: return launch_split_s<4>(sh, epi, st);
+        case 5: return launch_split_s<5>(sh, epi, st);
+        case 6: return launch_split_s<6>(sh, epi, st);
+        default: return hipErrorInvalidValue;
+    }
+}
+
+template <int S>
+hipError_t slice_s(bool transposed, const double* src, int64_t ld, int64_t R, int64_t K, unsigned short* sl, int* ex,
+                   hipStream_t st) {
+    const int64_t nch = split_nchunk(K);
+    if (!transposed) {
+        const int64_t jobs = R * nch;
+        hipLaunchKernelGGL((slice_rows_kernel<S>), dim3((unsigned)((jobs + 3) / 4)), dim3(256), 0, st, src, ld, R, K, sl,
+                           ex, R);
+    } else {
+        const int64_t blocks = ((R + 31) / 32) * nch;
+        hipLaunchKernelGGL((slice_cols_kernel<S>), dim3((unsigned)blocks), dim3(256), 0, st, src, ld, R, K, sl, ex, R);
+    }
+    return hipGetLastError();
+}
+
+// Slices src into the buffer b (rows b.R, length b.K).  transposed: element
+// (r, k) at src[k*ld + r]; otherwise at src[r*ld + k].
+int slice_into(int S, bool transposed, const double* src, int64_t ld, char* ws, const SlicedBuf& b, hipStream_t st) {
+    StageTimer tm(LADDER_STAGE_SLICE, 0.0, (8.0 + 2.0 * S) * (double)b.R * (double)b.K, st);
+    unsigned short* sl = (unsigned short*)(ws + b.s_off);
+    int* ex = (int*)(ws + b.e_off);
+    hipError_t e;
+    switch (S) {
+        case 2: e = slice_s<2>(transposed, src, ld, b.R, b.K, sl, ex, st); break;
+        case 3: e = slice_s<3>(transposed, src, ld, b.R, b.K, sl, ex, st); break;
+        case 4: e = slice_s<4>(transposed, src, ld, b.R, b.K, sl, ex, st); break;
+        case 5: e = slice_s<5>(transposed, src, ld, b.R, b.K, sl, ex, st); break;
+        case 6: e = slice_s<6>(transposed, src, ld, b.R, b.K, sl, ex, st); break;
+        default: e = hipErrorInvalidValue;
+    }
+    return hip_check(e, "slice launch");
 }
 
 // out_ij^ab = in_ji^ba
@@ -266,7 +403,7 @@ int ladder_forward(int64_t o, int64_t v, int64_t n, const double* L, const doubl
         ((uintptr_t)ws % ALIGN))
         return fail(LADDER_EINVAL, "misaligned pointer (arrays need 8-byte, ws 256-byte alignment)");
     const Plan p = make_plan(o, v, n, op, s);
-    if (ws_bytes < p.total) return fail(LADDER_EWORKSPACE, "workspace of %zu bytes, %zu needed", ws_bytes, p.total);
+    if (ws_bytes < p.fwd_total) return fail(LADDER_EWORKSPACE, "workspace of %zu bytes, %zu needed", ws_bytes, p.fwd_total);
     const int64_t tb = s.ovv_elems * 8, lb = s.vvn * 8;
     if (overlap(R, tb, L, lb) || overlap(R, tb, tau, tb) || overlap(R, tb, tbar, tb) || overlap(R, tb, ws, (int64_t)ws_bytes))
         return fail(LADDER_EINVAL, "R overlaps an input or the workspace");
@@ -277,21 +414,45 @@ int ladder_forward(int64_t o, int64_t v, int64_t n, const double* L, const doubl
     char* w = (char*)ws;
     double* g = (double*)(w + p.tile_off);
     double* part = (double*)(w + p.part_off);
+    const int S = p.S;
+    if (S) {
+        if ((rc = slice_into(S, false, L, n, w, p.L_J, st))) return rc;
+        if ((rc = slice_into(S, false, tau, s.vv, w, p.tau_cd, st))) return rc;
+    }
     for (int64_t bi = 0; bi < p.nbatch; ++bi) {
         const int64_t a0 = bi * p.nA;
         const int64_t nA = std::min(p.nA, v - a0);
         {
             StageTimer tm(LADDER_STAGE_GEMM_B, gemm_flops(nA * v, s.vv, n), gemm_bytes(nA * v, s.vv, n), st);
             EpiSwapMid eg{g, v, v, v, 1.0, 0.0};
-            if ((rc = hip_check(launch_gemm<true, true>(L + a0 * v * n, n, L, n, nA * v, s.vv, n, eg, st), "GEMM-B launch")))
-                return rc;
+            hipError_t e;
+            if (!S) {
+                e = launch_gemm<true, true>(L + a0 * v * n, n, L, n, nA * v, s.vv, n, eg, st);
+            } else {
+                SplitShape sh{view(w, p.L_J, a0 * v), view(w, p.L_J, 0), nA * v, s.vv, n};
+                e = launch_split(S, sh, eg, st);
+            }
+            if ((rc = hip_check(e, "GEMM-B launch"))) return rc;
+        }
+        if (S) {
+            SlicedBuf tl = p.tile_sl;
+            tl.R = nA * v;  // this batch's rows
+            if ((rc = slice_into(S, false, g, s.vv, w, tl, st))) return rc;
         }
         {
             StageTimer tm(LADDER_STAGE_GEMM_C, gemm_flops(s.oo, nA * v, s.vv) + (E ? 2.0 * s.oo * nA * v : 0.0),
                           gemm_bytes(s.oo, nA * v, s.vv) + (E ? 8.0 * s.oo * nA * v : 0.0), st);
             EpiStrided er{R + a0 * v, s.vv, 1.0, beta, E ? tbar + a0 * v : nullptr, part + bi * p.part_per_batch};
-            if ((rc = hip_check(launch_gemm<true, true>(tau, s.vv, g, s.vv, s.oo, nA * v, s.vv, er, st), "GEMM-C launch")))
-                return rc;
+            hipError_t e;
+            if (!S) {
+                e = launch_gemm<true, true>(tau, s.vv, g, s.vv, s.oo, nA * v, s.vv, er, st);
+            } else {
+                SlicedBuf tl = p.tile_sl;
+                tl.R = nA * v;
+                SplitShape sh{view(w, p.tau_cd, 0), view(w, tl, 0), s.oo, nA * v, s.vv};
+                e = launch_split(S, sh, er, st);
+            }
+            if ((rc = hip_check(e, "GEMM-C launch"))) return rc;
         }
     }
     if (E) {
@@ -318,7 +479,7 @@ int ladder_adjoint(int64_t o, int64_t v, int64_t n, const double* L, const doubl
     if (!aligned8(L) || !aligned8(tau) || !aligned8(wt) || !aligned8(X) || ((uintptr_t)ws % ALIGN))
         return fail(LADDER_EINVAL, "misaligned pointer (arrays need 8-byte, ws 256-byte alignment)");
     const Plan p = make_plan(o, v, n, op, s);
-    if (ws_bytes < p.total) return fail(LADDER_EWORKSPACE, "workspace of %zu bytes, %zu needed", ws_bytes, p.total);
+    if (ws_bytes < p.adj_total) return fail(LADDER_EWORKSPACE, "workspace of %zu bytes, %zu needed", ws_bytes, p.adj_total);
     const int64_t tb = s.ovv_elems * 8, lb = s.vvn * 8;
     if (overlap(X, lb, L, lb) || overlap(X, lb, tau, tb) || overlap(X, lb, wt, tb) || overlap(X, lb, ws, (int64_t)ws_bytes))
         return fail(LADDER_EINVAL, "X overlaps an input or the workspace");
@@ -328,33 +489,59 @@ int ladder_adjoint(int64_t o, int64_t v, int64_t n, const double* L, const doubl
     double* D = (double*)(w + p.tile_off);
     const bool general = (op.flags & LADDER_FLAG_GENERAL) != 0;
     double* pw = general ? (double*)(w + p.swap_off) : nullptr;
-    double* pt = general ? (double*)(w + p.swap_off + p.swap_bytes / 2) : nullptr;
+    double* pt = general ? pw + s.ovv_elems : nullptr;
+    const int S = p.S;
     if (general) {
         StageTimer tm(LADDER_STAGE_SWAP, 0.0, 32.0 * (double)s.ovv_elems, st);
         hipLaunchKernelGGL(pair_swap_kernel, dim3(grid_for(s.ovv_elems)), dim3(256), 0, st, wt, pw, o, v);
         hipLaunchKernelGGL(pair_swap_kernel, dim3(grid_for(s.ovv_elems)), dim3(256), 0, st, tau, pt, o, v);
         if ((rc = hip_check(hipGetLastError(), "pair swap launch"))) return rc;
     }
+    if (S) {
+        if ((rc = slice_into(S, true, wt, s.vv, w, p.w_ij, st))) return rc;
+        if ((rc = slice_into(S, true, tau, s.vv, w, p.tau_ij, st))) return rc;
+        if ((rc = slice_into(S, true, L, n, w, p.L_bd, st))) return rc;
+        if (general) {
+            if ((rc = slice_into(S, true, pw, s.vv, w, p.pw_ij, st))) return rc;
+            if ((rc = slice_into(S, true, pt, s.vv, w, p.ptau_ij, st))) return rc;
+        }
+    }
     for (int64_t bi = 0; bi < p.nbatch; ++bi) {
         const int64_t a0 = bi * p.nA;
         const int64_t nA = std::min(p.nA, v - a0);
-        {
+        for (int term = 0; term < (general ? 2 : 1); ++term) {
             StageTimer tm(LADDER_STAGE_GEMM_E, gemm_flops(nA * v, s.vv, s.oo), gemm_bytes(nA * v, s.vv, s.oo), st);
-            EpiSwapMid ed{D, v, v, v, 1.0, 0.0};
-            if ((rc = hip_check(launch_gemm<false, false>(wt + a0 * v, s.vv, tau, s.vv, nA * v, s.vv, s.oo, ed, st), "GEMM-E launch")))
-                return rc;
+            EpiSwapMid ed{D, v, v, v, 1.0, term ? 1.0 : 0.0};
+            hipError_t e;
+            if (!S) {
+                const double* wa = term ? pw : wt;
+                const double* ta = term ? pt : tau;
+                e = launch_gemm<false, false>(wa + a0 * v, s.vv, ta, s.vv, nA * v, s.vv, s.oo, ed, st);
+            } else {
+                SplitShape sh{view(w, term ? p.pw_ij : p.w_ij, a0 * v), view(w, term ? p.ptau_ij : p.tau_ij, 0), nA * v,
+                              s.vv, s.oo};
+                e = launch_split(S, sh, ed, st);
+            }
+            if ((rc = hip_check(e, "GEMM-E launch"))) return rc;
         }
-        if (general) {
-            StageTimer tm(LADDER_STAGE_GEMM_E, gemm_flops(nA * v, s.vv, s.oo), gemm_bytes(nA * v, s.vv, s.oo), st);
-            EpiSwapMid ed2{D, v, v, v, 1.0, 1.0};
-            if ((rc = hip_check(launch_gemm<false, false>(pw + a0 * v, s.vv, pt, s.vv, nA * v, s.vv, s.oo, ed2, st), "GEMM-E launch")))
-                return rc;
+        if (S) {
+            SlicedBuf tl = p.tile_sl;
+            tl.R = nA * v;
+            if ((rc = slice_into(S, false, D, s.vv, w, tl, st))) return rc;
         }
         {
             StageTimer tm(LADDER_STAGE_GEMM_F, gemm_flops(nA * v, n, s.vv), gemm_bytes(nA * v, n, s.vv), st);
             EpiStrided ex{X + a0 * v * n, n, general ? alpha : 2.0 * alpha, beta, nullptr, nullptr};
-            if ((rc = hip_check(launch_gemm<true, false>(D, s.vv, L, n, nA * v, n, s.vv, ex, st), "GEMM-F launch")))
-                return rc;
+            hipError_t e;
+            if (!S) {
+                e = launch_gemm<true, false>(D, s.vv, L, n, nA * v, n, s.vv, ex, st);
+            } else {
+                SlicedBuf tl = p.tile_sl;
+                tl.R = nA * v;
+                SplitShape sh{view(w, tl, 0), view(w, p.L_bd, 0), nA * v, n, s.vv};
+                e = launch_split(S, sh, ex, st);
+            }
+            if ((rc = hip_check(e, "GEMM-F launch"))) return rc;
         }
     }
     return LADDER_OK;
@@ -372,7 +559,8 @@ int ladder_mp2_amplitudes(int64_t o, int64_t v, int64_t n, const double* Lov, co
         return fail(LADDER_EINVAL, "t overlaps an input");
     EpiMP2 ep{t, eps, o, v};
     StageTimer tm(LADDER_STAGE_MP2, gemm_flops(o * v, o * v, n), gemm_bytes(o * v, o * v, n), (hipStream_t)stream);
-    return hip_check(launch_gemm<true, true>(Lov, n, Lov, n, o * v, o * v, n, ep, (hipStream_t)stream), "amplitude GEMM launch");
+    return hip_check(launch_gemm<true, true>(Lov, n, Lov, n, o * v, o * v, n, ep, (hipStream_t)stream),
+                     "amplitude GEMM launch");
 }
 
 int ladder_amplitude_update(int64_t o, int64_t v, const double* eps, const double* R, double* t, void* stream) {
@@ -385,7 +573,8 @@ int ladder_amplitude_update(int64_t o, int64_t v, const double* eps, const doubl
     if (R != t && overlap(t, s.ovv_elems * 8, R, s.ovv_elems * 8)) return fail(LADDER_EINVAL, "R partially overlaps t");
     if (overlap(t, s.ovv_elems * 8, eps, (o + v) * 8)) return fail(LADDER_EINVAL, "t overlaps eps");
     StageTimer tm(LADDER_STAGE_UPDATE, 2.0 * (double)s.ovv_elems, 24.0 * (double)s.ovv_elems, (hipStream_t)stream);
-    hipLaunchKernelGGL(amplitude_update_kernel, dim3(grid_for(s.ovv_elems)), dim3(256), 0, (hipStream_t)stream, eps, R, t, o, v);
+    hipLaunchKernelGGL(amplitude_update_kernel, dim3(grid_for(s.ovv_elems)), dim3(256), 0, (hipStream_t)stream, eps, R,
+                       t, o, v);
     return hip_check(hipGetLastError(), "amplitude update launch");
 }
 

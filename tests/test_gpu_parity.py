@@ -206,3 +206,90 @@ def test_autograd_finite_differences(dev):
         worst = max(worst, abs(fd - X[a, c, J]) / np.abs(X).max())
     print("finite differences: worst |fd - X| / max|X| = %.3e" % worst)
     assert worst < 1e-7
+
+
+# ------------------------------------------------------------------ split BF16
+SPLIT5 = P.Options(precision=P.SPLIT_BF16, n_slices=5)
+# Accuracy targets of the split path: 1e-8 normwise in R and X, 1e-10 relative in E.
+SPLIT_TOL_RX = 1e-8
+SPLIT_TOL_E = 1e-10
+
+
+@pytest.mark.parametrize("o,v,n,seed,S", [(2, 5, 3, 1, 3), (3, 4, 2, 2, 2), (2, 33, 21, 4, 3)])
+def test_split_integer_inputs_bitwise(dev, o, v, n, seed, S):
+    """Small integers are carried exactly by two or three slices, and every FP32
+    chunk sum is exact, so the split path must agree bitwise with the oracle."""
+    L, tau, w = integer_inputs(seed, o, v, n, lim=3)
+    R, E, X = run(dev, o, v, n, L, tau, w, P.Options(precision=P.SPLIT_BF16, n_slices=S, n_abatch=7))
+    Rr, Er = oracle.forward(o, v, n, L, tau, w)
+    Xr = oracle.adjoint(o, v, n, L, tau, w)
+    assert np.array_equal(R, Rr)
+    assert E == Er
+    assert np.array_equal(X, Xr)
+
+
+def test_split_tiny_workload(dev):
+    o, v, n = 4, 20, 60
+    L, tau, tbar, _, _ = oracle.make_inputs(o, v, n, 1)
+    R, E, X = run(dev, o, v, n, L, tau, tbar, SPLIT5)
+    Rr, Er = oracle.forward(o, v, n, L, tau, tbar)
+    Xr = oracle.adjoint(o, v, n, L, tau, tbar)
+    print("split tiny: err_R %.3e err_E %.3e err_X %.3e" % (err_norm(R, Rr), err_rel(E, Er), err_norm(X, Xr)))
+    assert err_norm(R, Rr) <= SPLIT_TOL_RX and err_rel(E, Er) <= SPLIT_TOL_E and err_norm(X, Xr) <= SPLIT_TOL_RX
+
+
+@pytest.mark.parametrize("o,v,n,nA", [(5, 37, 70, 4), (3, 41, 300, 0), (7, 19, 257, 19), (2, 129, 17, 64)])
+def test_split_ragged_tiles_chunks_batches(dev, o, v, n, nA):
+    """K not a multiple of the 256 chunk nor of 16, several batches, ragged edges."""
+    L, tau, w = gaussian_inputs(200 + v, o, v, n)
+    R, E, X = run(dev, o, v, n, L, tau, w, P.Options(precision=P.SPLIT_BF16, n_slices=5, n_abatch=nA))
+    Rr, Er = oracle.forward(o, v, n, L, tau, w)
+    Xr = oracle.adjoint(o, v, n, L, tau, w)
+    assert err_norm(R, Rr) <= SPLIT_TOL_RX and err_rel(E, Er) <= SPLIT_TOL_E and err_norm(X, Xr) <= SPLIT_TOL_RX
+
+
+def test_split_general_flag(dev):
+    o, v, n = 3, 23, 40
+    L, tau, w = gaussian_inputs(17, o, v, n, symmetric=False)
+    opts = P.Options(precision=P.SPLIT_BF16, n_slices=5, flags=P.FLAG_GENERAL, n_abatch=6)
+    R, E, X = run(dev, o, v, n, L, tau, w, opts)
+    Rr, Er = oracle.forward(o, v, n, L, tau, w)
+    Xr = oracle.adjoint(o, v, n, L, tau, w)
+    assert err_norm(R, Rr) <= SPLIT_TOL_RX and err_rel(E, Er) <= SPLIT_TOL_E and err_norm(X, Xr) <= SPLIT_TOL_RX
+
+
+def test_split_deterministic_bitwise(dev):
+    o, v, n = 6, 45, 90
+    L, tau, w = gaussian_inputs(18, o, v, n)
+    a = run(dev, o, v, n, L, tau, w, P.Options(precision=P.SPLIT_BF16, n_abatch=7))
+    b = run(dev, o, v, n, L, tau, w, P.Options(precision=P.SPLIT_BF16, n_abatch=7))
+    assert np.array_equal(a[0], b[0]) and a[1] == b[1] and np.array_equal(a[2], b[2])
+
+
+def test_split_medium_error_versus_slices(dev):
+    """o=20, v=150, n=600: error of every output against the oracle for S = 2..6;
+    S = 5 (the default) must meet the targets, and more slices must not be worse."""
+    o, v, n = 20, 150, 600
+    L, tau, tbar, _, _ = oracle.make_inputs(o, v, n, 2)
+    Rr, Er = oracle.matrix.forward(o, v, n, L, tau, tbar)
+    Xr = oracle.matrix.adjoint(o, v, n, L, tau, tbar)
+    errs = {}
+    for S in (2, 3, 4, 5, 6):
+        R, E, X = run(dev, o, v, n, L, tau, tbar, P.Options(precision=P.SPLIT_BF16, n_slices=S))
+        errs[S] = (err_norm(R, Rr), err_rel(E, Er), err_norm(X, Xr))
+        print("split medium S=%d: err_R %.3e err_E %.3e err_X %.3e" % ((S,) + errs[S]))
+    eR, eE, eX = errs[5]
+    assert eR <= SPLIT_TOL_RX and eE <= SPLIT_TOL_E and eX <= SPLIT_TOL_RX
+    assert errs[6][0] <= 2 * errs[5][0] and errs[5][0] <= errs[3][0]
+
+
+def test_split_autograd(dev):
+    o, v, n = 3, 21, 25
+    L, tau, w = gaussian_inputs(19, o, v, n)
+    Lg = g(L, dev).requires_grad_(True)
+    E = P.ladder_energy(Lg, g(tau, dev), g(w, dev), (o, v, n), SPLIT5)
+    E.backward()
+    Rr, Er = oracle.forward(o, v, n, L, tau, w)
+    Xr = oracle.adjoint(o, v, n, L, tau, w)
+    assert err_rel(float(E.detach()), Er) <= SPLIT_TOL_E
+    assert err_norm(Lg.grad.cpu().numpy(), Xr) <= SPLIT_TOL_RX
