@@ -206,9 +206,10 @@ struct EpiStrided {
         if (weight) l.e += weight[m * ldc + n] * c;
         *p = beta == 0.0 ? alpha * c : alpha * c + beta * *p;
     }
+    // Needs every thread of the block (it has a barrier); any block size up to 1024.
     __device__ void finish(Local& l, int64_t w) const {
         if (!weight) return;
-        __shared__ double red[F64_THREADS / 64];
+        __shared__ double red[16];
         double e = l.e;
 #pragma unroll
         for (int off = 32; off > 0; off >>= 1) e += __shfl_xor(e, off);
@@ -216,7 +217,7 @@ struct EpiStrided {
         __syncthreads();
         if (threadIdx.x == 0) {
             double t = 0.0;
-            for (int i = 0; i < F64_THREADS / 64; ++i) t += red[i];
+            for (int i = 0; i < (int)(blockDim.x >> 6); ++i) t += red[i];
             partial[w] = t;
         }
     }
