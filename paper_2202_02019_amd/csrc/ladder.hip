@@ -378,13 +378,22 @@ const char* ladder_strerror(int code) {
 
 const char* ladder_last_error(void) { return g_last_error.c_str(); }
 
+// The split GEMM addresses a 128-row operand tile with 32-bit byte offsets.
+int check_split_dims(const Sizes& s, int64_t n, const ladder_options& op) {
+    if (op.precision != LADDER_SPLIT_BF16) return LADDER_OK;
+    const int64_t kmax = std::max(std::max(s.vv, s.oo), n);
+    if (split_kpad(kmax) * 2 * SPLIT_BM >= (int64_t(1) << 32))
+        return fail(LADDER_EUNSUPPORTED, "split precision needs v^2, o^2 and n below 2^24");
+    return LADDER_OK;
+}
+
 int ladder_workspace_size(int64_t o, int64_t v, int64_t n, const ladder_options* opts, size_t* bytes) {
     g_last_error.clear();
     if (!bytes) return fail(LADDER_EINVAL, "bytes is NULL");
     Sizes s;
     ladder_options op;
     int rc;
-    if ((rc = check_dims(o, v, n, s)) || (rc = get_opts(opts, op))) return rc;
+    if ((rc = check_dims(o, v, n, s)) || (rc = get_opts(opts, op)) || (rc = check_split_dims(s, n, op))) return rc;
     *bytes = make_plan(o, v, n, op, s).total;
     return LADDER_OK;
 }
@@ -396,7 +405,7 @@ int ladder_forward(int64_t o, int64_t v, int64_t n, const double* L, const doubl
     Sizes s;
     ladder_options op;
     int rc;
-    if ((rc = check_dims(o, v, n, s)) || (rc = get_opts(opts, op))) return rc;
+    if ((rc = check_dims(o, v, n, s)) || (rc = get_opts(opts, op)) || (rc = check_split_dims(s, n, op))) return rc;
     if (!L || !tau || !R || !ws) return fail(LADDER_EINVAL, "L, tau, R and ws must be non-NULL");
     if (E && !tbar) return fail(LADDER_EINVAL, "E requested but tbar is NULL");
     if (!aligned8(L) || !aligned8(tau) || !aligned8(R) || (tbar && !aligned8(tbar)) || (E && !aligned8(E)) ||
@@ -474,7 +483,7 @@ int ladder_adjoint(int64_t o, int64_t v, int64_t n, const double* L, const doubl
     Sizes s;
     ladder_options op;
     int rc;
-    if ((rc = check_dims(o, v, n, s)) || (rc = get_opts(opts, op))) return rc;
+    if ((rc = check_dims(o, v, n, s)) || (rc = get_opts(opts, op)) || (rc = check_split_dims(s, n, op))) return rc;
     if (!L || !tau || !wt || !X || !ws) return fail(LADDER_EINVAL, "L, tau, w, X and ws must be non-NULL");
     if (!aligned8(L) || !aligned8(tau) || !aligned8(wt) || !aligned8(X) || ((uintptr_t)ws % ALIGN))
         return fail(LADDER_EINVAL, "misaligned pointer (arrays need 8-byte, ws 256-byte alignment)");

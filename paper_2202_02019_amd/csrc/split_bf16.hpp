@@ -40,7 +40,6 @@ constexpr int SPLIT_KC = 256;       // chunk length along k
 constexpr int SPLIT_KALIGN = 16;    // k is padded with zeros to a multiple of this
 constexpr int SPLIT_MAX_S = 6;
 constexpr int SPLIT_BM = 128, SPLIT_BN = 128, SPLIT_BK = 16;
-constexpr int SPLIT_LDS_ROW = 24;   // bf16 per LDS row: 16 data + 8 pad (48 bytes, bank-spread)
 constexpr int SPLIT_THREADS = 512;
 
 __host__ __device__ inline int64_t split_kpad(int64_t K) { return (K + SPLIT_KALIGN - 1) / SPLIT_KALIGN * SPLIT_KALIGN; }
@@ -171,13 +170,66 @@ struct SplitShape {
 // 512 threads = 8 waves in a 4 x 2 grid; wave (wm, wn) owns rows wm*32 .. +32 and
 // columns wn*64 .. +64 of the 128 x 128 tile (two 32x32 MFMA blocks), so two
 // waves share each SIMD and one's MFMAs overlap the other's FP64 combine.
+//
+// Operand tiles go from global memory straight into LDS (global_load_lds_dwordx4,
+// no VGPR staging) through a 3-deep ring of K-steps, so two K-steps of loads are
+// in flight while the third is multiplied.  An LDS slice tile is 128 rows x 16 k
+// of BF16 = 256 slots of 16 bytes; row r, k-half h lives in slot
+// 2r + (h ^ f(r)) with f(r) = bit2(r) ^ bit3(r), which keeps both the DMA writes
+// (one 1 KB run per wave instruction) and the MFMA fragment reads (8 or 16
+// consecutive rows per LDS cycle) free of bank conflicts.
+constexpr int SPLIT_STAGES = 3;
+constexpr int SPLIT_TILE_SLOTS = 256;  // 16-byte slots per slice tile (4 KB)
+
+__device__ inline int split_slot(int r, int h) { return 2 * r + (h ^ (((r >> 2) ^ (r >> 3)) & 1)); }
+
+typedef __attribute__((address_space(3))) void* lds_ptr_t;
+
+// Global memory -> LDS without VGPR staging (global_load_lds): lane i's bytes
+// land at lds_base + size*i; the global address is the wave-uniform `base`
+// (SGPRs) plus the lane's 32-bit byte offset.  Written as inline assembly on
+// purpose: the compiler treats its own LDS-DMA builtin as aliasing every later
+// LDS read and would wait for the just-issued loads before each fragment read,
+// which serialises the ring.  Ordering is explicit instead: a buffer is read
+// only after s_waitcnt vmcnt and s_barrier, and the statement clobbers memory
+// so that no LDS access moves across it.  It has no register outputs; M0 is
+// written here and used by nothing else in the kernel.
+__device__ inline void lds_dma16(const void* base, unsigned voff, unsigned lds_base) {
+    asm volatile("s_mov_b32 m0, %0\n\ts_nop 0\n\tglobal_load_lds_dwordx4 %1, %2" ::"s"(lds_base), "v"(voff), "s"(base)
+                 : "memory");
+}
+__device__ inline void lds_dma4(const void* base, unsigned voff, unsigned lds_base) {
+    asm volatile("s_mov_b32 m0, %0\n\ts_nop 0\n\tglobal_load_lds_dword %1, %2" ::"s"(lds_base), "v"(voff), "s"(base)
+                 : "memory");
+}
+__device__ inline const void* uniform_ptr(const void* p) {
+    const uint64_t x = (uint64_t)(uintptr_t)p;
+    const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)x);
+    const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)(x >> 32));
+    return (const void*)(uintptr_t)(((uint64_t)hi << 32) | lo);
+}
+__device__ inline unsigned lds_addr(const void* p) {
+    return __builtin_amdgcn_readfirstlane((unsigned)(uintptr_t)(lds_ptr_t)p);
+}
+
+// The three ring buffers are distinct LDS variables and the K loop is unrolled
+// by three, so every access names its buffer statically; the compiler can then
+// tell the in-flight DMA of one buffer from the fragment reads of another and
+// waits only where a buffer is reused.
+template <int S>
+struct SplitRing {
+    unsigned short t[2][S][SPLIT_TILE_SLOTS * 8];  // [operand A=0/B=1][slice][slots]
+};
+
 template <int S, class Epi>
 __global__ __launch_bounds__(SPLIT_THREADS) void gemm_split_kernel(SplitShape sh, Epi epi) {
-    __shared__ unsigned short As[2][S][SPLIT_BM * SPLIT_LDS_ROW];
-    __shared__ unsigned short Bs[2][S][SPLIT_BN * SPLIT_LDS_ROW];
+    __shared__ __attribute__((aligned(16))) SplitRing<S> ring0, ring1, ring2;
+    // chunk exponents, double-buffered by chunk parity: [parity][A=0/B=1][128 rows]
+    __shared__ __attribute__((aligned(16))) int lexp[2][2][SPLIT_BM];
 
     const int tid = threadIdx.x;
-    const int lane = tid & 63, wave = tid >> 6;
+    const int lane = tid & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);  // wave-uniform: keeps the roles in SGPRs
     const int wm = wave >> 1, wn = wave & 1;
     TileMap tmap{(sh.M + SPLIT_BM - 1) / SPLIT_BM, (sh.N + SPLIT_BN - 1) / SPLIT_BN};
     int64_t ti, tj;
@@ -185,28 +237,35 @@ __global__ __launch_bounds__(SPLIT_THREADS) void gemm_split_kernel(SplitShape sh
     const int64_t m0 = ti * SPLIT_BM, n0 = tj * SPLIT_BN;
     const int64_t Kp = split_kpad(sh.K);
     const int64_t nk = Kp / SPLIT_BK;
+    constexpr int STEPS_PER_CHUNK = SPLIT_KC / SPLIT_BK;
 
-    // global -> LDS: threads 0..255 move A, 256..511 move B; 16 bytes (8 k) of
-    // row (t%256)/2, half t%2, for every slice.
-    const bool is_b = tid >= 256;
-    const int lrow = (tid & 255) >> 1, lhalf = tid & 1;
-    const SplitOperand& op = is_b ? sh.b : sh.a;
-    const bool in = (is_b ? n0 : m0) + lrow < (is_b ? sh.N : sh.M);
-    const unsigned short* gsrc = op.s + ((is_b ? n0 : m0) + lrow) * op.ld + 8 * lhalf;
-    const int64_t gstride = op.slice_stride;
-    unsigned short* ldst0 = is_b ? &Bs[0][0][0] : &As[0][0][0];
-    constexpr int LDS_SLICE = SPLIT_BM * SPLIT_LDS_ROW;
-    const int lds_w = lrow * SPLIT_LDS_ROW + 8 * lhalf;
+    // DMA role: waves 0-3 load A, 4-7 load B; wave w%4 covers slots 64*(w%4) .. +64
+    // (rows 32*(w%4) .. +32) of every slice.  Lane i fills slot 64*(w%4) + i.
+    // Waves with w%4 < 2 also load the chunk exponents of rows 64*(w%4) .. +64.
+    const int dop = wave >> 2, dq = wave & 3;
+    const SplitOperand& op = dop ? sh.b : sh.a;
+    const int64_t row0 = dop ? n0 : m0;
+    const int64_t last = (dop ? sh.N : sh.M) - 1 - row0;  // last valid row of this tile, >= 0
+    const int slot = 64 * dq + lane;
+    const int drow = slot >> 1;
+    const int dhalf = (slot & 1) ^ (((drow >> 2) ^ (drow >> 3)) & 1);
+    // rows past the edge load a valid row; their results are never stored
+    const unsigned dvoff = (unsigned)(((drow < last ? drow : last) * op.ld + 8 * dhalf) * 2);
+    const unsigned short* dbase = (const unsigned short*)uniform_ptr(op.s + row0 * op.ld);
+    const int64_t dstride = op.slice_stride;
+    const int64_t e_ld = op.e_ld;
+    const int erow = 64 * dq + lane;
+    const unsigned evoff = (unsigned)((erow < last ? erow : last) * 4);
+    const int* ebase = (const int*)uniform_ptr(op.e + row0);
 
-    ux8 rg[S];
-    auto gload = [&](int64_t kt) {
+    auto dma = [&](SplitRing<S>& rg, int64_t kt) {
 #pragma unroll
         for (int p = 0; p < S; ++p)
-            rg[p] = in ? *(const ux8*)(gsrc + p * gstride + kt * SPLIT_BK) : ux8{0, 0, 0, 0, 0, 0, 0, 0};
-    };
-    auto lstore = [&](int buf) {
-#pragma unroll
-        for (int p = 0; p < S; ++p) *(ux8*)(ldst0 + (buf * S + p) * LDS_SLICE + lds_w) = rg[p];
+            lds_dma16(uniform_ptr(dbase + p * dstride + kt * SPLIT_BK), dvoff, lds_addr(&rg.t[dop][p][64 * dq * 8]));
+        if (dq < 2 && kt % STEPS_PER_CHUNK == 0) {
+            const int64_t ch = kt / STEPS_PER_CHUNK;
+            lds_dma4(uniform_ptr(ebase + ch * e_ld), evoff, lds_addr(&lexp[ch & 1][dop][64 * dq]));
+        }
     };
 
     fx16 acc[3][2];
@@ -219,28 +278,30 @@ __global__ __launch_bounds__(SPLIT_THREADS) void gemm_split_kernel(SplitShape sh
         for (int r = 0; r < 16; ++r) acc64[bj][r] = 0.0;
     }
 
-    // MFMA fragment read offsets: row l%32 of the 32-row block, k half l/32.
-    const int frag = (lane & 31) * SPLIT_LDS_ROW + 8 * (lane >> 5);
-    const int arow = (wm * 32) * SPLIT_LDS_ROW + frag;
-    const int brow0 = (wn * 64) * SPLIT_LDS_ROW + frag;
-    const int brow1 = (wn * 64 + 32) * SPLIT_LDS_ROW + frag;
+    // Fragment reads: row (block base + l%32), k-half l/32.
+    const int fr = lane & 31, fh = lane >> 5;
+    const int a_off = split_slot(wm * 32 + fr, fh) * 8;
+    const int b_off0 = split_slot(wn * 64 + fr, fh) * 8;
+    const int b_off1 = split_slot(wn * 64 + 32 + fr, fh) * 8;
 
-    gload(0);
-    lstore(0);
-    __syncthreads();
-    for (int64_t kt = 0; kt < nk; ++kt) {
-        const int cur = (int)(kt & 1);
-        if (kt + 1 < nk) gload(kt + 1);
+    // One K-step on ring buffer `cur`, while step kt+2 is loaded into `nxt`.
+    auto step = [&](SplitRing<S>& cur, SplitRing<S>& nxt, int64_t kt) {
+        if (kt + 1 < nk)  // this wave's step-kt loads are done once at most S (step kt+1) remain
+            __builtin_amdgcn_s_waitcnt((S & 0xF) | ((S >> 4) << 14) | (0x7 << 4) | (0xF << 8));
+        else
+            __builtin_amdgcn_s_waitcnt((0x7 << 4) | (0xF << 8));
+        __builtin_amdgcn_s_barrier();  // every wave's step-kt loads landed; step kt-1 reads are finished
+        if (kt + 2 < nk) dma(nxt, kt + 2);
 
         bx8 bq[S][2];
 #pragma unroll
         for (int q = 0; q < S; ++q) {
-            bq[q][0] = __builtin_bit_cast(bx8, *(const ux8*)(&Bs[cur][q][brow0]));
-            bq[q][1] = __builtin_bit_cast(bx8, *(const ux8*)(&Bs[cur][q][brow1]));
+            bq[q][0] = __builtin_bit_cast(bx8, *(const ux8*)(&cur.t[1][q][b_off0]));
+            bq[q][1] = __builtin_bit_cast(bx8, *(const ux8*)(&cur.t[1][q][b_off1]));
         }
 #pragma unroll
         for (int p = 0; p < S; ++p) {
-            const bx8 ap = __builtin_bit_cast(bx8, *(const ux8*)(&As[cur][p][arow]));
+            const bx8 ap = __builtin_bit_cast(bx8, *(const ux8*)(&cur.t[0][p][a_off]));
 #pragma unroll
             for (int q = 0; q < S - p; ++q) {
                 const int g = (p + q) < 2 ? (p + q) : 2;
@@ -250,25 +311,21 @@ __global__ __launch_bounds__(SPLIT_THREADS) void gemm_split_kernel(SplitShape sh
             }
         }
 
-        // end of a chunk (or of k): fold the exact FP32 chunk sums into FP64
-        if (((kt + 1) % (SPLIT_KC / SPLIT_BK)) == 0 || kt + 1 == nk) {
-            const int64_t ch = kt / (SPLIT_KC / SPLIT_BK);
-            const int* ea_row = sh.a.e + ch * sh.a.e_ld;
-            const int* eb_row = sh.b.e + ch * sh.b.e_ld;
-            int eb[2];
+        if (((kt + 1) % STEPS_PER_CHUNK) == 0 || kt + 1 == nk) {  // fold the exact FP32 chunk sums into FP64
+            const int par = (int)((kt / STEPS_PER_CHUNK) & 1);
+            const int eb0 = lexp[par][1][wn * 64 + (lane & 31)];
+            const int eb1 = lexp[par][1][wn * 64 + 32 + (lane & 31)];
 #pragma unroll
-            for (int bj = 0; bj < 2; ++bj) {
-                const int64_t n = n0 + wn * 64 + 32 * bj + (lane & 31);
-                eb[bj] = n < sh.N ? eb_row[n] : 0;
-            }
+            for (int r4 = 0; r4 < 4; ++r4) {
+                const int4 ea4 = *(const int4*)(&lexp[par][0][wm * 32 + 8 * r4 + 4 * (lane >> 5)]);
+                const int ea[4] = {ea4.x, ea4.y, ea4.z, ea4.w};
 #pragma unroll
-            for (int r = 0; r < 16; ++r) {
-                const int64_t m = m0 + wm * 32 + 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);
-                const int ea = m < sh.M ? ea_row[m] : 0;
-#pragma unroll
-                for (int bj = 0; bj < 2; ++bj) {
-                    const double t = ((double)acc[0][bj][r] + (double)acc[1][bj][r]) + (double)acc[2][bj][r];
-                    acc64[bj][r] += ldexp(t, ea + eb[bj]);
+                for (int r1 = 0; r1 < 4; ++r1) {
+                    const int r = 4 * r4 + r1;
+                    const double t0 = ((double)acc[0][0][r] + (double)acc[1][0][r]) + (double)acc[2][0][r];
+                    const double t1 = ((double)acc[0][1][r] + (double)acc[1][1][r]) + (double)acc[2][1][r];
+                    acc64[0][r] += ldexp(t0, ea[r1] + eb0);
+                    acc64[1][r] += ldexp(t1, ea[r1] + eb1);
                 }
             }
 #pragma unroll
@@ -276,9 +333,14 @@ __global__ __launch_bounds__(SPLIT_THREADS) void gemm_split_kernel(SplitShape sh
 #pragma unroll
                 for (int bj = 0; bj < 2; ++bj) acc[g][bj] = fx16{};
         }
+    };
 
-        if (kt + 1 < nk) lstore(cur ^ 1);
-        __syncthreads();
+    dma(ring0, 0);
+    if (nk > 1) dma(ring1, 1);
+    for (int64_t kt = 0; kt < nk; kt += 3) {
+        step(ring0, ring2, kt);
+        if (kt + 1 < nk) step(ring1, ring0, kt + 1);
+        if (kt + 2 < nk) step(ring2, ring1, kt + 2);
     }
 
     // D layout of v_mfma_f32_32x32x16_bf16 (measured on gfx950): lane l, element r
