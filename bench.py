@@ -28,6 +28,7 @@ WORKLOADS = {
     "medium": (20, 150, 600, 2),
     "retinal": (78, 657, 2200, 3),
     "autograd": (40, 350, 1200, 5),
+    "batched": (None, None, None, 4),
 }
 PEAK = {"fp64": 78.6, "bf16": 2516.6}  # dense MFMA TFLOP/s, MI355X
 
@@ -43,10 +44,14 @@ def main():
     ap.add_argument("--warmup", type=int, default=None)
     ap.add_argument("--workload", default="retinal", choices=sorted(WORKLOADS))
     ap.add_argument("--shape", default=None, help="o,v,n override (probe shapes)")
-    ap.add_argument("--precision", default="fp64", choices=["fp64", "split"])
+    ap.add_argument("--precision", default="split", choices=["fp64", "split"])
     ap.add_argument("--slices", type=int, default=0)
     ap.add_argument("--n-abatch", type=int, default=0)
     ap.add_argument("--cpu-rows", type=int, default=1, help="a (and p) rows the CPU baseline computes; 0 = skip")
+    ap.add_argument("--no-compare", action="store_true",
+                    help="skip the untimed FP64 leg that the split path is compared with")
+    ap.add_argument("--copy-probe", action="store_true",
+                    help="run a 1 GiB device copy first (reference kernel for the HBM traffic counters)")
     args = ap.parse_args()
 
     if args.gpus != 1:
@@ -60,17 +65,28 @@ def main():
     import paper_2202_02019_amd as P
     from synthetic import gpu as SG
 
+    if args.workload == "batched":
+        return run_batched(args)
     o, v, n, seed = WORKLOADS[args.workload]
     name = args.workload
     if args.shape:
         o, v, n = (int(x) for x in args.shape.split(","))
         name = "probe"
+    if args.n_abatch == 0 and name == "retinal":
+        args.n_abatch = 8 if args.precision == "split" else 16  # a few large virtual batches fit in 288 GB
     big = nominal_flops(o, v, n) > 1e14
+    huge = nominal_flops(o, v, n) > 1e15  # a single step takes minutes: no warm-up by default
     steps = args.steps if args.steps is not None else (1 if big else 10)
-    warmup = args.warmup if args.warmup is not None else (1 if big else 2)
+    warmup = args.warmup if args.warmup is not None else (0 if huge else (1 if big else 2))
 
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
+    if args.copy_probe:
+        src = torch.ones(1 << 27, dtype=torch.float64, device=dev)  # 1 GiB
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
     t0 = time.time()
     L = SG.draw_L_vv(seed, o, v, n)
     Lov = SG.draw_L_ov(seed, o, v, n)
@@ -132,6 +148,30 @@ def main():
                          "tflops": (s["flops"] / (s["total_ms"] * 1e-3) / 1e12) if s["total_ms"] > 0 else None}
                      for k, s in stages.items()}
 
+    compare = None
+    if args.precision == "split" and not args.no_compare:
+        # the same step on the FP64 MFMA path, untimed for `value`
+        o64 = P.Options(precision=P.FP64, n_abatch=16 if name == "retinal" else 0)
+        ws64 = torch.empty(P.workspace_size(o, v, n, o64), dtype=torch.uint8, device=dev) if \
+            P.workspace_size(o, v, n, o64) > ws.numel() else ws
+        R64 = torch.empty_like(R)
+        E64 = torch.empty((), dtype=torch.float64, device=dev)
+        X64 = torch.empty_like(X)
+        torch.cuda.synchronize()
+        ev0.record(stream)
+        P.forward(L, tau, tbar, o=o, v=v, n=n, R=R64, E=E64, ws=ws64, opts=o64)
+        P.adjoint(L, tau, tbar, o=o, v=v, n=n, X=X64, ws=ws64, opts=o64)
+        ev1.record(stream)
+        torch.cuda.synchronize()
+        ms64 = ev0.elapsed_time(ev1)
+        e64 = float(E64.cpu())
+        compare = {"fp64_ms_per_step": ms64, "fp64_tflops": F / (ms64 * 1e-3) / 1e12, "speedup_vs_fp64": ms64 / ms,
+                   "err_E_vs_fp64": abs(float(E.cpu()) - e64) / abs(e64),
+                   "err_R_vs_fp64": float((R - R64).abs().max() / R64.abs().max()),
+                   "err_X_vs_fp64": float((X - X64).abs().max() / X64.abs().max())}
+        del R64, X64, ws64
+        print("bench: fp64 comparison step %.1f s" % (ms64 / 1e3), file=sys.stderr, flush=True)
+
     cpu = None
     errs = {}
     if args.cpu_rows > 0:
@@ -165,8 +205,76 @@ def main():
         "energy": float(E.cpu()),
         "roofline": roofline, "stages": stage_summary, "cpu_baseline": cpu,
         "frac_fp64_peak": value / PEAK["fp64"],
+        "fp64_comparison": compare,
     }
     out.update(errs)
+    print(json.dumps(out))
+
+
+def run_batched(args):
+    """64 ragged instances: one graph launch of ladder_batched vs 64 sequential calls."""
+    import torch
+
+    import paper_2202_02019_amd as P
+    import synthetic
+    from synthetic import gpu as SG
+
+    sizes = synthetic.batched_sizes(4, 64)
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    prec = P.FP64 if args.precision == "fp64" else P.SPLIT_BF16
+    opts = P.Options(precision=prec, n_slices=args.slices, n_abatch=args.n_abatch)
+    insts = []
+    t0 = time.time()
+    for m, (o, v, n) in enumerate(sizes):
+        seed = 1000 + m
+        L = SG.draw_L_vv(seed, o, v, n)
+        Lov = SG.draw_L_ov(seed, o, v, n)
+        eps = SG.draw_eps(seed, o, v)
+        tau = P.mp2_amplitudes(Lov, eps, o=o, v=v, n=n)
+        del Lov
+        tbar = SG.add_noise(seed, o, v, tau)
+        insts.append(dict(o=o, v=v, n=n, L=L, tau=tau, tbar=tbar, R=torch.empty_like(tau),
+                          E=torch.empty((), dtype=torch.float64, device=dev), X=torch.empty_like(L)))
+    what = P.DO_FORWARD | P.DO_ADJOINT
+    ws = torch.empty(P.batched_workspace_size(insts, what, opts), dtype=torch.uint8, device=dev)
+    F = sum(nominal_flops(o, v, n) for o, v, n in sizes)
+    torch.cuda.synchronize()
+    print("bench: batched 64 instances, F=%.3e, inputs ready in %.1fs, workspace %.2f GiB"
+          % (F, time.time() - t0, ws.numel() / 2 ** 30), file=sys.stderr, flush=True)
+    steps = args.steps if args.steps is not None else 2
+    warmup = args.warmup if args.warmup is not None else 1
+    stream = torch.cuda.current_stream()
+    for _ in range(warmup):  # the first call captures the graph
+        P.batched(insts, what, ws=ws, opts=opts)
+    torch.cuda.synchronize()
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    ev0.record(stream)
+    for _ in range(steps):
+        P.batched(insts, what, ws=ws, opts=opts)
+    ev1.record(stream)
+    torch.cuda.synchronize()
+    ms = ev0.elapsed_time(ev1) / steps
+    print("bench: graph %.1f ms per batch" % ms, file=sys.stderr, flush=True)
+    # the same work as 64 sequential forward + adjoint calls on one stream
+    wsq = ws[: max(P.workspace_size(d["o"], d["v"], d["n"], opts) for d in insts)]
+    ev0.record(stream)
+    for d in insts:
+        P.forward(d["L"], d["tau"], d["tbar"], o=d["o"], v=d["v"], n=d["n"], R=d["R"], E=d["E"], ws=wsq, opts=opts)
+        P.adjoint(d["L"], d["tau"], d["tbar"], o=d["o"], v=d["v"], n=d["n"], X=d["X"], ws=wsq, opts=opts)
+    ev1.record(stream)
+    torch.cuda.synchronize()
+    ms_seq = ev0.elapsed_time(ev1)
+    out = {
+        "metric": "ladder fwd+adjoint TFLOP/s & s/iter, split-BF16 vs FP64 at <=1e-10 rel err in E",
+        "value": F / (ms * 1e-3) / 1e12, "unit": "TFLOP/s", "n_gpus": 1, "steps": steps, "warmup": warmup,
+        "ms_per_step": ms, "s_per_iter": ms / 1e3, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f64" if args.precision == "fp64" else "bf16-split/f64", "data": "synthetic",
+        "config": {"workload": "batched", "instances": 64, "sizes_seed": 4, "data_seeds": "1000+m",
+                   "precision": args.precision, "n_abatch": args.n_abatch, "nominal_flops": F},
+        "sequential_ms": ms_seq, "sequential_tflops": F / (ms_seq * 1e-3) / 1e12, "graph_speedup": ms_seq / ms,
+        "roofline": None, "cpu_baseline": None,
+    }
     print(json.dumps(out))
 
 

@@ -70,6 +70,7 @@ struct StageRec {
 std::mutex g_prof_mu;
 bool g_prof_on = false;
 std::vector<StageRec> g_prof;
+thread_local bool g_capturing = false;  // no timing events inside a graph capture
 
 // Brackets one launch with events on its stream when profiling is on.
 struct StageTimer {
@@ -78,7 +79,7 @@ struct StageTimer {
     hipStream_t st;
     StageTimer(int stage, double flops, double bytes, hipStream_t s) : st(s) {
         std::lock_guard<std::mutex> lk(g_prof_mu);
-        if (!g_prof_on) return;
+        if (!g_prof_on || g_capturing) return;
         rec.stage = stage;
         rec.flops = flops;
         rec.bytes = bytes;
@@ -355,6 +356,97 @@ unsigned grid_for(int64_t total) {
     return (unsigned)g;
 }
 
+// The split GEMM addresses a 128-row operand tile with 32-bit byte offsets.
+int check_split_dims(const Sizes& s, int64_t n, const ladder_options& op) {
+    if (op.precision != LADDER_SPLIT_BF16) return LADDER_OK;
+    const int64_t kmax = std::max(std::max(s.vv, s.oo), n);
+    if (split_kpad(kmax) * 2 * SPLIT_BM >= (int64_t(1) << 32))
+        return fail(LADDER_EUNSUPPORTED, "split precision needs v^2, o^2 and n below 2^24");
+    return LADDER_OK;
+}
+
+// ------------------------------------------------------------ ragged batches
+// ladder_batched runs every instance's forward and/or adjoint as parallel
+// branches of one hipGraph: instance i goes to branch i % branches, each branch
+// owns one workspace slot and runs its instances in order, so up to `branches`
+// instances share the GPU at a time.  The graph is captured on the first call
+// with a given set of shapes, pointers and options and replayed afterwards.
+constexpr int BATCH_BRANCHES = 8;
+constexpr size_t BATCH_TILE_BYTES = size_t(1) << 30;  // default g/D tile per instance
+constexpr size_t MAX_GRAPHS = 8;
+
+struct BatchPlan {
+    ladder_options op;
+    std::vector<ladder_options> inst_opts;
+    size_t slot = 0, total = 0;
+    int branches = 0;
+};
+
+int batch_plan(int count, const ladder_instance* inst, uint32_t what, const ladder_options* opts, BatchPlan& bp) {
+    int rc;
+    if (count < 1 || !inst) return fail(LADDER_EINVAL, "count must be >= 1 and inst non-NULL");
+    if (what == 0 || (what & ~(LADDER_DO_FORWARD | LADDER_DO_ADJOINT)))
+        return fail(LADDER_EINVAL, "what must be a non-empty combination of LADDER_DO_FORWARD and LADDER_DO_ADJOINT");
+    if ((rc = get_opts(opts, bp.op))) return rc;
+    bp.inst_opts.resize(count);
+    for (int i = 0; i < count; ++i) {
+        const ladder_instance& x = inst[i];
+        Sizes s;
+        if ((rc = check_dims(x.o, x.v, x.n, s)) || (rc = check_split_dims(s, x.n, bp.op))) {
+            g_last_error = "instance " + std::to_string(i) + ": " + g_last_error;
+            return rc;
+        }
+        if (!x.L || !x.tau) return fail(LADDER_EINVAL, "instance %d: L and tau must be non-NULL", i);
+        if ((what & LADDER_DO_FORWARD) && !x.R) return fail(LADDER_EINVAL, "instance %d: R is NULL", i);
+        if ((what & LADDER_DO_ADJOINT) && (!x.X || !x.tbar)) return fail(LADDER_EINVAL, "instance %d: X and tbar are needed", i);
+        if (x.E && !x.tbar) return fail(LADDER_EINVAL, "instance %d: E requested but tbar is NULL", i);
+        ladder_options oi = bp.op;
+        if (oi.n_abatch == 0) {
+            int64_t per_a = s.vvv * 8;
+            if (oi.precision == LADDER_SPLIT_BF16) per_a += (int64_t)(slice_bytes(oi.n_slices, x.v, s.vv) + exp_bytes(x.v, s.vv));
+            oi.n_abatch = std::max<int64_t>(1, std::min<int64_t>((int64_t)(BATCH_TILE_BYTES / (size_t)per_a), (x.v + 1) / 2));
+        }
+        bp.inst_opts[i] = oi;
+        const Plan p = make_plan(x.o, x.v, x.n, oi, s);
+        bp.slot = std::max(bp.slot, align_up(p.total));
+    }
+    bp.branches = std::min(count, BATCH_BRANCHES);
+    bp.total = bp.slot * (size_t)bp.branches;
+    return LADDER_OK;
+}
+
+struct DeviceStreams {
+    bool ready = false;
+    hipStream_t cap = nullptr;
+    hipStream_t branch[BATCH_BRANCHES] = {};
+    hipEvent_t fork = nullptr;
+    hipEvent_t join[BATCH_BRANCHES] = {};
+};
+struct GraphEntry {
+    std::vector<int64_t> key;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+};
+std::mutex g_graph_mu;
+std::vector<GraphEntry> g_graphs;
+DeviceStreams g_streams[64];
+
+// Library-owned streams (default priority) and events used only for capture.
+int ensure_branch_streams(int dev) {
+    if (dev < 0 || dev >= 64) return fail(LADDER_EUNSUPPORTED, "device index %d", dev);
+    DeviceStreams& ds = g_streams[dev];
+    if (ds.ready) return LADDER_OK;
+    int rc;
+    if ((rc = hip_check(hipStreamCreateWithFlags(&ds.cap, hipStreamNonBlocking), "stream create"))) return rc;
+    if ((rc = hip_check(hipEventCreateWithFlags(&ds.fork, hipEventDisableTiming), "event create"))) return rc;
+    for (int b = 0; b < BATCH_BRANCHES; ++b) {
+        if ((rc = hip_check(hipStreamCreateWithFlags(&ds.branch[b], hipStreamNonBlocking), "stream create"))) return rc;
+        if ((rc = hip_check(hipEventCreateWithFlags(&ds.join[b], hipEventDisableTiming), "event create"))) return rc;
+    }
+    ds.ready = true;
+    return LADDER_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -377,15 +469,6 @@ const char* ladder_strerror(int code) {
 }
 
 const char* ladder_last_error(void) { return g_last_error.c_str(); }
-
-// The split GEMM addresses a 128-row operand tile with 32-bit byte offsets.
-int check_split_dims(const Sizes& s, int64_t n, const ladder_options& op) {
-    if (op.precision != LADDER_SPLIT_BF16) return LADDER_OK;
-    const int64_t kmax = std::max(std::max(s.vv, s.oo), n);
-    if (split_kpad(kmax) * 2 * SPLIT_BM >= (int64_t(1) << 32))
-        return fail(LADDER_EUNSUPPORTED, "split precision needs v^2, o^2 and n below 2^24");
-    return LADDER_OK;
-}
 
 int ladder_workspace_size(int64_t o, int64_t v, int64_t n, const ladder_options* opts, size_t* bytes) {
     g_last_error.clear();
@@ -589,14 +672,91 @@ int ladder_amplitude_update(int64_t o, int64_t v, const double* eps, const doubl
 
 int ladder_batched_workspace_size(int count, const ladder_instance* inst, uint32_t what, const ladder_options* opts,
                                   size_t* bytes) {
-    (void)count; (void)inst; (void)what; (void)opts; (void)bytes;
-    return fail(LADDER_EUNSUPPORTED, "ladder_batched is not built into this library yet");
+    g_last_error.clear();
+    if (!bytes) return fail(LADDER_EINVAL, "bytes is NULL");
+    BatchPlan bp;
+    int rc = batch_plan(count, inst, what, opts, bp);
+    if (rc) return rc;
+    *bytes = bp.total;
+    return LADDER_OK;
 }
 
 int ladder_batched(int count, const ladder_instance* inst, uint32_t what, void* ws, size_t ws_bytes,
                    const ladder_options* opts, void* stream) {
-    (void)count; (void)inst; (void)what; (void)ws; (void)ws_bytes; (void)opts; (void)stream;
-    return fail(LADDER_EUNSUPPORTED, "ladder_batched is not built into this library yet");
+    g_last_error.clear();
+    BatchPlan bp;
+    int rc = batch_plan(count, inst, what, opts, bp);
+    if (rc) return rc;
+    if (!ws || ((uintptr_t)ws % ALIGN)) return fail(LADDER_EINVAL, "ws must be non-NULL and 256-byte aligned");
+    if (ws_bytes < bp.total) return fail(LADDER_EWORKSPACE, "workspace of %zu bytes, %zu needed", ws_bytes, bp.total);
+
+    // Cache key: everything the captured launches depend on.
+    std::vector<int64_t> key = {count, (int64_t)what, (int64_t)(uintptr_t)ws, (int64_t)ws_bytes, bp.op.precision,
+                                bp.op.n_slices, bp.op.n_abatch, (int64_t)bp.op.flags};
+    for (int i = 0; i < count; ++i) {
+        const ladder_instance& x = inst[i];
+        for (int64_t f : {x.o, x.v, x.n, (int64_t)(uintptr_t)x.L, (int64_t)(uintptr_t)x.tau, (int64_t)(uintptr_t)x.tbar,
+                          (int64_t)(uintptr_t)x.R, (int64_t)(uintptr_t)x.E, (int64_t)(uintptr_t)x.X})
+            key.push_back(f);
+    }
+    std::lock_guard<std::mutex> lk(g_graph_mu);
+    int dev = 0;
+    if ((rc = hip_check(hipGetDevice(&dev), "hipGetDevice"))) return rc;
+    key.push_back(dev);
+    GraphEntry* hit = nullptr;
+    for (auto& e : g_graphs)
+        if (e.key == key) hit = &e;
+    if (!hit) {
+        if ((rc = ensure_branch_streams(dev))) return rc;
+        DeviceStreams& ds = g_streams[dev];
+        GraphEntry e;
+        e.key = key;
+        hipStream_t cap = ds.cap;
+        if ((rc = hip_check(hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal), "graph capture begin"))) return rc;
+        g_capturing = true;
+        int brc = hip_check(hipEventRecord(ds.fork, cap), "fork event");
+        for (int b = 0; b < bp.branches && !brc; ++b) brc = hip_check(hipStreamWaitEvent(ds.branch[b], ds.fork, 0), "fork wait");
+        for (int i = 0; i < count && !brc; ++i) {
+            const ladder_instance& x = inst[i];
+            const int b = i % bp.branches;
+            char* slot = (char*)ws + (size_t)b * bp.slot;
+            if (what & LADDER_DO_FORWARD)
+                brc = ladder_forward(x.o, x.v, x.n, x.L, x.tau, x.tbar, 0.0, x.R, x.E, slot, bp.slot, &bp.inst_opts[i],
+                                     ds.branch[b]);
+            if (!brc && (what & LADDER_DO_ADJOINT))
+                brc = ladder_adjoint(x.o, x.v, x.n, x.L, x.tau, x.tbar, 1.0, 0.0, x.X, slot, bp.slot, &bp.inst_opts[i],
+                                     ds.branch[b]);
+        }
+        for (int b = 0; b < bp.branches && !brc; ++b) {
+            brc = hip_check(hipEventRecord(ds.join[b], ds.branch[b]), "join event");
+            if (!brc) brc = hip_check(hipStreamWaitEvent(cap, ds.join[b], 0), "join wait");
+        }
+        g_capturing = false;
+        const std::string err = g_last_error;
+        hipGraph_t graph = nullptr;
+        const hipError_t ec = hipStreamEndCapture(cap, &graph);
+        if (brc) {
+            if (graph) (void)hipGraphDestroy(graph);
+            g_last_error = "while capturing the batch: " + err;
+            return brc;
+        }
+        if ((rc = hip_check(ec, "graph capture end"))) return rc;
+        hipGraphExec_t exec = nullptr;
+        if ((rc = hip_check(hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0), "graph instantiate"))) {
+            (void)hipGraphDestroy(graph);
+            return rc;
+        }
+        e.graph = graph;
+        e.exec = exec;
+        if (g_graphs.size() >= MAX_GRAPHS) {
+            (void)hipGraphExecDestroy(g_graphs.front().exec);
+            (void)hipGraphDestroy(g_graphs.front().graph);
+            g_graphs.erase(g_graphs.begin());
+        }
+        g_graphs.push_back(e);
+        hit = &g_graphs.back();
+    }
+    return hip_check(hipGraphLaunch(hit->exec, (hipStream_t)stream), "graph launch");
 }
 
 int ladder_profile_start(void) {
@@ -641,6 +801,24 @@ int ladder_profile_stop(ladder_stage_stats* out, int max_stages, int* n_out) {
 }
 
 void ladder_shutdown(void) {
+    {
+        std::lock_guard<std::mutex> gl(g_graph_mu);
+        for (auto& e : g_graphs) {
+            (void)hipGraphExecDestroy(e.exec);
+            (void)hipGraphDestroy(e.graph);
+        }
+        g_graphs.clear();
+        for (auto& ds : g_streams) {
+            if (!ds.ready) continue;
+            (void)hipStreamDestroy(ds.cap);
+            (void)hipEventDestroy(ds.fork);
+            for (int b = 0; b < BATCH_BRANCHES; ++b) {
+                (void)hipStreamDestroy(ds.branch[b]);
+                (void)hipEventDestroy(ds.join[b]);
+            }
+            ds = DeviceStreams{};
+        }
+    }
     std::lock_guard<std::mutex> lk(g_prof_mu);
     for (auto& r : g_prof) {
         (void)hipEventDestroy(r.a);

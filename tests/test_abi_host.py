@@ -112,3 +112,19 @@ def test_workspace_never_holds_full_v4(o, v, n):
         assert ws < 8 * v ** 4
     ws1 = P.workspace_size(o, v, n, P.Options(n_abatch=1))
     assert ws1 < 8 * v ** 3 + (1 << 24) + 8 * o * o * v * v
+
+
+def test_batched_validation():
+    lib = _lib()
+    arr = (B._CInstance * 2)()
+    arr[0] = B._CInstance(2, 3, 4, FAKE, 2 * FAKE, 3 * FAKE, 4 * FAKE, 0, 6 * FAKE)
+    arr[1] = B._CInstance(2, 0, 4, FAKE, 2 * FAKE, 3 * FAKE, 4 * FAKE, 0, 6 * FAKE)
+    sz = ctypes.c_size_t(0)
+    assert lib.ladder_batched_workspace_size(0, arr, 3, _opts(), ctypes.byref(sz)) == EINVAL
+    assert lib.ladder_batched_workspace_size(1, arr, 0, _opts(), ctypes.byref(sz)) == EINVAL
+    assert lib.ladder_batched_workspace_size(2, arr, 3, _opts(), ctypes.byref(sz)) == EINVAL  # v = 0
+    assert "instance 1" in lib.ladder_last_error().decode()
+    assert lib.ladder_batched_workspace_size(1, arr, 3, _opts(), ctypes.byref(sz)) == 0 and sz.value > 0
+    arr[0].R = None
+    assert lib.ladder_batched_workspace_size(1, arr, 1, _opts(), ctypes.byref(sz)) == EINVAL
+    assert lib.ladder_batched(1, arr, 2, 8 * FAKE, 16, _opts(), None) == EWORKSPACE

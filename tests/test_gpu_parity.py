@@ -293,3 +293,112 @@ def test_split_autograd(dev):
     Xr = oracle.adjoint(o, v, n, L, tau, w)
     assert err_rel(float(E.detach()), Er) <= SPLIT_TOL_E
     assert err_norm(Lg.grad.cpu().numpy(), Xr) <= SPLIT_TOL_RX
+
+
+# ------------------------------------------------------------------ ragged batches
+def _instances(dev, shapes, seed0):
+    insts, refs = [], []
+    for k, (o, v, n) in enumerate(shapes):
+        L, tau, w = gaussian_inputs(seed0 + k, o, v, n)
+        insts.append(dict(o=o, v=v, n=n, L=g(L, dev), tau=g(tau, dev), tbar=g(w, dev),
+                          R=torch.empty((o, o, v, v), dtype=torch.float64, device=dev),
+                          E=torch.empty((), dtype=torch.float64, device=dev),
+                          X=torch.empty((v, v, n), dtype=torch.float64, device=dev)))
+        refs.append((L, tau, w))
+    return insts, refs
+
+
+@pytest.mark.parametrize("precision", [P.FP64, P.SPLIT_BF16])
+def test_batched_matches_single_calls_and_oracle(dev, precision):
+    shapes = [(3, 17, 30), (5, 9, 11), (2, 40, 70), (4, 23, 5), (6, 31, 44), (1, 12, 9), (7, 6, 20), (3, 50, 33),
+              (2, 19, 101), (4, 8, 16)]
+    insts, refs = _instances(dev, shapes, 300)
+    opts = P.Options(precision=precision, n_abatch=4)
+    P.batched(insts, P.DO_FORWARD | P.DO_ADJOINT, opts=opts)
+    torch.cuda.synchronize()
+    tol_rx, tol_e = (TOL, TOL) if precision == P.FP64 else (SPLIT_TOL_RX, SPLIT_TOL_E)
+    for d, (L, tau, w) in zip(insts, refs):
+        o, v, n = d["o"], d["v"], d["n"]
+        R1, E1 = P.forward(d["L"], d["tau"], d["tbar"], o=o, v=v, n=n, opts=opts)
+        X1 = P.adjoint(d["L"], d["tau"], d["tbar"], o=o, v=v, n=n, opts=opts)
+        assert torch.equal(d["R"], R1) and torch.equal(d["X"], X1) and torch.equal(d["E"], E1)
+        Rr, Er = oracle.forward(o, v, n, L, tau, w)
+        Xr = oracle.adjoint(o, v, n, L, tau, w)
+        assert err_norm(d["R"].cpu().numpy(), Rr) <= tol_rx and err_norm(d["X"].cpu().numpy(), Xr) <= tol_rx
+        assert err_rel(float(d["E"].cpu()), Er) <= tol_e
+
+
+def test_batched_graph_replay_sees_new_data(dev):
+    """The second call with the same shapes and pointers replays the captured graph;
+    it must compute on the current contents of the inputs."""
+    shapes = [(3, 14, 20), (2, 21, 13), (4, 9, 30)]
+    insts, _ = _instances(dev, shapes, 400)
+    P.batched(insts, P.DO_FORWARD | P.DO_ADJOINT)
+    first = [(d["R"].clone(), d["E"].clone(), d["X"].clone()) for d in insts]
+    for d in insts:
+        d["tau"].mul_(2.0)   # same pointers, new data
+    P.batched(insts, P.DO_FORWARD | P.DO_ADJOINT)
+    torch.cuda.synchronize()
+    for d, (R0, E0, X0) in zip(insts, first):
+        assert torch.allclose(d["R"], 2.0 * R0, rtol=1e-13, atol=0)
+        assert torch.allclose(d["X"], 2.0 * X0, rtol=1e-13, atol=0)
+        assert torch.allclose(d["E"], 2.0 * E0, rtol=1e-13, atol=0)
+    for _ in range(3):  # replays interleaved with eager work stay correct
+        P.batched(insts, P.DO_FORWARD)
+        R1, _ = P.forward(insts[0]["L"], insts[0]["tau"], insts[0]["tbar"], o=3, v=14, n=20)
+        torch.cuda.synchronize()
+        assert torch.equal(insts[0]["R"], R1)
+
+
+def test_batched_forward_only_leaves_X_alone(dev):
+    shapes = [(2, 10, 12), (3, 7, 9)]
+    insts, _ = _instances(dev, shapes, 500)
+    for d in insts:
+        d["X"].fill_(7.0)
+    P.batched(insts, P.DO_FORWARD)
+    torch.cuda.synchronize()
+    assert all(bool((d["X"] == 7.0).all()) for d in insts)
+
+
+def test_autograd_workload_split_forward(dev):
+    """o=40, v=350, n=1200, seed 5: LadderEnergy with the split forward and the
+    hand-written adjoint.  Checked against the oracle gradient on 200 random
+    (J, a, c) entries, against central differences of the FP64 GPU energy on a few
+    entries, and E against the FP64 path."""
+    import time
+    o, v, n = 40, 350, 1200
+    t0 = time.time()
+    L, tau, tbar, _, _ = oracle.make_inputs(o, v, n, 5)
+    print("autograd workload: inputs in %.1fs" % (time.time() - t0), flush=True)
+    Lg = g(L, dev).requires_grad_(True)
+    tg, wg = g(tau, dev), g(tbar, dev)
+    E = P.ladder_energy(Lg, tg, wg, (o, v, n), SPLIT5)
+    E.backward()
+    X = Lg.grad.detach().cpu().numpy()
+    E64 = float(P.forward(Lg.detach(), tg, wg, o=o, v=v, n=n)[1].cpu())
+    print("autograd workload: E split %.17g fp64 %.17g rel %.2e" % (float(E.detach()), E64, err_rel(float(E.detach()), E64)))
+    assert err_rel(float(E.detach()), E64) <= SPLIT_TOL_E
+    rng = np.random.default_rng(5)
+    ac = np.stack([rng.integers(v, size=200), rng.integers(v, size=200)], axis=1)
+    J = rng.integers(n, size=200)
+    t0 = time.time()
+    Xs = oracle.X_sample(o, v, n, L, tau, tbar, ac)
+    print("autograd workload: 200 oracle gradient rows in %.1fs" % (time.time() - t0), flush=True)
+    got = X[ac[:, 0], ac[:, 1], J]
+    ref = Xs[np.arange(200), J]
+    scale = np.abs(Xs).max()
+    print("autograd workload: max |X - X_oracle| / max|X_oracle rows| = %.2e" % (np.abs(got - ref).max() / scale))
+    assert np.abs(got - ref).max() <= SPLIT_TOL_RX * scale
+    # whole rows too: every J of the sampled (a, c)
+    assert np.abs(X[ac[:, 0], ac[:, 1], :] - Xs).max() <= SPLIT_TOL_RX * scale
+    h = 1e-6
+    Ld = Lg.detach()
+    for k in range(4):
+        a, c, j = int(ac[k, 0]), int(ac[k, 1]), int(J[k])
+        Lp = Ld.clone(); Lp[a, c, j] += h
+        Lm = Ld.clone(); Lm[a, c, j] -= h
+        Ep = float(P.forward(Lp, tg, wg, o=o, v=v, n=n)[1].cpu())
+        Em = float(P.forward(Lm, tg, wg, o=o, v=v, n=n)[1].cpu())
+        fd = (Ep - Em) / (2 * h)
+        print("autograd workload: FD (%d,%d,%d) %.12e  X %.12e" % (a, c, j, fd, X[a, c, j]))
+        assert abs(fd - X[a, c, j]) <= 1e-6 * scale
