@@ -257,7 +257,7 @@ def run_batched(args):
     ms = ev0.elapsed_time(ev1) / steps
     print("bench: graph %.1f ms per batch" % ms, file=sys.stderr, flush=True)
     # the same work as 64 sequential forward + adjoint calls on one stream
-    wsq = ws[: max(P.workspace_size(d["o"], d["v"], d["n"], opts) for d in insts)]
+    wsq = torch.empty(max(P.workspace_size(d["o"], d["v"], d["n"], opts) for d in insts), dtype=torch.uint8, device=dev)
     ev0.record(stream)
     for d in insts:
         P.forward(d["L"], d["tau"], d["tbar"], o=d["o"], v=d["v"], n=d["n"], R=d["R"], E=d["E"], ws=wsq, opts=opts)
