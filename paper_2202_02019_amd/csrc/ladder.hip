@@ -367,17 +367,20 @@ int check_split_dims(const Sizes& s, int64_t n, const ladder_options& op) {
 
 // ------------------------------------------------------------ ragged batches
 // ladder_batched runs every instance's forward and/or adjoint as parallel
-// branches of one hipGraph: instance i goes to branch i % branches, each branch
-// owns one workspace slot and runs its instances in order, so up to `branches`
-// instances share the GPU at a time.  The graph is captured on the first call
-// with a given set of shapes, pointers and options and replayed afterwards.
-constexpr int BATCH_BRANCHES = 8;
-constexpr size_t BATCH_TILE_BYTES = size_t(1) << 30;  // default g/D tile per instance
+// branches of one hipGraph.  Instances are dealt to branches longest first, each
+// to the branch with the least nominal work so far (LPT), each branch owns one
+// workspace slot and runs its instances in order, so up to `branches` instances
+// share the GPU at a time.  The graph is captured on the first call with a given
+// set of shapes, pointers and options and replayed afterwards.
+constexpr int BATCH_BRANCHES = 4;
+constexpr size_t BATCH_TILE_BYTES = size_t(4) << 30;  // default g/D tile per instance
 constexpr size_t MAX_GRAPHS = 8;
 
 struct BatchPlan {
     ladder_options op;
     std::vector<ladder_options> inst_opts;
+    std::vector<int> branch_of;  // LPT assignment
+    std::vector<int> order;      // launch order: longest first
     size_t slot = 0, total = 0;
     int branches = 0;
 };
@@ -412,6 +415,22 @@ int batch_plan(int count, const ladder_instance* inst, uint32_t what, const ladd
     }
     bp.branches = std::min(count, BATCH_BRANCHES);
     bp.total = bp.slot * (size_t)bp.branches;
+    // longest processing time first onto the least loaded branch
+    std::vector<double> work(count);
+    for (int i = 0; i < count; ++i) {
+        const double o = (double)inst[i].o, v = (double)inst[i].v, n = (double)inst[i].n;
+        work[i] = v * v * v * v * (n + o * o);
+    }
+    bp.order.resize(count);
+    for (int i = 0; i < count; ++i) bp.order[i] = i;
+    std::stable_sort(bp.order.begin(), bp.order.end(), [&](int a, int b) { return work[a] > work[b]; });
+    std::vector<double> load(bp.branches, 0.0);
+    bp.branch_of.assign(count, 0);
+    for (int i : bp.order) {
+        const int b = (int)(std::min_element(load.begin(), load.end()) - load.begin());
+        bp.branch_of[i] = b;
+        load[b] += work[i];
+    }
     return LADDER_OK;
 }
 
@@ -716,9 +735,10 @@ int ladder_batched(int count, const ladder_instance* inst, uint32_t what, void* 
         g_capturing = true;
         int brc = hip_check(hipEventRecord(ds.fork, cap), "fork event");
         for (int b = 0; b < bp.branches && !brc; ++b) brc = hip_check(hipStreamWaitEvent(ds.branch[b], ds.fork, 0), "fork wait");
-        for (int i = 0; i < count && !brc; ++i) {
+        for (int k = 0; k < count && !brc; ++k) {
+            const int i = bp.order[k];
             const ladder_instance& x = inst[i];
-            const int b = i % bp.branches;
+            const int b = bp.branch_of[i];
             char* slot = (char*)ws + (size_t)b * bp.slot;
             if (what & LADDER_DO_FORWARD)
                 brc = ladder_forward(x.o, x.v, x.n, x.L, x.tau, x.tbar, 0.0, x.R, x.E, slot, bp.slot, &bp.inst_opts[i],
