@@ -31,9 +31,15 @@
  *     the caller's `ws` buffer (device memory of `ws_bytes` bytes, 256-byte
  *     aligned), sized with ladder_workspace_size().  It holds only per-batch
  *     tiles of g or D (n_abatch * v^3 doubles), never the whole v^4 array.
- *   * Pair symmetry: the adjoint assumes tau_ij^ab = tau_ji^ba and
+ *   * Pair symmetry: the library assumes tau_ij^ab = tau_ji^ba and
  *     tbar_ij^ab = tbar_ji^ba (true for closed-shell CCSD amplitudes) unless
- *     LADDER_FLAG_GENERAL is set, which adds the second density term explicitly.
+ *     LADDER_FLAG_GENERAL is set.  With it, the default path packs the
+ *     contractions into symmetric and antisymmetric parts (the strategy the
+ *     paper adapts from Scuseria et al. in Sec. II B): the forward O^2 V^4
+ *     product runs on i<=j, a<=b, c<=d (1/4 of the dense work) and the density
+ *     on i<=j, c<=d (1/2).  LADDER_FLAG_DENSE selects the unpacked contraction;
+ *     LADDER_FLAG_GENERAL forms the second density term explicitly and is
+ *     always dense.
  *   * L need not be symmetric in (a,c) (T1-transformed vectors are not).
  *   * Results are deterministic: no floating-point atomics; the same inputs and
  *     options give bitwise identical R, E and X.
@@ -65,7 +71,8 @@ extern "C" {
 #define LADDER_SPLIT_BF16 1 /* exponent-aligned BF16 slices on BF16 MFMA, exact FP32 chunk sums, FP64 combine */
 
 /* Option flags. */
-#define LADDER_FLAG_GENERAL 1u /* adjoint: do not assume pair symmetry of tau and tbar */
+#define LADDER_FLAG_GENERAL 1u /* adjoint: do not assume pair symmetry of tau and tbar (implies DENSE) */
+#define LADDER_FLAG_DENSE 2u   /* contract all (i,j), (a,b), (c,d): skip the +/- packing */
 
 typedef struct {
     int32_t precision; /* LADDER_FP64 or LADDER_SPLIT_BF16 */
@@ -82,9 +89,10 @@ void ladder_default_options(ladder_options* opts);
 /*
  * Bytes of device workspace that ladder_forward / ladder_adjoint need for the
  * shape (o, v, n) and options (the larger of the two).  With n_abatch = 0 the
- * batch is the largest that keeps the per-batch g/D tile at or below
- * LADDER_DEFAULT_TILE_BYTES and covers at most half of the virtual range
- * (ceil(v/2)), so the full v^4 array is never held.
+ * batch is the largest that keeps the per-batch g/D tile (with its packed
+ * halves on the +/- path) at or below LADDER_DEFAULT_TILE_BYTES and covers at
+ * most half of the virtual range (a quarter on the +/- path), so no v^4-sized
+ * array is ever held.
  */
 #define LADDER_DEFAULT_TILE_BYTES ((size_t)16 << 30)
 int ladder_workspace_size(int64_t o, int64_t v, int64_t n, const ladder_options* opts, size_t* bytes);
@@ -177,7 +185,9 @@ int ladder_batched(int count, const ladder_instance* inst, uint32_t what, void* 
 #define LADDER_STAGE_MP2 6      /* first-order amplitudes */
 #define LADDER_STAGE_UPDATE 7   /* amplitude update */
 #define LADDER_STAGE_SLICE 8    /* split mode: FP64 -> BF16 slices */
-#define LADDER_NUM_STAGES 9
+#define LADDER_STAGE_PACK 9     /* +/- packing of tau, tbar and the g tile */
+#define LADDER_STAGE_UNPACK 10  /* R and D rebuilt from their packed parts */
+#define LADDER_NUM_STAGES 11
 typedef struct {
     int32_t stage;
     int32_t launches;

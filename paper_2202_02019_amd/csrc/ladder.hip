@@ -35,6 +35,7 @@
 #include "../../include/ladder.h"
 #include "gemm_f64.hpp"
 #include "split_bf16.hpp"
+#include "pm_pack.hpp"
 
 using namespace ladder;
 
@@ -139,7 +140,8 @@ int get_opts(const ladder_options* in, ladder_options& o) {
                         SPLIT_MAX_S, (int)o.n_slices);
     }
     if (o.n_abatch < 0) return fail(LADDER_EINVAL, "n_abatch must be >= 0");
-    if (o.flags & ~LADDER_FLAG_GENERAL) return fail(LADDER_EUNSUPPORTED, "unknown flag bits 0x%x", o.flags);
+    if (o.flags & ~(LADDER_FLAG_GENERAL | LADDER_FLAG_DENSE))
+        return fail(LADDER_EUNSUPPORTED, "unknown flag bits 0x%x", o.flags);
     if (o.reserved != 0) return fail(LADDER_EINVAL, "reserved option field must be 0");
     return LADDER_OK;
 }
@@ -191,19 +193,29 @@ struct Plan {
     SlicedBuf w_ij, tau_ij, L_bd;        // split adjoint: w and tau along (ij) (rows (ab)/(cd)), L along (bd) (rows J)
     size_t swap_off = 0;                 // general adjoint: P w and P tau, FP64
     SlicedBuf pw_ij, ptau_ij;            // general split adjoint: their slices
+    // +/- packed path (pair-symmetric inputs): sizes and offsets
+    bool pm = false;
+    int64_t P2o = 0, Q2o = 0, P2v = 0, Q2v = 0, NP = 0, NM = 0;  // NP, NM: packed g rows of a full batch
+    size_t f_tp = 0, f_tm = 0, f_gp = 0, f_gm = 0, f_rp = 0, f_rm = 0;  // forward, FP64
+    SlicedBuf tp_cd, tm_cd, gp_sl, gm_sl;                               // forward, split
+    size_t a_wp = 0, a_wm = 0, a_tp = 0, a_tm = 0, a_dp = 0, a_dm = 0;  // adjoint, FP64
+    SlicedBuf wp_ij, wm_ij, tp_ij, tm_ij;                               // adjoint, split
     size_t fwd_total = 0, adj_total = 0, total = 0;
 };
+
+constexpr int PM_UNPACK_GRID = 1024;  // blocks of the R unpack kernel (one energy partial each)
 
 Plan make_plan(int64_t o, int64_t v, int64_t n, const ladder_options& op, const Sizes& s) {
     Plan p;
     p.S = op.precision == LADDER_SPLIT_BF16 ? op.n_slices : 0;
+    const bool packed = !(op.flags & (LADDER_FLAG_GENERAL | LADDER_FLAG_DENSE));
     int64_t nA = op.n_abatch;
     if (nA == 0) {
-        int64_t per_a = s.vvv * 8;
+        int64_t per_a = s.vvv * 8 * (packed ? 2 : 1);  // the tile, plus its packed halves on the +/- path
         if (p.S) per_a += (int64_t)(slice_bytes(p.S, v, s.vv) + exp_bytes(v, s.vv));
         nA = (int64_t)(LADDER_DEFAULT_TILE_BYTES / (size_t)per_a);
-        // at least two batches, so the whole v^4 array is never held at once
-        nA = std::min(nA, (v + 1) / 2);
+        // several batches, so that no v^4-sized array is ever held at once
+        nA = std::min(nA, packed ? (v + 3) / 4 : (v + 1) / 2);
         if (nA < 1) nA = 1;
     }
     if (nA > v) nA = v;
@@ -215,30 +227,70 @@ Plan make_plan(int64_t o, int64_t v, int64_t n, const ladder_options& op, const 
     if (p.S) p.tile_sl = take_sliced(a, p.S, nA * v, s.vv);
     const size_t common = a.top;
 
+    const bool general = (op.flags & LADDER_FLAG_GENERAL) != 0;
+    p.pm = !general && !(op.flags & LADDER_FLAG_DENSE);
+    if (p.pm) {
+        p.P2o = pm_P2(o); p.Q2o = pm_Q2(o); p.P2v = pm_P2(v); p.Q2v = pm_Q2(v);
+        p.NP = pm_gp_off(nA, v, 0);
+        p.NM = pm_gm_off(nA, v, 0);
+    }
+
     Arena f = a;  // forward-only part
-    p.part_per_batch = (size_t)tiles(s.oo, nA * v);
-    p.part_off = f.take(p.part_per_batch * (size_t)p.nbatch * 8);
-    if (p.S) {
-        p.L_J = take_sliced(f, p.S, s.vv, n);
-        p.tau_cd = take_sliced(f, p.S, s.oo, s.vv);
+    if (!p.pm) {
+        p.part_per_batch = (size_t)tiles(s.oo, nA * v);
+        p.part_off = f.take(p.part_per_batch * (size_t)p.nbatch * 8);
+        if (p.S) {
+            p.L_J = take_sliced(f, p.S, s.vv, n);
+            p.tau_cd = take_sliced(f, p.S, s.oo, s.vv);
+        }
+    } else {
+        p.part_per_batch = 2 * PM_UNPACK_GRID;
+        p.part_off = f.take(p.part_per_batch * (size_t)p.nbatch * 8);
+        p.f_tp = f.take((size_t)(p.P2o * p.P2v) * 8);
+        p.f_tm = f.take((size_t)(p.Q2o * p.Q2v) * 8 + 8);
+        p.f_gp = f.take((size_t)(p.NP * p.P2v) * 8);
+        p.f_gm = f.take((size_t)(p.NM * p.Q2v) * 8 + 8);
+        p.f_rp = f.take((size_t)(p.P2o * p.NP) * 8);
+        p.f_rm = f.take((size_t)(p.Q2o * p.NM) * 8 + 8);
+        if (p.S) {
+            p.L_J = take_sliced(f, p.S, s.vv, n);
+            p.tp_cd = take_sliced(f, p.S, p.P2o, p.P2v);
+            p.tm_cd = take_sliced(f, p.S, std::max<int64_t>(p.Q2o, 1), std::max<int64_t>(p.Q2v, 1));
+            p.gp_sl = take_sliced(f, p.S, p.NP, p.P2v);
+            p.gm_sl = take_sliced(f, p.S, std::max<int64_t>(p.NM, 1), std::max<int64_t>(p.Q2v, 1));
+        }
     }
     p.fwd_total = f.top;
 
     Arena d = a;  // adjoint-only part
-    const bool general = (op.flags & LADDER_FLAG_GENERAL) != 0;
-    if (general) p.swap_off = d.take((size_t)s.ovv_elems * 16);
-    if (p.S) {
-        p.w_ij = take_sliced(d, p.S, s.vv, s.oo);
-        p.tau_ij = take_sliced(d, p.S, s.vv, s.oo);
-        p.L_bd = take_sliced(d, p.S, n, s.vv);
-        if (general) {
-            p.pw_ij = take_sliced(d, p.S, s.vv, s.oo);
-            p.ptau_ij = take_sliced(d, p.S, s.vv, s.oo);
+    if (!p.pm) {
+        if (general) p.swap_off = d.take((size_t)s.ovv_elems * 16);
+        if (p.S) {
+            p.w_ij = take_sliced(d, p.S, s.vv, s.oo);
+            p.tau_ij = take_sliced(d, p.S, s.vv, s.oo);
+            p.L_bd = take_sliced(d, p.S, n, s.vv);
+            if (general) {
+                p.pw_ij = take_sliced(d, p.S, s.vv, s.oo);
+                p.ptau_ij = take_sliced(d, p.S, s.vv, s.oo);
+            }
+        }
+    } else {
+        p.a_wp = d.take((size_t)(p.P2o * s.vv) * 8);
+        p.a_wm = d.take((size_t)(p.Q2o * s.vv) * 8 + 8);
+        p.a_tp = d.take((size_t)(p.P2o * p.P2v) * 8);
+        p.a_tm = d.take((size_t)(p.Q2o * p.Q2v) * 8 + 8);
+        p.a_dp = d.take((size_t)(nA * v * p.P2v) * 8);
+        p.a_dm = d.take((size_t)(nA * v * p.Q2v) * 8 + 8);
+        if (p.S) {
+            p.wp_ij = take_sliced(d, p.S, s.vv, p.P2o);
+            p.wm_ij = take_sliced(d, p.S, s.vv, std::max<int64_t>(p.Q2o, 1));
+            p.tp_ij = take_sliced(d, p.S, p.P2v, p.P2o);
+            p.tm_ij = take_sliced(d, p.S, std::max<int64_t>(p.Q2v, 1), std::max<int64_t>(p.Q2o, 1));
+            p.L_bd = take_sliced(d, p.S, n, s.vv);
         }
     }
     p.adj_total = d.top;
     (void)common;
-    (void)o;
     p.total = std::max(p.fwd_total, p.adj_total);
     return p;
 }
@@ -315,6 +367,11 @@ int slice_into(int S, bool transposed, const double* src, int64_t ld, char* ws, 
     return hip_check(e, "slice launch");
 }
 
+__global__ void fill_zero_kernel(double* __restrict__ x, int64_t count) {
+    for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < count; t += (int64_t)gridDim.x * blockDim.x)
+        x[t] = 0.0;
+}
+
 // out_ij^ab = in_ji^ba
 __global__ void pair_swap_kernel(const double* __restrict__ in, double* __restrict__ out, int64_t o, int64_t v) {
     const int64_t total = o * o * v * v;
@@ -362,6 +419,165 @@ int check_split_dims(const Sizes& s, int64_t n, const ladder_options& op) {
     const int64_t kmax = std::max(std::max(s.vv, s.oo), n);
     if (split_kpad(kmax) * 2 * SPLIT_BM >= (int64_t(1) << 32))
         return fail(LADDER_EUNSUPPORTED, "split precision needs v^2, o^2 and n below 2^24");
+    return LADDER_OK;
+}
+
+
+// ---------------------------------------------------------------- +/- packed path
+// Forward with the symmetric/antisymmetric packing of pm_pack.hpp: per batch the
+// g tile is packed to g+ (a<=b, c<=d) and g- (a<b, c<d), the two products
+// R+ = tau+ g+^T and R- = tau- g-^T run on (i<=j) and (i<j) rows, and the unpack
+// kernel writes R_ij^ab and R_ij^ba for the batch's a (with the energy partials).
+int forward_pm(int64_t o, int64_t v, int64_t n, const double* L, const double* tau, const double* tbar, double beta,
+               double* R, double* E, char* w, const Plan& p, const Sizes& s, hipStream_t st) {
+    int rc;
+    const int S = p.S;
+    double* g = (double*)(w + p.tile_off);
+    double* part = (double*)(w + p.part_off);
+    double *tp = (double*)(w + p.f_tp), *tm = (double*)(w + p.f_tm), *gp = (double*)(w + p.f_gp),
+           *gm = (double*)(w + p.f_gm), *rp = (double*)(w + p.f_rp), *rm = (double*)(w + p.f_rm);
+    {
+        StageTimer tm_(LADDER_STAGE_PACK, 0.0, 16.0 * (double)pm_amp_count(o, v), st);
+        hipLaunchKernelGGL(pm_pack_amp_kernel, dim3(grid_for(pm_amp_count(o, v))), dim3(256), 0, st, tau, o, v, tp, tm);
+        if ((rc = hip_check(hipGetLastError(), "pack launch"))) return rc;
+    }
+    const bool minus = p.Q2o > 0 && p.Q2v > 0;
+    if (S) {
+        if ((rc = slice_into(S, false, L, n, w, p.L_J, st))) return rc;
+        if ((rc = slice_into(S, false, tp, p.P2v, w, p.tp_cd, st))) return rc;
+        if (minus && (rc = slice_into(S, false, tm, p.Q2v, w, p.tm_cd, st))) return rc;
+    }
+    for (int64_t bi = 0; bi < p.nbatch; ++bi) {
+        const int64_t a0 = bi * p.nA;
+        const int64_t nA = std::min(p.nA, v - a0);
+        const int64_t NPb = pm_gp_off(nA, v, a0), NMb = pm_gm_off(nA, v, a0);
+        {
+            StageTimer tm_(LADDER_STAGE_GEMM_B, gemm_flops(nA * v, s.vv, n), gemm_bytes(nA * v, s.vv, n), st);
+            EpiSwapMid eg{g, v, v, v, 1.0, 0.0};
+            hipError_t e;
+            if (!S) {
+                e = launch_gemm<true, true>(L + a0 * v * n, n, L, n, nA * v, s.vv, n, eg, st);
+            } else {
+                SplitShape sh{view(w, p.L_J, a0 * v), view(w, p.L_J, 0), nA * v, s.vv, n};
+                e = launch_split(S, sh, eg, st);
+            }
+            if ((rc = hip_check(e, "GEMM-B launch"))) return rc;
+        }
+        {
+            const int64_t cnt = pm_g_count(v, a0, nA);
+            StageTimer tm_(LADDER_STAGE_PACK, 0.0, 24.0 * (double)cnt, st);
+            hipLaunchKernelGGL(pm_pack_g_kernel, dim3(grid_for(cnt)), dim3(256), 0, st, g, v, a0, nA, gp, gm);
+            if ((rc = hip_check(hipGetLastError(), "pack launch"))) return rc;
+        }
+        const bool minus_b = minus && NMb > 0;
+        SlicedBuf gps = p.gp_sl, gms = p.gm_sl;
+        gps.R = NPb;
+        gms.R = NMb;
+        if (S) {
+            if ((rc = slice_into(S, false, gp, p.P2v, w, gps, st))) return rc;
+            if (minus_b && (rc = slice_into(S, false, gm, p.Q2v, w, gms, st))) return rc;
+        }
+        for (int sign = 0; sign < (minus_b ? 2 : 1); ++sign) {
+            const int64_t M = sign ? p.Q2o : p.P2o, N = sign ? NMb : NPb, K = sign ? p.Q2v : p.P2v;
+            StageTimer tm_(LADDER_STAGE_GEMM_C, gemm_flops(M, N, K), gemm_bytes(M, N, K), st);
+            EpiStrided er{sign ? rm : rp, N, 1.0, 0.0, nullptr, nullptr};
+            hipError_t e;
+            if (!S) {
+                e = launch_gemm<true, true>(sign ? tm : tp, K, sign ? gm : gp, K, M, N, K, er, st);
+            } else {
+                SplitShape sh{view(w, sign ? p.tm_cd : p.tp_cd, 0), view(w, sign ? gms : gps, 0), M, N, K};
+                e = launch_split(S, sh, er, st);
+            }
+            if ((rc = hip_check(e, "GEMM-C launch"))) return rc;
+        }
+        {
+            StageTimer tm_(LADDER_STAGE_UNPACK, 2.0 * (double)s.oo * nA * v, 16.0 * (double)s.oo * nA * v, st);
+            for (int pass = 0; pass < 2; ++pass)
+                hipLaunchKernelGGL(pm_unpack_R_kernel, dim3(PM_UNPACK_GRID), dim3(256), 0, st, rp, rm, o, v, a0, nA, beta,
+                                   E ? tbar : nullptr, R, part + bi * p.part_per_batch + pass * PM_UNPACK_GRID, pass);
+            if ((rc = hip_check(hipGetLastError(), "unpack launch"))) return rc;
+        }
+    }
+    if (E) {
+        const int64_t count = (int64_t)p.part_per_batch * p.nbatch;
+        StageTimer tm_(LADDER_STAGE_ENERGY, (double)count, 8.0 * (double)count, st);
+        hipLaunchKernelGGL(reduce_partials_kernel, dim3(1), dim3(256), 0, st, part, count, E);
+        if ((rc = hip_check(hipGetLastError(), "energy reduction launch"))) return rc;
+    }
+    return LADDER_OK;
+}
+
+// Adjoint with the packing: D+ = w+^T tau+ over (i<=j) and D- = w-^T tau- over
+// (i<j), on the (c<=d) / (c<d) columns only; the unpack kernel rebuilds the D
+// tile [(a,c),(b,d)] that GEMM-F contracts with L.
+int adjoint_pm(int64_t o, int64_t v, int64_t n, const double* L, const double* tau, const double* wt, double alpha,
+               double beta, double* X, char* w, const Plan& p, const Sizes& s, hipStream_t st) {
+    int rc;
+    const int S = p.S;
+    double* D = (double*)(w + p.tile_off);
+    double *wp = (double*)(w + p.a_wp), *wm = (double*)(w + p.a_wm), *tp = (double*)(w + p.a_tp),
+           *tm = (double*)(w + p.a_tm), *dp = (double*)(w + p.a_dp), *dm = (double*)(w + p.a_dm);
+    {
+        StageTimer tm_(LADDER_STAGE_PACK, 0.0, 16.0 * (double)(pm_amp_count(o, v) + pm_w_count(o, v)), st);
+        hipLaunchKernelGGL(pm_pack_amp_kernel, dim3(grid_for(pm_amp_count(o, v))), dim3(256), 0, st, tau, o, v, tp, tm);
+        hipLaunchKernelGGL(pm_pack_w_kernel, dim3(grid_for(pm_w_count(o, v))), dim3(256), 0, st, wt, o, v, wp, wm);
+        if ((rc = hip_check(hipGetLastError(), "pack launch"))) return rc;
+    }
+    const bool minus = p.Q2o > 0 && p.Q2v > 0;
+    if (S) {
+        if ((rc = slice_into(S, true, wp, s.vv, w, p.wp_ij, st))) return rc;
+        if ((rc = slice_into(S, true, tp, p.P2v, w, p.tp_ij, st))) return rc;
+        if (minus) {
+            if ((rc = slice_into(S, true, wm, s.vv, w, p.wm_ij, st))) return rc;
+            if ((rc = slice_into(S, true, tm, p.Q2v, w, p.tm_ij, st))) return rc;
+        }
+        if ((rc = slice_into(S, true, L, n, w, p.L_bd, st))) return rc;
+    }
+    for (int64_t bi = 0; bi < p.nbatch; ++bi) {
+        const int64_t a0 = bi * p.nA;
+        const int64_t nA = std::min(p.nA, v - a0);
+        for (int sign = 0; sign < (minus ? 2 : 1); ++sign) {
+            const int64_t M = nA * v, N = sign ? p.Q2v : p.P2v, K = sign ? p.Q2o : p.P2o;
+            StageTimer tm_(LADDER_STAGE_GEMM_E, gemm_flops(M, N, K), gemm_bytes(M, N, K), st);
+            EpiStrided ed{sign ? dm : dp, N, 1.0, 0.0, nullptr, nullptr};
+            hipError_t e;
+            if (!S) {
+                e = launch_gemm<false, false>((sign ? wm : wp) + a0 * v, s.vv, sign ? tm : tp, N, M, N, K, ed, st);
+            } else {
+                SplitShape sh{view(w, sign ? p.wm_ij : p.wp_ij, a0 * v), view(w, sign ? p.tm_ij : p.tp_ij, 0), M, N, K};
+                e = launch_split(S, sh, ed, st);
+            }
+            if ((rc = hip_check(e, "GEMM-E launch"))) return rc;
+        }
+        if (!minus && p.Q2v > 0) {  // o = 1: no antisymmetric part, D- = 0
+            hipLaunchKernelGGL(fill_zero_kernel, dim3(grid_for(nA * v * p.Q2v)), dim3(256), 0, st, dm, nA * v * p.Q2v);
+            if ((rc = hip_check(hipGetLastError(), "fill launch"))) return rc;
+        }
+        {
+            StageTimer tm_(LADDER_STAGE_UNPACK, 0.0, 24.0 * (double)(nA * s.vvv), st);
+            hipLaunchKernelGGL(pm_unpack_D_kernel, dim3(grid_for(nA * s.vvv)), dim3(256), 0, st, dp, dm, v, nA, D);
+            if ((rc = hip_check(hipGetLastError(), "unpack launch"))) return rc;
+        }
+        if (S) {
+            SlicedBuf tl = p.tile_sl;
+            tl.R = nA * v;
+            if ((rc = slice_into(S, false, D, s.vv, w, tl, st))) return rc;
+        }
+        {
+            StageTimer tm_(LADDER_STAGE_GEMM_F, gemm_flops(nA * v, n, s.vv), gemm_bytes(nA * v, n, s.vv), st);
+            EpiStrided ex{X + a0 * v * n, n, 2.0 * alpha, beta, nullptr, nullptr};
+            hipError_t e;
+            if (!S) {
+                e = launch_gemm<true, false>(D, s.vv, L, n, nA * v, n, s.vv, ex, st);
+            } else {
+                SlicedBuf tl = p.tile_sl;
+                tl.R = nA * v;
+                SplitShape sh{view(w, tl, 0), view(w, p.L_bd, 0), nA * v, n, s.vv};
+                e = launch_split(S, sh, ex, st);
+            }
+            if ((rc = hip_check(e, "GEMM-F launch"))) return rc;
+        }
+    }
     return LADDER_OK;
 }
 
@@ -523,6 +739,7 @@ int ladder_forward(int64_t o, int64_t v, int64_t n, const double* L, const doubl
 
     hipStream_t st = (hipStream_t)stream;
     char* w = (char*)ws;
+    if (p.pm) return forward_pm(o, v, n, L, tau, tbar, beta, R, E, w, p, s, st);
     double* g = (double*)(w + p.tile_off);
     double* part = (double*)(w + p.part_off);
     const int S = p.S;
@@ -597,6 +814,7 @@ int ladder_adjoint(int64_t o, int64_t v, int64_t n, const double* L, const doubl
 
     hipStream_t st = (hipStream_t)stream;
     char* w = (char*)ws;
+    if (p.pm) return adjoint_pm(o, v, n, L, tau, wt, alpha, beta, X, w, p, s, st);
     double* D = (double*)(w + p.tile_off);
     const bool general = (op.flags & LADDER_FLAG_GENERAL) != 0;
     double* pw = general ? (double*)(w + p.swap_off) : nullptr;

@@ -19,6 +19,7 @@ _LIB_PATH = os.path.join(PKG, "libladder.so")
 FP64 = 0
 SPLIT_BF16 = 1
 FLAG_GENERAL = 1
+FLAG_DENSE = 2
 DO_FORWARD = 1
 DO_ADJOINT = 2
 
@@ -29,7 +30,7 @@ EXPORTS = (
     "ladder_profile_start", "ladder_profile_stop",
 )
 
-STAGE_NAMES = ("gemm_b", "gemm_c", "energy", "gemm_e", "gemm_f", "swap", "mp2", "update", "slice")
+STAGE_NAMES = ("gemm_b", "gemm_c", "energy", "gemm_e", "gemm_f", "swap", "mp2", "update", "slice", "pack", "unpack")
 
 
 class LadderError(RuntimeError):

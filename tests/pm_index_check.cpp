@@ -1,0 +1,126 @@
+// Host check of the +/- packing index arithmetic (pm_pack.hpp) against the dense
+// definitions, run on the CPU (built by tests/test_pm_host.py with AddressSanitizer
+// on host code, so any index outside a packed buffer aborts).
+//   R_ij^ab = sum_cd (ac|bd) tau_ij^cd,  D_{ab,cd} = sum_ij tbar_ij^ab tau_ij^cd.
+#include <math.h>
+#include <stdio.h>
+#include <stdlib.h>
+
+#include <vector>
+
+#include "../paper_2202_02019_amd/csrc/pm_pack.hpp"
+
+using namespace ladder;
+
+static double rnd(unsigned long long& s) {
+    s = s * 6364136223846793005ULL + 1442695040888963407ULL;
+    return ((double)(s >> 11) * 0x1.0p-53) - 0.5;
+}
+
+int check(int64_t o, int64_t v, int64_t n, int64_t nA, unsigned long long seed) {
+    std::vector<double> L(v * v * n), tau(o * o * v * v), tb(o * o * v * v);
+    for (auto& x : L) x = rnd(seed);
+    for (auto* x : {&tau, &tb})
+        for (int64_t i = 0; i < o; ++i)
+            for (int64_t j = 0; j < o; ++j)
+                for (int64_t a = 0; a < v; ++a)
+                    for (int64_t b = 0; b < v; ++b) {
+                        const int64_t k1 = ((i * o + j) * v + a) * v + b, k2 = ((j * o + i) * v + b) * v + a;
+                        if (k2 < k1) (*x)[k1] = (*x)[k2];
+                        else (*x)[k1] = rnd(seed);
+                    }
+    // dense reference R and D
+    auto g = [&](int64_t a, int64_t c, int64_t b, int64_t d) {
+        double s = 0;
+        for (int64_t J = 0; J < n; ++J) s += L[(a * v + c) * n + J] * L[(b * v + d) * n + J];
+        return s;
+    };
+    std::vector<double> Rref(o * o * v * v, 0.0);
+    for (int64_t ij = 0; ij < o * o; ++ij)
+        for (int64_t a = 0; a < v; ++a)
+            for (int64_t b = 0; b < v; ++b) {
+                double s = 0;
+                for (int64_t c = 0; c < v; ++c)
+                    for (int64_t d = 0; d < v; ++d) s += g(a, c, b, d) * tau[ij * v * v + c * v + d];
+                Rref[ij * v * v + a * v + b] = s;
+            }
+    // packed inputs (exact-size buffers)
+    std::vector<double> tp(pm_P2(o) * pm_P2(v)), tm(pm_Q2(o) * pm_Q2(v) + 1), wp(pm_P2(o) * v * v), wm(pm_Q2(o) * v * v + 1);
+    for (int64_t t = 0; t < pm_amp_count(o, v); ++t) pm_pack_amp_elem(t, tau.data(), o, v, tp.data(), tm.data());
+    for (int64_t t = 0; t < pm_w_count(o, v); ++t) pm_pack_w_elem(t, tb.data(), o, v, wp.data(), wm.data());
+    std::vector<double> R(o * o * v * v, NAN);
+    double worstR = 0, worstD = 0, E = 0, Eref = 0;
+    for (int64_t a0 = 0; a0 < v; a0 += nA) {
+        const int64_t nb = nA < v - a0 ? nA : v - a0;
+        std::vector<double> gt(nb * v * v * v);
+        for (int64_t ap = 0; ap < nb; ++ap)
+            for (int64_t b = 0; b < v; ++b)
+                for (int64_t c = 0; c < v; ++c)
+                    for (int64_t d = 0; d < v; ++d) gt[((ap * v + b) * v + c) * v + d] = g(a0 + ap, c, b, d);
+        const int64_t NP = pm_gp_off(nb, v, a0), NM = pm_gm_off(nb, v, a0);
+        std::vector<double> gp(NP * pm_P2(v)), gm(NM * pm_Q2(v) + 1);
+        for (int64_t t = 0; t < pm_g_count(v, a0, nb); ++t) pm_pack_g_elem(t, gt.data(), v, a0, nb, gp.data(), gm.data());
+        std::vector<double> rp(pm_P2(o) * NP), rm(pm_Q2(o) * NM + 1);
+        for (int64_t p = 0; p < pm_P2(o); ++p)
+            for (int64_t r = 0; r < NP; ++r) {
+                double s = 0;
+                for (int64_t k = 0; k < pm_P2(v); ++k) s += tp[p * pm_P2(v) + k] * gp[r * pm_P2(v) + k];
+                rp[p * NP + r] = s;
+            }
+        for (int64_t q = 0; q < pm_Q2(o); ++q)
+            for (int64_t r = 0; r < NM; ++r) {
+                double s = 0;
+                for (int64_t k = 0; k < pm_Q2(v); ++k) s += tm[q * pm_Q2(v) + k] * gm[r * pm_Q2(v) + k];
+                rm[q * NM + r] = s;
+            }
+        for (int pass = 0; pass < 2; ++pass)
+            for (int64_t t = 0; t < o * o * nb * v; ++t) {
+                double e;
+                if (pm_unpack_R_elem(t, rp.data(), rm.data(), o, v, a0, nb, 0.0, tb.data(), R.data(), pass, &e)) E += e;
+            }
+        // density tiles
+        std::vector<double> dp(nb * v * pm_P2(v)), dm(nb * v * pm_Q2(v) + 1), D(nb * v * v * v);
+        for (int64_t row = 0; row < nb * v; ++row) {
+            for (int64_t k = 0; k < pm_P2(v); ++k) {
+                double s = 0;
+                for (int64_t p = 0; p < pm_P2(o); ++p) s += wp[p * v * v + a0 * v + row] * tp[p * pm_P2(v) + k];
+                dp[row * pm_P2(v) + k] = s;
+            }
+            for (int64_t k = 0; k < pm_Q2(v); ++k) {
+                double s = 0;
+                for (int64_t q = 0; q < pm_Q2(o); ++q) s += wm[q * v * v + a0 * v + row] * tm[q * pm_Q2(v) + k];
+                dm[row * pm_Q2(v) + k] = s;
+            }
+        }
+        for (int64_t t = 0; t < nb * v * v * v; ++t) pm_unpack_D_elem(t, dp.data(), dm.data(), v, D.data());
+        for (int64_t ap = 0; ap < nb; ++ap)
+            for (int64_t c = 0; c < v; ++c)
+                for (int64_t b = 0; b < v; ++b)
+                    for (int64_t d = 0; d < v; ++d) {
+                        double s = 0;
+                        for (int64_t ij = 0; ij < o * o; ++ij)
+                            s += tb[ij * v * v + (a0 + ap) * v + b] * tau[ij * v * v + c * v + d];
+                        worstD = fmax(worstD, fabs(D[((ap * v + c) * v + b) * v + d] - s));
+                    }
+    }
+    for (int64_t k = 0; k < o * o * v * v; ++k) {
+        if (isnan(R[k])) { printf("R element %lld never written\n", (long long)k); return 1; }
+        worstR = fmax(worstR, fabs(R[k] - Rref[k]));
+        Eref += tb[k] * Rref[k];
+    }
+    printf("o=%lld v=%lld n=%lld nA=%lld  max|dR| %.3e  max|dD| %.3e  |dE| %.3e\n", (long long)o, (long long)v, (long long)n,
+           (long long)nA, worstR, worstD, fabs(E - Eref));
+    return (worstR < 1e-12 && worstD < 1e-12 && fabs(E - Eref) < 1e-11) ? 0 : 1;
+}
+
+int main() {
+    int bad = 0;
+    bad |= check(1, 1, 1, 1, 1);
+    bad |= check(2, 3, 2, 1, 2);
+    bad |= check(3, 5, 3, 2, 3);
+    bad |= check(4, 7, 2, 3, 4);
+    bad |= check(2, 9, 4, 9, 5);
+    bad |= check(5, 6, 3, 4, 6);
+    printf(bad ? "FAIL\n" : "OK\n");
+    return bad;
+}

@@ -110,8 +110,11 @@ def test_workspace_never_holds_full_v4(o, v, n):
     ws = P.workspace_size(o, v, n)
     if v > 20:
         assert ws < 8 * v ** 4
-    ws1 = P.workspace_size(o, v, n, P.Options(n_abatch=1))
-    assert ws1 < 8 * v ** 3 + (1 << 24) + 8 * o * o * v * v
+    # one virtual index per batch: the g/D tile and its packed halves (v^3 each) plus
+    # packed copies of the amplitudes (o^2 v^2); nothing of size v^4
+    for flags in (0, P.FLAG_DENSE):
+        ws1 = P.workspace_size(o, v, n, P.Options(n_abatch=1, flags=flags))
+        assert ws1 < 16 * v ** 3 + 16 * o * o * v * v + (1 << 24)
 
 
 def test_batched_validation():

@@ -39,10 +39,14 @@ def run(dev, o, v, n, L, tau, w, opts=None):
     return R.cpu().numpy(), float(E.cpu()), X.cpu().numpy()
 
 
+PATHS = [pytest.param(0, id="pm"), pytest.param(P.FLAG_DENSE, id="dense")]
+
+
+@pytest.mark.parametrize("flags", PATHS)
 @pytest.mark.parametrize("o,v,n,seed", [(2, 5, 3, 1), (3, 4, 2, 2), (1, 3, 1, 3)])
-def test_integer_inputs_bitwise(dev, o, v, n, seed):
+def test_integer_inputs_bitwise(dev, o, v, n, seed, flags):
     L, tau, w = integer_inputs(seed, o, v, n)
-    R, E, X = run(dev, o, v, n, L, tau, w)
+    R, E, X = run(dev, o, v, n, L, tau, w, P.Options(flags=flags))
     Rr, Er = oracle.forward(o, v, n, L, tau, w)
     Xr = oracle.adjoint(o, v, n, L, tau, w)
     assert np.array_equal(R, Rr)
@@ -59,21 +63,23 @@ def test_micro_example(dev):
     assert np.array_equal(X.ravel(), np.array(gd["X"]).ravel())
 
 
-def test_tiny_workload(dev):
+@pytest.mark.parametrize("flags", PATHS)
+def test_tiny_workload(dev, flags):
     o, v, n = 4, 20, 60
     L, tau, tbar, _, _ = oracle.make_inputs(o, v, n, 1)
-    R, E, X = run(dev, o, v, n, L, tau, tbar)
+    R, E, X = run(dev, o, v, n, L, tau, tbar, P.Options(flags=flags))
     Rr, Er = oracle.forward(o, v, n, L, tau, tbar)
     Xr = oracle.adjoint(o, v, n, L, tau, tbar)
     print("tiny: err_R %.3e err_E %.3e err_X %.3e" % (err_norm(R, Rr), err_rel(E, Er), err_norm(X, Xr)))
     assert err_norm(R, Rr) <= TOL and err_rel(E, Er) <= TOL and err_norm(X, Xr) <= TOL
 
 
-@pytest.mark.parametrize("o,v,n,nA", [(5, 37, 70, 4), (3, 41, 130, 0), (7, 19, 257, 19), (2, 129, 17, 64)])
-def test_ragged_tiles_and_batches(dev, o, v, n, nA):
+@pytest.mark.parametrize("flags", PATHS)
+@pytest.mark.parametrize("o,v,n,nA", [(5, 37, 70, 4), (3, 41, 130, 0), (7, 19, 257, 19), (2, 129, 17, 64), (1, 23, 9, 5)])
+def test_ragged_tiles_and_batches(dev, o, v, n, nA, flags):
     """Shapes whose M, N, K are not tile multiples, several batches with a ragged last one."""
     L, tau, w = gaussian_inputs(100 + v, o, v, n)
-    R, E, X = run(dev, o, v, n, L, tau, w, P.Options(n_abatch=nA))
+    R, E, X = run(dev, o, v, n, L, tau, w, P.Options(n_abatch=nA, flags=flags))
     Rr, Er = oracle.forward(o, v, n, L, tau, w)
     Xr = oracle.adjoint(o, v, n, L, tau, w)
     assert err_norm(R, Rr) <= TOL and err_rel(E, Er) <= TOL and err_norm(X, Xr) <= TOL
@@ -91,7 +97,8 @@ def test_general_flag_on_asymmetric_input(dev):
     assert err_norm(Xs, Xr) > 1e-3
 
 
-def test_alpha_beta_accumulation(dev):
+@pytest.mark.parametrize("flags", PATHS)
+def test_alpha_beta_accumulation(dev, flags):
     o, v, n = 3, 17, 33
     L, tau, w = gaussian_inputs(8, o, v, n)
     R0 = np.random.default_rng(1).standard_normal((o, o, v, v))
@@ -99,8 +106,9 @@ def test_alpha_beta_accumulation(dev):
     Lg, tg, wg = g(L, dev), g(tau, dev), g(w, dev)
     R = g(R0, dev)
     X = g(X0, dev)
-    P.forward(Lg, tg, wg, o=o, v=v, n=n, R=R, beta=0.5)
-    P.adjoint(Lg, tg, wg, o=o, v=v, n=n, X=X, alpha=-2.0, beta=1.5)
+    opts = P.Options(flags=flags)
+    P.forward(Lg, tg, wg, o=o, v=v, n=n, R=R, beta=0.5, opts=opts)
+    P.adjoint(Lg, tg, wg, o=o, v=v, n=n, X=X, alpha=-2.0, beta=1.5, opts=opts)
     Rr, _ = oracle.forward(o, v, n, L, tau, w)
     Xr = oracle.adjoint(o, v, n, L, tau, w)
     assert err_norm(R.cpu().numpy(), 0.5 * R0 + Rr) <= TOL
@@ -126,11 +134,12 @@ def test_nan_input_propagates_to_energy(dev):
     assert np.isnan(E)
 
 
-def test_deterministic_bitwise(dev):
+@pytest.mark.parametrize("flags", PATHS)
+def test_deterministic_bitwise(dev, flags):
     o, v, n = 6, 45, 90
     L, tau, w = gaussian_inputs(11, o, v, n)
-    a = run(dev, o, v, n, L, tau, w, P.Options(n_abatch=7))
-    b = run(dev, o, v, n, L, tau, w, P.Options(n_abatch=7))
+    a = run(dev, o, v, n, L, tau, w, P.Options(n_abatch=7, flags=flags))
+    b = run(dev, o, v, n, L, tau, w, P.Options(n_abatch=7, flags=flags))
     assert np.array_equal(a[0], b[0]) and a[1] == b[1] and np.array_equal(a[2], b[2])
 
 
@@ -144,11 +153,12 @@ def test_workspace_too_small_raises(dev):
         P.forward(Lg, tg, wg, o=o, v=v, n=n, R=R, ws=ws)
 
 
-def test_medium_workload(dev):
+@pytest.mark.parametrize("flags", PATHS)
+def test_medium_workload(dev, flags):
     """o=20, v=150, n=600, seed 2: every element of R and X and E against the oracle."""
     o, v, n = 20, 150, 600
     L, tau, tbar, _, _ = oracle.make_inputs(o, v, n, 2)
-    R, E, X = run(dev, o, v, n, L, tau, tbar)
+    R, E, X = run(dev, o, v, n, L, tau, tbar, P.Options(flags=flags))
     Rr, Er = oracle.matrix.forward(o, v, n, L, tau, tbar)
     Xr = oracle.matrix.adjoint(o, v, n, L, tau, tbar)
     print("medium: E %.17g (oracle %.17g) err_R %.3e err_E %.3e err_X %.3e"
@@ -224,12 +234,14 @@ def err_E_terms(E, Er, w, Rr):
     return abs(float(E) - float(Er)) / float(np.abs(np.asarray(w) * np.asarray(Rr)).sum())
 
 
+@pytest.mark.parametrize("flags", PATHS)
 @pytest.mark.parametrize("o,v,n,seed,S", [(2, 5, 3, 1, 3), (3, 4, 2, 2, 2), (2, 33, 21, 4, 3)])
-def test_split_integer_inputs_bitwise(dev, o, v, n, seed, S):
-    """Small integers are carried exactly by two or three slices, and every FP32
-    chunk sum is exact, so the split path must agree bitwise with the oracle."""
+def test_split_integer_inputs_bitwise(dev, o, v, n, seed, S, flags):
+    """Small integers (and the half-integers of the +/- packing) are carried exactly
+    by two or three slices, and every FP32 chunk sum is exact, so the split path
+    must agree bitwise with the oracle."""
     L, tau, w = integer_inputs(seed, o, v, n, lim=3)
-    R, E, X = run(dev, o, v, n, L, tau, w, P.Options(precision=P.SPLIT_BF16, n_slices=S, n_abatch=7))
+    R, E, X = run(dev, o, v, n, L, tau, w, P.Options(precision=P.SPLIT_BF16, n_slices=S, n_abatch=7, flags=flags))
     Rr, Er = oracle.forward(o, v, n, L, tau, w)
     Xr = oracle.adjoint(o, v, n, L, tau, w)
     assert np.array_equal(R, Rr)
@@ -247,11 +259,12 @@ def test_split_tiny_workload(dev):
     assert err_norm(R, Rr) <= SPLIT_TOL_RX and err_rel(E, Er) <= SPLIT_TOL_E and err_norm(X, Xr) <= SPLIT_TOL_RX
 
 
-@pytest.mark.parametrize("o,v,n,nA", [(5, 37, 70, 4), (3, 41, 300, 0), (7, 19, 257, 19), (2, 129, 17, 64)])
-def test_split_ragged_tiles_chunks_batches(dev, o, v, n, nA):
+@pytest.mark.parametrize("flags", PATHS)
+@pytest.mark.parametrize("o,v,n,nA", [(5, 37, 70, 4), (3, 41, 300, 0), (7, 19, 257, 19), (2, 129, 17, 64), (1, 23, 9, 5)])
+def test_split_ragged_tiles_chunks_batches(dev, o, v, n, nA, flags):
     """K not a multiple of the 256 chunk nor of 16, several batches, ragged edges."""
     L, tau, w = gaussian_inputs(200 + v, o, v, n)
-    R, E, X = run(dev, o, v, n, L, tau, w, P.Options(precision=P.SPLIT_BF16, n_slices=5, n_abatch=nA))
+    R, E, X = run(dev, o, v, n, L, tau, w, P.Options(precision=P.SPLIT_BF16, n_slices=5, n_abatch=nA, flags=flags))
     Rr, Er = oracle.forward(o, v, n, L, tau, w)
     Xr = oracle.adjoint(o, v, n, L, tau, w)
     assert err_norm(R, Rr) <= SPLIT_TOL_RX and err_E_terms(E, Er, w, Rr) <= SPLIT_TOL_E and err_norm(X, Xr) <= SPLIT_TOL_RX
