@@ -98,7 +98,8 @@ struct GemmShape {
 
 // Finished-tile visitor: calls epi(m, n, value) for every in-range element and
 // lets the epilogue fold a per-workgroup scalar (used for energy partials).
-template <bool A_KCONTIG, bool B_KCONTIG, class Epi>
+// STAGE only names the instantiation (one kernel symbol per stage in profiles).
+template <bool A_KCONTIG, bool B_KCONTIG, class Epi, int STAGE>
 __global__ __launch_bounds__(F64_THREADS) void gemm_f64_kernel(GemmShape s, Epi epi) {
     __shared__ double As[2][F64_BK * F64_LDS];
     __shared__ double Bs[2][F64_BK * F64_LDS];

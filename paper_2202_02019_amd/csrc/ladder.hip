@@ -296,11 +296,12 @@ Plan make_plan(int64_t o, int64_t v, int64_t n, const ladder_options& op, const 
 }
 
 // ---------------------------------------------------------------- launches
-template <bool AK, bool BK, class Epi>
+template <bool AK, bool BK, int STAGE, class Epi>
 hipError_t launch_gemm(const double* A, int64_t lda, const double* B, int64_t ldb, int64_t M, int64_t N, int64_t K,
                        const Epi& epi, hipStream_t st) {
     GemmShape sh{A, lda, B, ldb, M, N, K};
-    hipLaunchKernelGGL((gemm_f64_kernel<AK, BK, Epi>), dim3((unsigned)tiles(M, N)), dim3(F64_THREADS), 0, st, sh, epi);
+    hipLaunchKernelGGL((gemm_f64_kernel<AK, BK, Epi, STAGE>), dim3((unsigned)tiles(M, N)), dim3(F64_THREADS), 0, st, sh,
+                       epi);
     return hipGetLastError();
 }
 
@@ -316,20 +317,21 @@ SplitOperand view(char* ws, const SlicedBuf& b, int64_t row0) {
     return v;
 }
 
-template <int S, class Epi>
+template <int S, int STAGE, class Epi>
 hipError_t launch_split_s(const SplitShape& sh, const Epi& epi, hipStream_t st) {
-    hipLaunchKernelGGL((gemm_split_kernel<S, Epi>), dim3((unsigned)tiles(sh.M, sh.N)), dim3(SPLIT_THREADS), 0, st, sh, epi);
+    hipLaunchKernelGGL((gemm_split_kernel<S, Epi, STAGE>), dim3((unsigned)tiles(sh.M, sh.N)), dim3(SPLIT_THREADS), 0, st,
+                       sh, epi);
     return hipGetLastError();
 }
 
-template <class Epi>
+template <int STAGE, class Epi>
 hipError_t launch_split(int S, const SplitShape& sh, const Epi& epi, hipStream_t st) {
     switch (S) {
-        case 2: return launch_split_s<2>(sh, epi, st);
-        case 3: return launch_split_s<3>(sh, epi, st);
-        case 4: return launch_split_s<4>(sh, epi, st);
-        case 5: return launch_split_s<5>(sh, epi, st);
-        case 6: return launch_split_s<6>(sh, epi, st);
+        case 2: return launch_split_s<2, STAGE>(sh, epi, st);
+        case 3: return launch_split_s<3, STAGE>(sh, epi, st);
+        case 4: return launch_split_s<4, STAGE>(sh, epi, st);
+        case 5: return launch_split_s<5, STAGE>(sh, epi, st);
+        case 6: return launch_split_s<6, STAGE>(sh, epi, st);
         default: return hipErrorInvalidValue;
     }
 }
@@ -456,10 +458,10 @@ int forward_pm(int64_t o, int64_t v, int64_t n, const double* L, const double* t
             EpiSwapMid eg{g, v, v, v, 1.0, 0.0};
             hipError_t e;
             if (!S) {
-                e = launch_gemm<true, true>(L + a0 * v * n, n, L, n, nA * v, s.vv, n, eg, st);
+                e = launch_gemm<true, true, LADDER_STAGE_GEMM_B>(L + a0 * v * n, n, L, n, nA * v, s.vv, n, eg, st);
             } else {
                 SplitShape sh{view(w, p.L_J, a0 * v), view(w, p.L_J, 0), nA * v, s.vv, n};
-                e = launch_split(S, sh, eg, st);
+                e = launch_split<LADDER_STAGE_GEMM_B>(S, sh, eg, st);
             }
             if ((rc = hip_check(e, "GEMM-B launch"))) return rc;
         }
@@ -483,10 +485,10 @@ int forward_pm(int64_t o, int64_t v, int64_t n, const double* L, const double* t
             EpiStrided er{sign ? rm : rp, N, 1.0, 0.0, nullptr, nullptr};
             hipError_t e;
             if (!S) {
-                e = launch_gemm<true, true>(sign ? tm : tp, K, sign ? gm : gp, K, M, N, K, er, st);
+                e = launch_gemm<true, true, LADDER_STAGE_GEMM_C>(sign ? tm : tp, K, sign ? gm : gp, K, M, N, K, er, st);
             } else {
                 SplitShape sh{view(w, sign ? p.tm_cd : p.tp_cd, 0), view(w, sign ? gms : gps, 0), M, N, K};
-                e = launch_split(S, sh, er, st);
+                e = launch_split<LADDER_STAGE_GEMM_C>(S, sh, er, st);
             }
             if ((rc = hip_check(e, "GEMM-C launch"))) return rc;
         }
@@ -542,10 +544,10 @@ int adjoint_pm(int64_t o, int64_t v, int64_t n, const double* L, const double* t
             EpiStrided ed{sign ? dm : dp, N, 1.0, 0.0, nullptr, nullptr};
             hipError_t e;
             if (!S) {
-                e = launch_gemm<false, false>((sign ? wm : wp) + a0 * v, s.vv, sign ? tm : tp, N, M, N, K, ed, st);
+                e = launch_gemm<false, false, LADDER_STAGE_GEMM_E>((sign ? wm : wp) + a0 * v, s.vv, sign ? tm : tp, N, M, N, K, ed, st);
             } else {
                 SplitShape sh{view(w, sign ? p.wm_ij : p.wp_ij, a0 * v), view(w, sign ? p.tm_ij : p.tp_ij, 0), M, N, K};
-                e = launch_split(S, sh, ed, st);
+                e = launch_split<LADDER_STAGE_GEMM_E>(S, sh, ed, st);
             }
             if ((rc = hip_check(e, "GEMM-E launch"))) return rc;
         }
@@ -568,12 +570,12 @@ int adjoint_pm(int64_t o, int64_t v, int64_t n, const double* L, const double* t
             EpiStrided ex{X + a0 * v * n, n, 2.0 * alpha, beta, nullptr, nullptr};
             hipError_t e;
             if (!S) {
-                e = launch_gemm<true, false>(D, s.vv, L, n, nA * v, n, s.vv, ex, st);
+                e = launch_gemm<true, false, LADDER_STAGE_GEMM_F>(D, s.vv, L, n, nA * v, n, s.vv, ex, st);
             } else {
                 SlicedBuf tl = p.tile_sl;
                 tl.R = nA * v;
                 SplitShape sh{view(w, tl, 0), view(w, p.L_bd, 0), nA * v, n, s.vv};
-                e = launch_split(S, sh, ex, st);
+                e = launch_split<LADDER_STAGE_GEMM_F>(S, sh, ex, st);
             }
             if ((rc = hip_check(e, "GEMM-F launch"))) return rc;
         }
@@ -755,10 +757,10 @@ int ladder_forward(int64_t o, int64_t v, int64_t n, const double* L, const doubl
             EpiSwapMid eg{g, v, v, v, 1.0, 0.0};
             hipError_t e;
             if (!S) {
-                e = launch_gemm<true, true>(L + a0 * v * n, n, L, n, nA * v, s.vv, n, eg, st);
+                e = launch_gemm<true, true, LADDER_STAGE_GEMM_B>(L + a0 * v * n, n, L, n, nA * v, s.vv, n, eg, st);
             } else {
                 SplitShape sh{view(w, p.L_J, a0 * v), view(w, p.L_J, 0), nA * v, s.vv, n};
-                e = launch_split(S, sh, eg, st);
+                e = launch_split<LADDER_STAGE_GEMM_B>(S, sh, eg, st);
             }
             if ((rc = hip_check(e, "GEMM-B launch"))) return rc;
         }
@@ -773,12 +775,12 @@ int ladder_forward(int64_t o, int64_t v, int64_t n, const double* L, const doubl
             EpiStrided er{R + a0 * v, s.vv, 1.0, beta, E ? tbar + a0 * v : nullptr, part + bi * p.part_per_batch};
             hipError_t e;
             if (!S) {
-                e = launch_gemm<true, true>(tau, s.vv, g, s.vv, s.oo, nA * v, s.vv, er, st);
+                e = launch_gemm<true, true, LADDER_STAGE_GEMM_C>(tau, s.vv, g, s.vv, s.oo, nA * v, s.vv, er, st);
             } else {
                 SlicedBuf tl = p.tile_sl;
                 tl.R = nA * v;
                 SplitShape sh{view(w, p.tau_cd, 0), view(w, tl, 0), s.oo, nA * v, s.vv};
-                e = launch_split(S, sh, er, st);
+                e = launch_split<LADDER_STAGE_GEMM_C>(S, sh, er, st);
             }
             if ((rc = hip_check(e, "GEMM-C launch"))) return rc;
         }
@@ -845,11 +847,11 @@ int ladder_adjoint(int64_t o, int64_t v, int64_t n, const double* L, const doubl
             if (!S) {
                 const double* wa = term ? pw : wt;
                 const double* ta = term ? pt : tau;
-                e = launch_gemm<false, false>(wa + a0 * v, s.vv, ta, s.vv, nA * v, s.vv, s.oo, ed, st);
+                e = launch_gemm<false, false, LADDER_STAGE_GEMM_E>(wa + a0 * v, s.vv, ta, s.vv, nA * v, s.vv, s.oo, ed, st);
             } else {
                 SplitShape sh{view(w, term ? p.pw_ij : p.w_ij, a0 * v), view(w, term ? p.ptau_ij : p.tau_ij, 0), nA * v,
                               s.vv, s.oo};
-                e = launch_split(S, sh, ed, st);
+                e = launch_split<LADDER_STAGE_GEMM_E>(S, sh, ed, st);
             }
             if ((rc = hip_check(e, "GEMM-E launch"))) return rc;
         }
@@ -863,12 +865,12 @@ int ladder_adjoint(int64_t o, int64_t v, int64_t n, const double* L, const doubl
             EpiStrided ex{X + a0 * v * n, n, general ? alpha : 2.0 * alpha, beta, nullptr, nullptr};
             hipError_t e;
             if (!S) {
-                e = launch_gemm<true, false>(D, s.vv, L, n, nA * v, n, s.vv, ex, st);
+                e = launch_gemm<true, false, LADDER_STAGE_GEMM_F>(D, s.vv, L, n, nA * v, n, s.vv, ex, st);
             } else {
                 SlicedBuf tl = p.tile_sl;
                 tl.R = nA * v;
                 SplitShape sh{view(w, tl, 0), view(w, p.L_bd, 0), nA * v, n, s.vv};
-                e = launch_split(S, sh, ex, st);
+                e = launch_split<LADDER_STAGE_GEMM_F>(S, sh, ex, st);
             }
             if ((rc = hip_check(e, "GEMM-F launch"))) return rc;
         }
@@ -888,7 +890,7 @@ int ladder_mp2_amplitudes(int64_t o, int64_t v, int64_t n, const double* Lov, co
         return fail(LADDER_EINVAL, "t overlaps an input");
     EpiMP2 ep{t, eps, o, v};
     StageTimer tm(LADDER_STAGE_MP2, gemm_flops(o * v, o * v, n), gemm_bytes(o * v, o * v, n), (hipStream_t)stream);
-    return hip_check(launch_gemm<true, true>(Lov, n, Lov, n, o * v, o * v, n, ep, (hipStream_t)stream),
+    return hip_check(launch_gemm<true, true, LADDER_STAGE_MP2>(Lov, n, Lov, n, o * v, o * v, n, ep, (hipStream_t)stream),
                      "amplitude GEMM launch");
 }
 

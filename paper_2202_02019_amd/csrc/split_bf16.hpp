@@ -221,7 +221,8 @@ struct SplitRing {
     unsigned short t[2][S][SPLIT_TILE_SLOTS * 8];  // [operand A=0/B=1][slice][slots]
 };
 
-template <int S, class Epi>
+// STAGE only names the instantiation (one kernel symbol per stage in profiles).
+template <int S, class Epi, int STAGE>
 __global__ __launch_bounds__(SPLIT_THREADS) void gemm_split_kernel(SplitShape sh, Epi epi) {
     __shared__ __attribute__((aligned(16))) SplitRing<S> ring0, ring1, ring2;
     // chunk exponents, double-buffered by chunk parity: [parity][A=0/B=1][128 rows]

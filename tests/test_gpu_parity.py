@@ -126,12 +126,13 @@ def test_beta_zero_ignores_nan_in_output(dev):
     assert torch.isfinite(R).all() and torch.isfinite(X).all()
 
 
-def test_nan_input_propagates_to_energy(dev):
+@pytest.mark.parametrize("flags", PATHS)
+def test_nan_input_propagates_to_energy(dev, flags):
     o, v, n = 2, 9, 11
     L, tau, w = gaussian_inputs(10, o, v, n)
-    tau[1, 0, 3, 4] = np.nan
-    _, E, _ = run(dev, o, v, n, L, tau, w)
-    assert np.isnan(E)
+    tau[1, 0, 3, 4] = tau[0, 1, 4, 3] = np.nan  # keeps the pair symmetry the packed path relies on
+    _, E, X = run(dev, o, v, n, L, tau, w, P.Options(flags=flags))
+    assert np.isnan(E) and np.isnan(X).any()
 
 
 @pytest.mark.parametrize("flags", PATHS)
