@@ -454,13 +454,15 @@ int forward_pm(int64_t o, int64_t v, int64_t n, const double* L, const double* t
         const int64_t nA = std::min(p.nA, v - a0);
         const int64_t NPb = pm_gp_off(nA, v, a0), NMb = pm_gm_off(nA, v, a0);
         {
-            StageTimer tm_(LADDER_STAGE_GEMM_B, gemm_flops(nA * v, s.vv, n), gemm_bytes(nA * v, s.vv, n), st);
-            EpiSwapMid eg{g, v, v, v, 1.0, 0.0};
+            // only b >= a0 is needed by the packed g: N = (v - a0) v rows of L
+            const int64_t Nb = (v - a0) * v;
+            StageTimer tm_(LADDER_STAGE_GEMM_B, gemm_flops(nA * v, Nb, n), gemm_bytes(nA * v, Nb, n), st);
+            EpiSwapMid eg{g, v, v - a0, v, 1.0, 0.0};
             hipError_t e;
             if (!S) {
-                e = launch_gemm<true, true, LADDER_STAGE_GEMM_B>(L + a0 * v * n, n, L, n, nA * v, s.vv, n, eg, st);
+                e = launch_gemm<true, true, LADDER_STAGE_GEMM_B>(L + a0 * v * n, n, L + a0 * v * n, n, nA * v, Nb, n, eg, st);
             } else {
-                SplitShape sh{view(w, p.L_J, a0 * v), view(w, p.L_J, 0), nA * v, s.vv, n};
+                SplitShape sh{view(w, p.L_J, a0 * v), view(w, p.L_J, a0 * v), nA * v, Nb, n};
                 e = launch_split<LADDER_STAGE_GEMM_B>(S, sh, eg, st);
             }
             if ((rc = hip_check(e, "GEMM-B launch"))) return rc;

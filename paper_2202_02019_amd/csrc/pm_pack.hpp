@@ -92,7 +92,8 @@ __host__ __device__ inline void pm_pack_w_elem(int64_t t, const double* x, int64
     else wm[u] = r[a * v + b] - r[b * v + a];
 }
 
-// g tile g[(a',b)][(c,d)] of batch [a0, a0+nA) -> gp[rowp(a',b)][P(c,d)], gm[rowm(a',b)][Q(c,d)]:
+// g tile g[(a', b-a0)][(c,d)] of batch [a0, a0+nA) (only b >= a0 is formed) ->
+// gp[rowp(a',b)][P(c,d)], gm[rowm(a',b)][Q(c,d)]:
 //   gp = (ac|bd) + (ad|bc) for c < d, (ac|bc) for c = d (the w_cc = 1/2 folded in),
 //   gm = (ac|bd) - (ad|bc).
 __host__ __device__ inline void pm_pack_g_elem(int64_t t, const double* g, int64_t v, int64_t a0, int64_t nA, double* gp,
@@ -113,7 +114,7 @@ __host__ __device__ inline void pm_pack_g_elem(int64_t t, const double* g, int64
     const int64_t b = a0 + ap + (row - (plus ? pm_gp_off(ap, v, a0) : pm_gm_off(ap, v, a0))) + (plus ? 0 : 1);
     int64_t c, d;
     if (plus) pm_unP(col, c, d); else pm_unQ(col, c, d);
-    const double* r = g + (ap * v + b) * vv;
+    const double* r = g + (ap * (v - a0) + (b - a0)) * vv;
     if (plus) gp[u] = c < d ? r[c * v + d] + r[d * v + c] : r[c * v + c];
     else gm[u] = r[c * v + d] - r[d * v + c];
 }

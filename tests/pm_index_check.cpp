@@ -52,11 +52,11 @@ int check(int64_t o, int64_t v, int64_t n, int64_t nA, unsigned long long seed) 
     double worstR = 0, worstD = 0, E = 0, Eref = 0;
     for (int64_t a0 = 0; a0 < v; a0 += nA) {
         const int64_t nb = nA < v - a0 ? nA : v - a0;
-        std::vector<double> gt(nb * v * v * v);
+        std::vector<double> gt(nb * (v - a0) * v * v);  // only b >= a0 is formed
         for (int64_t ap = 0; ap < nb; ++ap)
-            for (int64_t b = 0; b < v; ++b)
+            for (int64_t b = a0; b < v; ++b)
                 for (int64_t c = 0; c < v; ++c)
-                    for (int64_t d = 0; d < v; ++d) gt[((ap * v + b) * v + c) * v + d] = g(a0 + ap, c, b, d);
+                    for (int64_t d = 0; d < v; ++d) gt[((ap * (v - a0) + (b - a0)) * v + c) * v + d] = g(a0 + ap, c, b, d);
         const int64_t NP = pm_gp_off(nb, v, a0), NM = pm_gm_off(nb, v, a0);
         std::vector<double> gp(NP * pm_P2(v)), gm(NM * pm_Q2(v) + 1);
         for (int64_t t = 0; t < pm_g_count(v, a0, nb); ++t) pm_pack_g_elem(t, gt.data(), v, a0, nb, gp.data(), gm.data());
