@@ -154,15 +154,16 @@ __host__ __device__ inline bool pm_unpack_R_elem(int64_t t, const double* rp, co
 
 // D tile [(a',c)][(b,d)] of a batch from dp[(a',b)][P(c,d)] and dm[(a',b)][Q(c,d)]:
 //   D_{ab,cd} = dp[(a,b)][P(min,max)] + s_cd dm[(a,b)][Q(min,max)].
+// Slot t enumerates (a', b, c, d) with d fastest: one (a', b) at a time, so the
+// packed rows being gathered stay in L2 while whole d-runs of D are written.
 __host__ __device__ inline void pm_unpack_D_elem(int64_t t, const double* dp, const double* dm, int64_t v, double* D) {
-    const int64_t vv = v * v, cp = pm_P2(v), cm = pm_Q2(v);
-    const int64_t d = t % v, b = (t / v) % v, ac = t / vv;
-    const int64_t c = ac % v, ap = ac / v;
+    const int64_t cp = pm_P2(v), cm = pm_Q2(v);
+    const int64_t d = t % v, c = (t / v) % v, row = t / (v * v);  // row = a' v + b
+    const int64_t b = row % v, ap = row / v;
     const int64_t lo = c < d ? c : d, hi = c < d ? d : c;
-    const int64_t row = ap * v + b;
     double x = dp[row * cp + pm_P(lo, hi)];
     if (c != d) x += (c < d ? 1.0 : -1.0) * dm[row * cm + pm_Q(lo, hi)];
-    D[t] = x;
+    D[((ap * v + c) * v + b) * v + d] = x;
 }
 
 #define PM_GRID_STRIDE(total) \
