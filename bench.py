@@ -34,6 +34,31 @@ WORKLOADS = {
 PEAK = {"fp64": 78.6, "bf16": 2516.6}  # dense MFMA TFLOP/s, MI355X
 
 
+def gemm_source_hash():
+    """First 16 hex digits of the SHA-256 of the GEMM kernel sources (the code the
+    stored HBM-traffic counters were taken on)."""
+    import hashlib
+    h = hashlib.sha256()
+    for f in ("split_bf16.hpp", "gemm_f64.hpp"):
+        with open(os.path.join(ROOT, "paper_2202_02019_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(workload, precision, kernel):
+    """HBM bytes per launch of `kernel` from the committed rocprofv3 FETCH_SIZE /
+    WRITE_SIZE summary for this workload, or None when there is none or the GEMM
+    sources have changed since the counters were taken."""
+    path = os.path.join(ROOT, "profiles", "traffic_%s_%s_pm.json" % (workload, precision))
+    if not os.path.exists(path):
+        return None
+    with open(path) as fh:
+        rec = json.load(fh)
+    if rec.get("sources_sha256_16") != gemm_source_hash() or kernel not in rec.get("kernels", {}):
+        return None
+    return rec["kernels"][kernel]["bytes"]
+
+
 def nominal_flops(o, v, n):
     return 4.0 * v ** 4 * (n + o * o) + 2.0 * o * o * v * v
 
@@ -135,8 +160,12 @@ def main():
     dom_name, dom = max(stages.items(), key=lambda kv: kv[1]["total_ms"])
     dtype_peak = "fp64" if args.precision == "fp64" else "bf16"
     achieved = dom["flops"] / dom["launches"] / (dom["avg_ms"] * 1e-3) / 1e12
+    default_shape = args.slices in (0, 5) and args.n_abatch == (8 if args.precision == "split" else 16)
+    traffic = measured_traffic(name, args.precision, dom_name) if default_shape else None
     roofline = {"bound": "mfma", "kernel": dom_name, "achieved": achieved, "peak": PEAK[dtype_peak],
-                "unit": "TFLOP/s", "frac": achieved / PEAK[dtype_peak], "traffic": None,
+                "unit": "TFLOP/s", "frac": achieved / PEAK[dtype_peak], "traffic": traffic,
+                "traffic_unit": "bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-kernel scaled)",
+                "algorithmic_bytes": dom["bytes"] / dom["launches"],
                 "avg_launch_ms": dom["avg_ms"], "launches_per_step": dom["launches"] / steps}
     if args.precision == "split":
         S = args.slices or 5

@@ -408,6 +408,20 @@ __global__ void amplitude_update_kernel(const double* __restrict__ eps, const do
     }
 }
 
+// Grid of the tiled packing kernels: tile pairs in x, rows over (y, z).
+dim3 pm_grid(int64_t v, int64_t rows) {
+    const int64_t gy = std::min<int64_t>(std::max<int64_t>(rows, 1), 65535);
+    return dim3((unsigned)pm_tile_pairs(v), (unsigned)gy, (unsigned)((rows + gy - 1) / gy));
+}
+
+// Packs amplitudes x[o][o][v][v] to xp[P(i,j)][P(c,d)] and xm[Q(i,j)][Q(c,d)].
+void pm_pack_amp(const double* x, int64_t o, int64_t v, double* xp, double* xm, hipStream_t st) {
+    const PmRows rw{0, o, 0, 0};
+    hipLaunchKernelGGL(pm_pack_sym_tiled_kernel, pm_grid(v, pm_P2(o)), dim3(256), 0, st, x, v, rw, pm_P2(o), 1, xp);
+    if (pm_Q2(o) > 0 && pm_Q2(v) > 0)
+        hipLaunchKernelGGL(pm_pack_sym_tiled_kernel, pm_grid(v, pm_Q2(o)), dim3(256), 0, st, x, v, rw, pm_Q2(o), 0, xm);
+}
+
 unsigned grid_for(int64_t total) {
     int64_t g = (total + 255) / 256;
     if (g > 65536) g = 65536;
@@ -440,7 +454,7 @@ int forward_pm(int64_t o, int64_t v, int64_t n, const double* L, const double* t
            *gm = (double*)(w + p.f_gm), *rp = (double*)(w + p.f_rp), *rm = (double*)(w + p.f_rm);
     {
         StageTimer tm_(LADDER_STAGE_PACK, 0.0, 16.0 * (double)pm_amp_count(o, v), st);
-        hipLaunchKernelGGL(pm_pack_amp_kernel, dim3(grid_for(pm_amp_count(o, v))), dim3(256), 0, st, tau, o, v, tp, tm);
+        pm_pack_amp(tau, o, v, tp, tm, st);
         if ((rc = hip_check(hipGetLastError(), "pack launch"))) return rc;
     }
     const bool minus = p.Q2o > 0 && p.Q2v > 0;
@@ -470,7 +484,10 @@ int forward_pm(int64_t o, int64_t v, int64_t n, const double* L, const double* t
         {
             const int64_t cnt = pm_g_count(v, a0, nA);
             StageTimer tm_(LADDER_STAGE_PACK, 0.0, 24.0 * (double)cnt, st);
-            hipLaunchKernelGGL(pm_pack_g_kernel, dim3(grid_for(cnt)), dim3(256), 0, st, g, v, a0, nA, gp, gm);
+            const PmRows rw{1, 0, a0, nA};
+            hipLaunchKernelGGL(pm_pack_sym_tiled_kernel, pm_grid(v, NPb), dim3(256), 0, st, g, v, rw, NPb, 1, gp);
+            if (NMb > 0 && p.Q2v > 0)
+                hipLaunchKernelGGL(pm_pack_sym_tiled_kernel, pm_grid(v, NMb), dim3(256), 0, st, g, v, rw, NMb, 0, gm);
             if ((rc = hip_check(hipGetLastError(), "pack launch"))) return rc;
         }
         const bool minus_b = minus && NMb > 0;
@@ -523,8 +540,10 @@ int adjoint_pm(int64_t o, int64_t v, int64_t n, const double* L, const double* t
            *tm = (double*)(w + p.a_tm), *dp = (double*)(w + p.a_dp), *dm = (double*)(w + p.a_dm);
     {
         StageTimer tm_(LADDER_STAGE_PACK, 0.0, 16.0 * (double)(pm_amp_count(o, v) + pm_w_count(o, v)), st);
-        hipLaunchKernelGGL(pm_pack_amp_kernel, dim3(grid_for(pm_amp_count(o, v))), dim3(256), 0, st, tau, o, v, tp, tm);
-        hipLaunchKernelGGL(pm_pack_w_kernel, dim3(grid_for(pm_w_count(o, v))), dim3(256), 0, st, wt, o, v, wp, wm);
+        pm_pack_amp(tau, o, v, tp, tm, st);
+        hipLaunchKernelGGL(pm_pack_w_tiled_kernel, pm_grid(v, p.P2o), dim3(256), 0, st, wt, o, v, p.P2o, 1, wp);
+        if (p.Q2o > 0)
+            hipLaunchKernelGGL(pm_pack_w_tiled_kernel, pm_grid(v, p.Q2o), dim3(256), 0, st, wt, o, v, p.Q2o, 0, wm);
         if ((rc = hip_check(hipGetLastError(), "pack launch"))) return rc;
     }
     const bool minus = p.Q2o > 0 && p.Q2v > 0;
@@ -559,7 +578,7 @@ int adjoint_pm(int64_t o, int64_t v, int64_t n, const double* L, const double* t
         }
         {
             StageTimer tm_(LADDER_STAGE_UNPACK, 0.0, 24.0 * (double)(nA * s.vvv), st);
-            hipLaunchKernelGGL(pm_unpack_D_kernel, dim3(grid_for(nA * s.vvv)), dim3(256), 0, st, dp, dm, v, nA, D);
+            hipLaunchKernelGGL(pm_unpack_D_tiled_kernel, pm_grid(v, nA * v), dim3(256), 0, st, dp, dm, v, nA * v, D);
             if ((rc = hip_check(hipGetLastError(), "unpack launch"))) return rc;
         }
         if (S) {

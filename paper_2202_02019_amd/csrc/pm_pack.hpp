@@ -16,9 +16,11 @@
 // contraction and the (c,d) range: 1/2 of the dense work.
 //
 // Pair indices: P(i,j) = j(j+1)/2 + i for i <= j, Q(i,j) = j(j-1)/2 + i for i < j.
-// Every kernel is a grid-stride loop over one element function; the element
-// functions are host-callable so that the index arithmetic can be checked on the
-// CPU against the dense definition.
+// The element functions below define every packed value; they are host-callable
+// so that the index arithmetic can be checked on the CPU against the dense
+// definition.  The R unpack kernel is a grid-stride loop over its element
+// function; the pack and D-unpack kernels are LDS-tiled (end of file) and the
+// host check compares them with the element functions bit for bit.
 #pragma once
 #include <hip/hip_runtime.h>
 #include <math.h>
@@ -169,22 +171,6 @@ __host__ __device__ inline void pm_unpack_D_elem(int64_t t, const double* dp, co
 #define PM_GRID_STRIDE(total) \
     for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < (total); t += (int64_t)gridDim.x * blockDim.x)
 
-__global__ void pm_pack_amp_kernel(const double* __restrict__ x, int64_t o, int64_t v, double* __restrict__ xp,
-                                   double* __restrict__ xm) {
-    PM_GRID_STRIDE(pm_amp_count(o, v)) pm_pack_amp_elem(t, x, o, v, xp, xm);
-}
-__global__ void pm_pack_w_kernel(const double* __restrict__ x, int64_t o, int64_t v, double* __restrict__ wp,
-                                 double* __restrict__ wm) {
-    PM_GRID_STRIDE(pm_w_count(o, v)) pm_pack_w_elem(t, x, o, v, wp, wm);
-}
-__global__ void pm_pack_g_kernel(const double* __restrict__ g, int64_t v, int64_t a0, int64_t nA, double* __restrict__ gp,
-                                 double* __restrict__ gm) {
-    PM_GRID_STRIDE(pm_g_count(v, a0, nA)) pm_pack_g_elem(t, g, v, a0, nA, gp, gm);
-}
-__global__ void pm_unpack_D_kernel(const double* __restrict__ dp, const double* __restrict__ dm, int64_t v, int64_t nA,
-                                   double* __restrict__ D) {
-    PM_GRID_STRIDE(nA * v * v * v) pm_unpack_D_elem(t, dp, dm, v, D);
-}
 // Needs all threads of the block (it has a barrier); one energy partial per block.
 __global__ void pm_unpack_R_kernel(const double* __restrict__ rp, const double* __restrict__ rm, int64_t o, int64_t v,
                                    int64_t a0, int64_t nA, double beta, const double* __restrict__ tbar,
@@ -205,6 +191,191 @@ __global__ void pm_unpack_R_kernel(const double* __restrict__ rp, const double* 
         for (int k = 0; k < (int)(blockDim.x >> 6); ++k) s += red[k];
         partial[blockIdx.x] = s;
     }
+}
+
+}  // namespace ladder
+
+namespace ladder {
+
+// ---------------------------------------------------------------------------
+// Tiled forms of the packing kernels.  A v x v matrix is processed in 32 x 32
+// tile pairs (Cb, Db), Cb <= Db: a workgroup stages M[Cb][Db] and M[Db][Cb]
+// through LDS with row-contiguous reads and writes the packed (or unpacked)
+// values contiguously, so every fetched line is used whole by one workgroup (the
+// element-wise kernels above gather with a stride of about v).  Each tile body is
+// split at its barrier into host-callable parts taking (tid, nthreads), so the
+// host check can run the same code with one thread; the values equal those of
+// the element functions above.
+constexpr int PM_T = 32;
+typedef double PmTile[PM_T][PM_T + 1];
+
+__host__ __device__ inline int64_t pm_tile_pairs(int64_t v) {
+    const int64_t nb = (v + PM_T - 1) / PM_T;
+    return nb * (nb + 1) / 2;
+}
+
+// A[r][q] = M[c0+r][d0+q], B[r][q] = M[d0+r][c0+q] (zero outside v x v).
+__host__ __device__ inline void pm_stage_pair(const double* M, int64_t v, int64_t c0, int64_t d0, PmTile& A, PmTile& B,
+                                              int tid, int nth) {
+    for (int e = tid; e < PM_T * PM_T; e += nth) {
+        const int r = e / PM_T, q = e % PM_T;
+        A[r][q] = (c0 + r < v && d0 + q < v) ? M[(c0 + r) * v + d0 + q] : 0.0;
+        B[r][q] = (d0 + r < v && c0 + q < v) ? M[(d0 + r) * v + c0 + q] : 0.0;
+    }
+}
+
+// Source matrix of packed row r.  mode 0 (amplitudes): r = P(i,j) / Q(i,j) of an
+// o x o pair index, source i o + j.  mode 1 (g tile of batch [a0, a0+nA)):
+// r = rowp / rowm(a', b), source a'(v - a0) + b - a0.
+struct PmRows {
+    int mode;
+    int64_t o;       // mode 0
+    int64_t a0, nA;  // mode 1
+};
+__host__ __device__ inline int64_t pm_src_row(const PmRows& rw, int64_t v, int64_t r, bool plus) {
+    int64_t i, j;
+    if (rw.mode == 0) {
+        if (plus) pm_unP(r, i, j); else pm_unQ(r, i, j);
+        return i * rw.o + j;
+    }
+    const int64_t a0 = rw.a0, nA = rw.nA;
+    const double K2 = 2.0 * (double)(plus ? v - a0 : v - a0 - 1) + 1.0;
+    int64_t ap = (int64_t)(0.5 * (K2 - sqrt(fmax(K2 * K2 - 8.0 * (double)r, 0.0))));
+    if (ap < 0) ap = 0;
+    if (ap > nA - 1) ap = nA - 1;
+    while (ap > 0 && (plus ? pm_gp_off(ap, v, a0) : pm_gm_off(ap, v, a0)) > r) --ap;
+    while (ap + 1 < nA && (plus ? pm_gp_off(ap + 1, v, a0) : pm_gm_off(ap + 1, v, a0)) <= r) ++ap;
+    const int64_t b = a0 + ap + (r - (plus ? pm_gp_off(ap, v, a0) : pm_gm_off(ap, v, a0))) + (plus ? 0 : 1);
+    return ap * (v - a0) + (b - a0);
+}
+
+// Packed row r, tile pair (c0, d0), from the staged A, B:
+//   plus:  out[P(c,d)] = off (M_cd + M_dc) for c < d, M_cc for c = d,
+//   minus: out[Q(c,d)] = off (M_cd - M_dc),
+// off = 1/2 for amplitudes (mode 0), 1 for g (mode 1, the w_cc = 1/2 folded in).
+__host__ __device__ inline void pm_pack_sym_tile(const PmTile& A, const PmTile& B, int64_t v, int64_t c0, int64_t d0,
+                                                 bool plus, double off, double* o, int tid, int nth) {
+    for (int e = tid; e < PM_T * PM_T; e += nth) {
+        const int q = e / PM_T, rr = e % PM_T;  // d offset, c offset (c is contiguous in the packed index)
+        const int64_t c = c0 + rr, d = d0 + q;
+        if (c >= v || d >= v || (plus ? c > d : c >= d)) continue;
+        const double mcd = A[rr][q], mdc = B[q][rr];
+        if (plus) o[pm_P(c, d)] = c == d ? mcd : off * (mcd + mdc);
+        else o[pm_Q(c, d)] = off * (mcd - mdc);
+    }
+}
+
+// w row (i,j), full (a,b): wp = (2 - delta_ij)(M + M^T)/2, wm = M - M^T.
+__host__ __device__ inline void pm_pack_w_tile(const PmTile& A, const PmTile& B, int64_t v, int64_t c0, int64_t d0,
+                                               bool plus, bool diag_ij, double* ow, int tid, int nth) {
+    const double f = plus && diag_ij ? 0.5 : 1.0, sg = plus ? 1.0 : -1.0;
+    const bool same = c0 == d0;
+    for (int e = tid; e < PM_T * PM_T; e += nth) {
+        const int rr = e / PM_T, q = e % PM_T;  // row offset, contiguous column offset
+        if (c0 + rr < v && d0 + q < v) ow[(c0 + rr) * v + d0 + q] = f * (A[rr][q] + sg * B[q][rr]);
+        if (!same && d0 + rr < v && c0 + q < v) ow[(d0 + rr) * v + c0 + q] = f * (B[rr][q] + sg * A[q][rr]);
+    }
+}
+
+// D tile: stage packed row (a', b): Pp[q][rr] = dp[P(c,d)], Pm[q][rr] = dm[Q(c,d)]
+// for (c, d) = (c0 + rr, d0 + q), c <= d (zero elsewhere).
+__host__ __device__ inline void pm_stage_D(const double* prow, const double* mrow, int64_t v, int64_t c0, int64_t d0,
+                                           PmTile& Pp, PmTile& Pm, int tid, int nth) {
+    for (int e = tid; e < PM_T * PM_T; e += nth) {
+        const int q = e / PM_T, rr = e % PM_T;
+        const int64_t c = c0 + rr, d = d0 + q;
+        const bool in = c < v && d < v && c <= d;
+        Pp[q][rr] = in ? prow[pm_P(c, d)] : 0.0;
+        Pm[q][rr] = (in && c < d) ? mrow[pm_Q(c, d)] : 0.0;
+    }
+}
+// D_{ab,cd} = dp + s_cd dm written at D[((a' v + c) v + b) v + d] for the tile pair.
+__host__ __device__ inline void pm_unpack_D_tile(const PmTile& Pp, const PmTile& Pm, int64_t v, int64_t ap, int64_t b,
+                                                 int64_t c0, int64_t d0, double* D, int tid, int nth) {
+    const bool same = c0 == d0;
+    for (int e = tid; e < PM_T * PM_T; e += nth) {
+        const int rr = e / PM_T, q = e % PM_T;  // output row offset, contiguous column offset
+        {   // (c, d) = (c0 + rr, d0 + q), c <= d
+            const int64_t c = c0 + rr, d = d0 + q;
+            if (c < v && d < v && (!same || rr <= q)) D[((ap * v + c) * v + b) * v + d] = Pp[q][rr] + Pm[q][rr];
+        }
+        {   // (d, c) = (d0 + rr, c0 + q), d > c: D_{ab,dc} = dp - dm
+            const int64_t d = d0 + rr, c = c0 + q;
+            if (c < v && d < v && (!same || q < rr)) D[((ap * v + d) * v + b) * v + c] = Pp[rr][q] - Pm[rr][q];
+        }
+    }
+}
+
+// Whole-block bodies: the kernels below run them with (threadIdx.x, blockDim.x)
+// and a barrier, the host check with (0, 1) and no barrier.
+struct PmBarrier {
+    __device__ void operator()() const { __syncthreads(); }
+};
+struct PmNoBarrier {
+    __host__ __device__ void operator()() const {}
+};
+
+// Packed row r of a symmetric / antisymmetric pack, tile pair tpair.
+template <class Sync>
+__host__ __device__ inline void pm_pack_sym_block(const double* src, int64_t v, const PmRows& rw, int64_t r, int64_t tpair,
+                                                  bool plus, double* out, PmTile& A, PmTile& B, int tid, int nth, Sync sync) {
+    int64_t cb, db;
+    pm_unP(tpair, cb, db);
+    const int64_t c0 = cb * PM_T, d0 = db * PM_T;
+    pm_stage_pair(src + pm_src_row(rw, v, r, plus) * v * v, v, c0, d0, A, B, tid, nth);
+    sync();
+    pm_pack_sym_tile(A, B, v, c0, d0, plus, rw.mode == 0 ? 0.5 : 1.0, out + r * (plus ? pm_P2(v) : pm_Q2(v)), tid, nth);
+}
+// w row r = P(i,j) (plus) or Q(i,j) (minus), tile pair tpair.
+template <class Sync>
+__host__ __device__ inline void pm_pack_w_block(const double* src, int64_t o, int64_t v, int64_t r, int64_t tpair, bool plus,
+                                                double* out, PmTile& A, PmTile& B, int tid, int nth, Sync sync) {
+    int64_t cb, db, i, j;
+    pm_unP(tpair, cb, db);
+    if (plus) pm_unP(r, i, j); else pm_unQ(r, i, j);
+    const int64_t c0 = cb * PM_T, d0 = db * PM_T;
+    pm_stage_pair(src + (i * o + j) * v * v, v, c0, d0, A, B, tid, nth);
+    sync();
+    pm_pack_w_tile(A, B, v, c0, d0, plus, i == j, out + r * v * v, tid, nth);
+}
+// D rows of packed row (a', b) = row, tile pair tpair.
+template <class Sync>
+__host__ __device__ inline void pm_unpack_D_block(const double* dp, const double* dm, int64_t v, int64_t row, int64_t tpair,
+                                                  double* D, PmTile& Pp, PmTile& Pm, int tid, int nth, Sync sync) {
+    int64_t cb, db;
+    pm_unP(tpair, cb, db);
+    const int64_t c0 = cb * PM_T, d0 = db * PM_T;
+    pm_stage_D(dp + row * pm_P2(v), dm + row * pm_Q2(v), v, c0, d0, Pp, Pm, tid, nth);
+    sync();
+    pm_unpack_D_tile(Pp, Pm, v, row / v, row % v, c0, d0, D, tid, nth);
+}
+
+// Launch shape of the tiled kernels: grid.x = tile pairs, rows over (y, z); the
+// row test is uniform per block, so every thread of a working block reaches the barrier.
+__device__ inline int64_t pm_block_row() { return (int64_t)blockIdx.y + (int64_t)blockIdx.z * gridDim.y; }
+
+__global__ __launch_bounds__(256) void pm_pack_sym_tiled_kernel(const double* __restrict__ src, int64_t v, PmRows rw,
+                                                                 int64_t nrows, int plus, double* __restrict__ out) {
+    __shared__ PmTile A, B;
+    const int64_t r = pm_block_row();
+    if (r >= nrows) return;
+    pm_pack_sym_block(src, v, rw, r, blockIdx.x, plus != 0, out, A, B, threadIdx.x, blockDim.x, PmBarrier{});
+}
+
+__global__ __launch_bounds__(256) void pm_pack_w_tiled_kernel(const double* __restrict__ src, int64_t o, int64_t v,
+                                                               int64_t nrows, int plus, double* __restrict__ out) {
+    __shared__ PmTile A, B;
+    const int64_t r = pm_block_row();
+    if (r >= nrows) return;
+    pm_pack_w_block(src, o, v, r, blockIdx.x, plus != 0, out, A, B, threadIdx.x, blockDim.x, PmBarrier{});
+}
+
+__global__ __launch_bounds__(256) void pm_unpack_D_tiled_kernel(const double* __restrict__ dp, const double* __restrict__ dm,
+                                                                 int64_t v, int64_t nrows, double* __restrict__ D) {
+    __shared__ PmTile Pp, Pm;
+    const int64_t row = pm_block_row();
+    if (row >= nrows) return;
+    pm_unpack_D_block(dp, dm, v, row, blockIdx.x, D, Pp, Pm, threadIdx.x, blockDim.x, PmBarrier{});
 }
 
 }  // namespace ladder

@@ -1,6 +1,8 @@
 // Host check of the +/- packing index arithmetic (pm_pack.hpp) against the dense
 // definitions, run on the CPU (built by tests/test_pm_host.py with AddressSanitizer
-// on host code, so any index outside a packed buffer aborts).
+// on host code, so any index outside a packed buffer aborts).  The tiled block
+// bodies that the device kernels run are executed here with one thread and must
+// reproduce the element functions bit for bit.
 //   R_ij^ab = sum_cd (ac|bd) tau_ij^cd,  D_{ab,cd} = sum_ij tbar_ij^ab tau_ij^cd.
 #include <math.h>
 #include <stdio.h>
@@ -15,6 +17,23 @@ using namespace ladder;
 static double rnd(unsigned long long& s) {
     s = s * 6364136223846793005ULL + 1442695040888963407ULL;
     return ((double)(s >> 11) * 0x1.0p-53) - 0.5;
+}
+
+// Runs a block body over every (row, tile pair) like the device grid does.
+template <class Body>
+static void run_tiled(int64_t v, int64_t rows, Body body) {
+    PmTile A, B;
+    for (int64_t r = 0; r < rows; ++r)
+        for (int64_t t = 0; t < pm_tile_pairs(v); ++t) body(r, t, A, B);
+}
+
+static int same(const std::vector<double>& x, const std::vector<double>& y, int64_t count, const char* what) {
+    for (int64_t k = 0; k < count; ++k)
+        if (!(x[k] == y[k])) {
+            printf("tiled %s differs at %lld: %.17g vs %.17g\n", what, (long long)k, x[k], y[k]);
+            return 1;
+        }
+    return 0;
 }
 
 int check(int64_t o, int64_t v, int64_t n, int64_t nA, unsigned long long seed) {
@@ -48,6 +67,21 @@ int check(int64_t o, int64_t v, int64_t n, int64_t nA, unsigned long long seed) 
     std::vector<double> tp(pm_P2(o) * pm_P2(v)), tm(pm_Q2(o) * pm_Q2(v) + 1), wp(pm_P2(o) * v * v), wm(pm_Q2(o) * v * v + 1);
     for (int64_t t = 0; t < pm_amp_count(o, v); ++t) pm_pack_amp_elem(t, tau.data(), o, v, tp.data(), tm.data());
     for (int64_t t = 0; t < pm_w_count(o, v); ++t) pm_pack_w_elem(t, tb.data(), o, v, wp.data(), wm.data());
+    int bad = 0;
+    {
+        std::vector<double> tp2(tp.size(), NAN), tm2(tm.size(), NAN), wp2(wp.size(), NAN), wm2(wm.size(), NAN);
+        const PmRows rw{0, o, 0, 0};
+        run_tiled(v, pm_P2(o), [&](int64_t r, int64_t t, PmTile& A, PmTile& B) {
+            pm_pack_sym_block(tau.data(), v, rw, r, t, true, tp2.data(), A, B, 0, 1, PmNoBarrier{});
+            pm_pack_w_block(tb.data(), o, v, r, t, true, wp2.data(), A, B, 0, 1, PmNoBarrier{});
+        });
+        run_tiled(v, pm_Q2(o), [&](int64_t r, int64_t t, PmTile& A, PmTile& B) {
+            pm_pack_sym_block(tau.data(), v, rw, r, t, false, tm2.data(), A, B, 0, 1, PmNoBarrier{});
+            pm_pack_w_block(tb.data(), o, v, r, t, false, wm2.data(), A, B, 0, 1, PmNoBarrier{});
+        });
+        bad |= same(tp2, tp, pm_P2(o) * pm_P2(v), "tau+") | same(tm2, tm, pm_Q2(o) * pm_Q2(v), "tau-");
+        bad |= same(wp2, wp, pm_P2(o) * v * v, "w+") | same(wm2, wm, pm_Q2(o) * v * v, "w-");
+    }
     std::vector<double> R(o * o * v * v, NAN);
     double worstR = 0, worstD = 0, E = 0, Eref = 0;
     for (int64_t a0 = 0; a0 < v; a0 += nA) {
@@ -60,6 +94,18 @@ int check(int64_t o, int64_t v, int64_t n, int64_t nA, unsigned long long seed) 
         const int64_t NP = pm_gp_off(nb, v, a0), NM = pm_gm_off(nb, v, a0);
         std::vector<double> gp(NP * pm_P2(v)), gm(NM * pm_Q2(v) + 1);
         for (int64_t t = 0; t < pm_g_count(v, a0, nb); ++t) pm_pack_g_elem(t, gt.data(), v, a0, nb, gp.data(), gm.data());
+        {
+            std::vector<double> gp2(gp.size(), NAN), gm2(gm.size(), NAN);
+            const PmRows rw{1, 0, a0, nb};
+            run_tiled(v, NP, [&](int64_t r, int64_t t, PmTile& A, PmTile& B) {
+                pm_pack_sym_block(gt.data(), v, rw, r, t, true, gp2.data(), A, B, 0, 1, PmNoBarrier{});
+            });
+            if (pm_Q2(v) > 0)
+                run_tiled(v, NM, [&](int64_t r, int64_t t, PmTile& A, PmTile& B) {
+                    pm_pack_sym_block(gt.data(), v, rw, r, t, false, gm2.data(), A, B, 0, 1, PmNoBarrier{});
+                });
+            bad |= same(gp2, gp, NP * pm_P2(v), "g+") | same(gm2, gm, NM * pm_Q2(v), "g-");
+        }
         std::vector<double> rp(pm_P2(o) * NP), rm(pm_Q2(o) * NM + 1);
         for (int64_t p = 0; p < pm_P2(o); ++p)
             for (int64_t r = 0; r < NP; ++r) {
@@ -93,6 +139,13 @@ int check(int64_t o, int64_t v, int64_t n, int64_t nA, unsigned long long seed) 
             }
         }
         for (int64_t t = 0; t < nb * v * v * v; ++t) pm_unpack_D_elem(t, dp.data(), dm.data(), v, D.data());
+        {
+            std::vector<double> D2(D.size(), NAN);
+            run_tiled(v, nb * v, [&](int64_t r, int64_t t, PmTile& A, PmTile& B) {
+                pm_unpack_D_block(dp.data(), dm.data(), v, r, t, D2.data(), A, B, 0, 1, PmNoBarrier{});
+            });
+            bad |= same(D2, D, nb * v * v * v, "D");
+        }
         for (int64_t ap = 0; ap < nb; ++ap)
             for (int64_t c = 0; c < v; ++c)
                 for (int64_t b = 0; b < v; ++b)
@@ -110,7 +163,7 @@ int check(int64_t o, int64_t v, int64_t n, int64_t nA, unsigned long long seed) 
     }
     printf("o=%lld v=%lld n=%lld nA=%lld  max|dR| %.3e  max|dD| %.3e  |dE| %.3e\n", (long long)o, (long long)v, (long long)n,
            (long long)nA, worstR, worstD, fabs(E - Eref));
-    return (worstR < 1e-12 && worstD < 1e-12 && fabs(E - Eref) < 1e-11) ? 0 : 1;
+    return (!bad && worstR < 1e-12 && worstD < 1e-12 && fabs(E - Eref) < 1e-11) ? 0 : 1;
 }
 
 int main() {
@@ -121,6 +174,8 @@ int main() {
     bad |= check(4, 7, 2, 3, 4);
     bad |= check(2, 9, 4, 9, 5);
     bad |= check(5, 6, 3, 4, 6);
+    bad |= check(2, 37, 2, 11, 7);   // two tile blocks, ragged
+    bad |= check(3, 70, 1, 33, 8);   // three tile blocks, ragged batches
     printf(bad ? "FAIL\n" : "OK\n");
     return bad;
 }

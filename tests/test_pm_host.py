@@ -1,5 +1,7 @@
-"""Host check of the +/- packing index arithmetic against the dense definitions
-(the device kernels are grid-stride loops over these same element functions)."""
+"""Host check of the +/- packing index arithmetic against the dense definitions.
+The element functions define every packed value; the tiled block bodies that the
+pack and D-unpack kernels run are executed on the host with one thread and must
+match the element functions bit for bit."""
 import os
 import shutil
 import subprocess
