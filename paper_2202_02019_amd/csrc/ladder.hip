@@ -309,9 +309,9 @@ hipError_t launch_gemm(const double* A, int64_t lda, const double* B, int64_t ld
 SplitOperand view(char* ws, const SlicedBuf& b, int64_t row0) {
     SplitOperand v;
     const int64_t Kp = split_kpad(b.K);
-    v.s = (const unsigned short*)(ws + b.s_off) + row0 * Kp;
+    v.s = (const unsigned short*)(ws + b.s_off) + row0 * 16;
     v.slice_stride = b.R * Kp;
-    v.ld = Kp;
+    v.kstride = b.R * 16;
     v.e = (const int*)(ws + b.e_off) + row0;
     v.e_ld = b.R;
     return v;
@@ -341,9 +341,8 @@ hipError_t slice_s(bool transposed, const double* src, int64_t ld, int64_t R, in
                    hipStream_t st) {
     const int64_t nch = split_nchunk(K);
     if (!transposed) {
-        const int64_t jobs = R * nch;
-        hipLaunchKernelGGL((slice_rows_kernel<S>), dim3((unsigned)((jobs + 3) / 4)), dim3(256), 0, st, src, ld, R, K, sl,
-                           ex, R);
+        const int64_t blocks = ((R + 15) / 16) * nch;
+        hipLaunchKernelGGL((slice_rows_kernel<S>), dim3((unsigned)blocks), dim3(256), 0, st, src, ld, R, K, sl, ex, R);
     } else {
         const int64_t blocks = ((R + 31) / 32) * nch;
         hipLaunchKernelGGL((slice_cols_kernel<S>), dim3((unsigned)blocks), dim3(256), 0, st, src, ld, R, K, sl, ex, R);
@@ -432,9 +431,10 @@ unsigned grid_for(int64_t total) {
 // The split GEMM addresses a 128-row operand tile with 32-bit byte offsets.
 int check_split_dims(const Sizes& s, int64_t n, const ladder_options& op) {
     if (op.precision != LADDER_SPLIT_BF16) return LADDER_OK;
+    // the slicer grids: up to v^2 rows in blocks of 16 times the chunks of the longest k
     const int64_t kmax = std::max(std::max(s.vv, s.oo), n);
-    if (split_kpad(kmax) * 2 * SPLIT_BM >= (int64_t(1) << 32))
-        return fail(LADDER_EUNSUPPORTED, "split precision needs v^2, o^2 and n below 2^24");
+    if ((s.vv / 16 + 1) * split_nchunk(kmax) >= (int64_t(1) << 31))
+        return fail(LADDER_EUNSUPPORTED, "split precision: v^2 * max(v^2, o^2, n) too large for the slicer grid");
     return LADDER_OK;
 }
 

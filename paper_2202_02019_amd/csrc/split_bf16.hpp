@@ -76,44 +76,53 @@ __device__ inline void write_slices(double x, int e, unsigned short* out, int64_
 }
 
 // ---------------------------------------------------------------- slicers
+// Slice layout ("k-blocked"): slice p of an R-row operand is R x Kp BF16 values
+// (Kp = split_kpad(K), zero beyond K) stored as Kp/16 blocks of [R rows][16 k]:
+// element (r, k) of slice p sits at  p*R*Kp + (k/16)*R*16 + r*16 + k%16.
+// One GEMM K-step (16 k) of a 128-row tile is then one contiguous 4 KB run, so
+// every cache line the tile loads is used whole in the same step.
+// Exponents: [nchunk][R] (chunk stride exp_ld).
+__host__ __device__ inline int64_t split_index(int64_t r, int64_t k, int64_t R) { return (k >> 4) * R * 16 + r * 16 + (k & 15); }
+
 // K-contiguous source: element (r, k) at src[r*ld + k], r < R, k < K.
-// One wave per (row, chunk).  slices: [S][R][Kp] (row stride Kp = split_kpad(K));
-// exps: [nchunk][R] (chunk stride ldexp_rows).
+// One workgroup per 16 rows and one chunk: thread (rr, kk) = (t/16, t%16) holds
+// k = chunk*256 + 16*kb + kk for kb < 16, so each k-block of the 16 rows is written
+// as one 512-byte run per slice.
 template <int S>
 __global__ __launch_bounds__(256) void slice_rows_kernel(const double* __restrict__ src, int64_t ld, int64_t R,
                                                          int64_t K, unsigned short* __restrict__ slices,
                                                          int* __restrict__ exps, int64_t exp_ld) {
-    const int lane = threadIdx.x & 63;
+    constexpr int RB = 16, NKB = SPLIT_KC / 16;
     const int64_t nch = split_nchunk(K), Kp = split_kpad(K);
-    const int64_t job = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
-    if (job >= R * nch) return;
-    const int64_t r = job / nch, ch = job - r * nch;
-    double x[SPLIT_KC / 64];
+    const int64_t rblocks = (R + RB - 1) / RB;
+    const int64_t rb = blockIdx.x % rblocks, ch = blockIdx.x / rblocks;
+    const int rr = threadIdx.x >> 4, kk = threadIdx.x & 15;
+    const int64_t r = rb * RB + rr;
+    if (ch >= nch) return;  // uniform per block
+    double x[NKB];
     double mx = 0.0;
-    bool bad = false;
 #pragma unroll
-    for (int t = 0; t < SPLIT_KC / 64; ++t) {
-        const int64_t k = ch * SPLIT_KC + lane + 64 * t;
-        x[t] = k < K ? src[r * ld + k] : 0.0;
-        mx = fmax(mx, fabs(x[t]));
-        bad |= !__builtin_isfinite(x[t]);
+    for (int kb = 0; kb < NKB; ++kb) {
+        const int64_t k = ch * SPLIT_KC + 16 * kb + kk;
+        x[kb] = (r < R && k < K) ? src[r * ld + k] : 0.0;
+        mx = fmax(mx, fabs(x[kb]));
     }
 #pragma unroll
-    for (int off = 32; off > 0; off >>= 1) mx = fmax(mx, __shfl_xor(mx, off));
+    for (int off = 8; off > 0; off >>= 1) mx = fmax(mx, __shfl_xor(mx, off));  // the 16 lanes of row rr
+    if (r >= R) return;
     const int e = chunk_exponent(mx);
-    if (lane == 0) exps[ch * exp_ld + r] = e;
-    (void)bad;
+    if (kk == 0) exps[ch * exp_ld + r] = e;
     const int64_t slice_stride = R * Kp;
 #pragma unroll
-    for (int t = 0; t < SPLIT_KC / 64; ++t) {
-        const int64_t k = ch * SPLIT_KC + lane + 64 * t;
-        if (k < Kp) write_slices<S>(x[t], e, slices + r * Kp + k, slice_stride);
+    for (int kb = 0; kb < NKB; ++kb) {
+        const int64_t k = ch * SPLIT_KC + 16 * kb + kk;
+        if (k < Kp) write_slices<S>(x[kb], e, slices + split_index(r, k, R), slice_stride);
     }
 }
 
 // Transposed source: element (r, k) at src[k*ld + r].  One workgroup per 32 rows
 // and one chunk, staged through LDS so that both the reads (along r) and the
-// slice writes (along k) are contiguous.
+// k-blocked slice writes are contiguous.
 template <int S>
 __global__ __launch_bounds__(256) void slice_cols_kernel(const double* __restrict__ src, int64_t ld, int64_t R,
                                                          int64_t K, unsigned short* __restrict__ slices,
@@ -142,22 +151,28 @@ __global__ __launch_bounds__(256) void slice_cols_kernel(const double* __restric
     for (int off = 4; off > 0; off >>= 1) mx = fmax(mx, __shfl_xor(mx, off));
     if (part == 0) ex[rr] = chunk_exponent(mx);
     __syncthreads();
-    const int64_t r = r0 + rr;
-    if (r >= R) return;
-    const int e = ex[rr];
-    if (part == 0) exps[ch * exp_ld + r] = e;
+    if (part == 0 && r0 + rr < R) exps[ch * exp_ld + r0 + rr] = ex[rr];
+    // writes: thread (wr, kk) = (t/16, t%16) covers rows wr and wr + 16 of every
+    // k-block, so a block's 32 rows x 16 k go out as one 1 KB run per slice
     const int64_t slice_stride = R * Kp;
-    for (int i = 0; i < 32; ++i) {
-        const int64_t k = k0 + part * 32 + i;
-        if (k < Kp) write_slices<S>(tile[part * 32 + i][rr], e, slices + r * Kp + k, slice_stride);
+    const int wr = tid >> 4, kk = tid & 15;
+    for (int kb = 0; kb < SPLIT_KC / 16; ++kb) {
+        const int64_t k = k0 + 16 * kb + kk;
+        if (k >= Kp) break;
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+            const int row = wr + 16 * h;
+            const int64_t r = r0 + row;
+            if (r < R) write_slices<S>(tile[16 * kb + kk][row], ex[row], slices + split_index(r, k, R), slice_stride);
+        }
     }
 }
 
 // ---------------------------------------------------------------- split GEMM
 struct SplitOperand {
-    const unsigned short* s;  // slice 0 of row 0 of this operand view
-    int64_t slice_stride;     // elements between slices
-    int64_t ld;               // = Kp
+    const unsigned short* s;  // slice 0, k-block 0, row 0 of this operand view
+    int64_t slice_stride;     // elements between slices (R * Kp of the sliced buffer)
+    int64_t kstride;          // elements between 16-k blocks (R * 16 of the sliced buffer); rows are 16 apart
     const int* e;             // exponent of (row 0, chunk 0) of this view
     int64_t e_ld;             // chunk stride of the exponent array
 };
@@ -251,8 +266,9 @@ __global__ __launch_bounds__(SPLIT_THREADS) void gemm_split_kernel(SplitShape sh
     const int drow = slot >> 1;
     const int dhalf = (slot & 1) ^ (((drow >> 2) ^ (drow >> 3)) & 1);
     // rows past the edge load a valid row; their results are never stored
-    const unsigned dvoff = (unsigned)(((drow < last ? drow : last) * op.ld + 8 * dhalf) * 2);
-    const unsigned short* dbase = (const unsigned short*)uniform_ptr(op.s + row0 * op.ld);
+    const unsigned dvoff = (unsigned)(((drow < last ? drow : last) * 16 + 8 * dhalf) * 2);
+    const unsigned short* dbase = (const unsigned short*)uniform_ptr(op.s + row0 * 16);
+    const int64_t dkstride = op.kstride;
     const int64_t dstride = op.slice_stride;
     const int64_t e_ld = op.e_ld;
     const int erow = 64 * dq + lane;
@@ -262,7 +278,7 @@ __global__ __launch_bounds__(SPLIT_THREADS) void gemm_split_kernel(SplitShape sh
     auto dma = [&](SplitRing<S>& rg, int64_t kt) {
 #pragma unroll
         for (int p = 0; p < S; ++p)
-            lds_dma16(uniform_ptr(dbase + p * dstride + kt * SPLIT_BK), dvoff, lds_addr(&rg.t[dop][p][64 * dq * 8]));
+            lds_dma16(uniform_ptr(dbase + p * dstride + kt * dkstride), dvoff, lds_addr(&rg.t[dop][p][64 * dq * 8]));
         if (dq < 2 && kt % STEPS_PER_CHUNK == 0) {
             const int64_t ch = kt / STEPS_PER_CHUNK;
             lds_dma4(uniform_ptr(ebase + ch * e_ld), evoff, lds_addr(&lexp[ch & 1][dop][64 * dq]));
