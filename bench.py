@@ -76,6 +76,8 @@ def main():
     ap.add_argument("--cpu-rows", type=int, default=1, help="a (and p) rows the CPU baseline computes; 0 = skip")
     ap.add_argument("--no-compare", action="store_true",
                     help="skip the untimed FP64 leg that the split path is compared with")
+    ap.add_argument("--tau-gradient", action="store_true",
+                    help="also time the transposed ladder (dE/dtau) once on the same inputs and check a sampled row")
     ap.add_argument("--copy-probe", action="store_true",
                     help="run a 1 GiB device copy first (reference kernel for the HBM traffic counters)")
     args = ap.parse_args()
@@ -125,7 +127,10 @@ def main():
     E = torch.empty((), dtype=torch.float64, device=dev)
     prec = P.FP64 if args.precision == "fp64" else P.SPLIT_BF16
     opts = P.Options(precision=prec, n_slices=args.slices, n_abatch=args.n_abatch)
-    ws = torch.empty(P.workspace_size(o, v, n, opts), dtype=torch.uint8, device=dev)
+    wsb = P.workspace_size(o, v, n, opts)
+    if args.tau_gradient:
+        wsb = max(wsb, P.tau_gradient_workspace_size(o, v, n, opts))
+    ws = torch.empty(wsb, dtype=torch.uint8, device=dev)
     torch.cuda.synchronize()
     print("bench: %s o=%d v=%d n=%d precision=%s inputs ready in %.1fs, workspace %.2f GiB"
           % (name, o, v, n, args.precision, time.time() - t0, ws.numel() / 2 ** 30), file=sys.stderr, flush=True)
@@ -203,6 +208,26 @@ def main():
         del R64, X64, ws64
         print("bench: fp64 comparison step %.1f s" % (ms64 / 1e3), file=sys.stderr, flush=True)
 
+    tgrad = None
+    if args.tau_gradient:
+        # dE/dtau = transposed ladder of tbar; nominal flops as the forward (2 n v^4 + 2 o^2 v^4)
+        G = torch.empty_like(R)
+        torch.cuda.synchronize()
+        ev0.record(stream)
+        P.tau_gradient(L, tbar, o=o, v=v, n=n, G=G, ws=ws, opts=opts)
+        ev1.record(stream)
+        torch.cuda.synchronize()
+        mst = ev0.elapsed_time(ev1)
+        Ft = 2.0 * n * v ** 4 + 2.0 * o * o * v ** 4
+        import oracle
+        c0 = time.time()
+        Gr = oracle.matrix.tau_gradient(o, v, n, L.cpu().numpy(), tbar.cpu().numpy(), c_range=(0, 1))
+        tgrad = {"ms": mst, "nominal_flops": Ft, "tflops": Ft / (mst * 1e-3) / 1e12,
+                 "err_sample_row_c0": float(np.abs(G[:, :, :1, :].cpu().numpy() - Gr).max() / np.abs(Gr).max()),
+                 "oracle_row_seconds": time.time() - c0}
+        del G
+        print("bench: tau gradient %.1f s" % (mst / 1e3), file=sys.stderr, flush=True)
+
     cpu = None
     errs = {}
     if args.cpu_rows > 0:
@@ -241,6 +266,7 @@ def main():
         "executed_gemm_flops": executed,
         "executed_gemm_tflops": executed / (ms * 1e-3) / 1e12,
         "fp64_comparison": compare,
+        "tau_gradient": tgrad,
     }
     out.update(errs)
     print(json.dumps(out))

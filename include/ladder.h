@@ -123,6 +123,24 @@ int ladder_adjoint(int64_t o, int64_t v, int64_t n, const double* L, const doubl
                    size_t ws_bytes, const ladder_options* opts, void* stream);
 
 /*
+ * Transposed ladder: the gradient of the ladder energy with respect to the
+ * amplitudes, i.e. the A2-term contribution to the multiplier equations
+ * (tbar A = -eta, Sec. II A):
+ *   G = beta * G + d/dtau [ sum_ijab w_ij^ab ladder(L, tau)_ij^ab ]
+ *   G_ij^cd (+)= sum_ab w_ij^ab (sum_J L^J_ac L^J_bd)
+ * This is ladder_forward applied to w with every L^J replaced by its transpose
+ * (L^J_ac -> L^J_ca); the library writes that transpose into the workspace, so
+ * the call needs ladder_tau_gradient_workspace_size bytes (the forward workspace
+ * plus v^2 n doubles).  Options as for ladder_forward (the default +/- path needs
+ * pair-symmetric w, for which G is pair-symmetric too).  With beta == 0, G is
+ * not read.  G must not overlap L, w or ws.
+ */
+int ladder_tau_gradient_workspace_size(int64_t o, int64_t v, int64_t n, const ladder_options* opts,
+                                       size_t* bytes);
+int ladder_tau_gradient(int64_t o, int64_t v, int64_t n, const double* L, const double* w, double beta,
+                        double* G, void* ws, size_t ws_bytes, const ladder_options* opts, void* stream);
+
+/*
  * First-order doubles amplitudes from the occupied-virtual Cholesky block (the
  * synthetic stand-in for converged T2; Cholesky expansion of Sec. II A):
  *   t_ij^ab = (sum_J L^J_ia L^J_jb) / ((eps_i + eps_j) - (eps_a + eps_b)).

@@ -22,6 +22,10 @@
  *                                                 the L-built three-index intermediate
  *                                                 (2 W~^J_pq of Sec. II C) restricted to
  *                                                 the V^4 density block of Sec. II B.
+ *   G_ij^cd = dE/dtau_ij^cd = sum_ab w_ij^ab g_acbd
+ *                                                 the transposed ladder: the A2-term part
+ *                                                 of the multiplier equations tbar A = -eta
+ *                                                 (Sec. II A), E being linear in tau.
  *
  * The adjoint is written in its general form: it does NOT assume the pair
  * symmetry tau_ij^ab = tau_ji^ba (Appendix A, d_pqrs = d_rspq), so a GPU path that
@@ -146,6 +150,58 @@ int oracle_ladder_forward_range(int64_t o, int64_t v, int64_t n, const double* L
 int oracle_ladder_forward(int64_t o, int64_t v, int64_t n, const double* L, const double* tau,
                           const double* tbar, double* R, double* E) {
     return oracle_ladder_forward_range(o, v, n, L, tau, tbar, 0, v, R, NULL, E);
+}
+
+/*
+ * Transposed ladder for the range c in [c_lo, c_hi), general L (no symmetry of
+ * L^J in its two indices assumed):
+ *   h_c[a][b][d]  = sum_J L[a][c][J] L[b][d][J]           (= g_acbd)
+ *   G[i][j][c][d] = sum_a sum_b w[i][j][a][b] h_c[a][b][d].
+ * Rows c outside the range are left untouched.
+ */
+int oracle_ladder_tau_gradient_range(int64_t o, int64_t v, int64_t n, const double* L,
+                                     const double* w, int64_t c_lo, int64_t c_hi, double* G) {
+    if (bad_dims(o, v, n) || !L || !w || !G || c_lo < 0 || c_hi > v || c_lo > c_hi) return -1;
+    const int64_t oo = o * o, vv = v * v;
+    int fail = 0;
+#pragma omp parallel
+    {
+        double* h = (double*)malloc((size_t)(v * vv) * sizeof(double));
+        if (!h) {
+#pragma omp atomic write
+            fail = 1;
+        }
+#pragma omp for schedule(dynamic, 1)
+        for (int64_t c = c_lo; c < c_hi; ++c) {
+            if (!h) continue;
+            for (int64_t a = 0; a < v; ++a) {
+                const double* Lac = L + (a * v + c) * n;
+                for (int64_t b = 0; b < v; ++b)
+                    for (int64_t d = 0; d < v; ++d) {
+                        const double* Lbd = L + (b * v + d) * n;
+                        double s = 0.0;
+                        for (int64_t J = 0; J < n; ++J) s += Lac[J] * Lbd[J];
+                        h[(a * v + b) * v + d] = s;
+                    }
+            }
+            for (int64_t ij = 0; ij < oo; ++ij) {
+                const double* wij = w + ij * vv;
+                for (int64_t d = 0; d < v; ++d) {
+                    double s = 0.0;
+                    for (int64_t a = 0; a < v; ++a)
+                        for (int64_t b = 0; b < v; ++b) s += wij[a * v + b] * h[(a * v + b) * v + d];
+                    G[ij * vv + c * v + d] = s;
+                }
+            }
+        }
+        free(h);
+    }
+    return fail ? -1 : 0;
+}
+
+int oracle_ladder_tau_gradient(int64_t o, int64_t v, int64_t n, const double* L, const double* w,
+                               double* G) {
+    return oracle_ladder_tau_gradient_range(o, v, n, L, w, 0, v, G);
 }
 
 /*

@@ -53,3 +53,19 @@ def adjoint(o, v, n, L, tau, w, p_range=None):
         C = D1.reshape(v, v, v).transpose(1, 0, 2) + D2.reshape(v, v, v).transpose(2, 0, 1)  # C[q, b, d]
         X[p - p_lo] = C.reshape(v, v * v) @ Lbd
     return X
+
+
+def tau_gradient(o, v, n, L, w, c_range=None):
+    """G_ij^cd = sum_ab w_ij^ab (ac|bd), general L (the transposed ladder).
+
+    With c_range = (c_lo, c_hi) only those rows are formed ([o][o][c_hi-c_lo][v]).
+    """
+    L = np.ascontiguousarray(L, dtype=np.float64).reshape(v, v, n)
+    W = np.ascontiguousarray(w, dtype=np.float64).reshape(o * o, v * v)  # [ij, (a,b)]
+    Lbd = L.reshape(v * v, n)
+    c_lo, c_hi = (0, v) if c_range is None else c_range
+    G = np.empty((o * o, c_hi - c_lo, v))
+    for c in range(c_lo, c_hi):
+        h = np.ascontiguousarray(L[:, c, :]) @ Lbd.T       # h[a, (b,d)] = sum_J L^J_ac L^J_bd
+        G[:, c - c_lo, :] = W @ h.reshape(v * v, v)        # G_ij^cd = sum_ab w_ij^ab h[(a,b), d]
+    return G.reshape(o, o, c_hi - c_lo, v)

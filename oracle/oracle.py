@@ -22,7 +22,8 @@ LIB = os.path.join(HERE, "liboracle.so")
 
 __all__ = [
     "build", "load", "forward", "adjoint", "forward_range", "adjoint_range", "R_sample",
-    "X_sample", "mp2_amplitudes", "amplitude_update", "make_inputs", "num_threads",
+    "X_sample", "tau_gradient", "tau_gradient_range", "mp2_amplitudes", "amplitude_update", "make_inputs",
+    "num_threads",
     "set_num_threads", "flops_forward", "flops_adjoint", "matrix",
 ]
 
@@ -51,12 +52,14 @@ def load():
         lib.oracle_ladder_adjoint_range.argtypes = [i64, i64, i64, dp, dp, dp, i64, i64, dp]
         lib.oracle_ladder_R_sample.argtypes = [i64, i64, i64, dp, dp, i64, vp, dp]
         lib.oracle_ladder_X_sample.argtypes = [i64, i64, i64, dp, dp, dp, i64, vp, dp]
+        lib.oracle_ladder_tau_gradient_range.argtypes = [i64, i64, i64, dp, dp, i64, i64, dp]
         lib.oracle_mp2_amplitudes.argtypes = [i64, i64, i64, dp, dp, dp]
         lib.oracle_amplitude_update.argtypes = [i64, i64, dp, dp, dp]
         lib.oracle_num_threads.restype = ctypes.c_int
         lib.oracle_set_num_threads.argtypes = [ctypes.c_int]
         for f in ("oracle_ladder_forward_range", "oracle_ladder_adjoint_range", "oracle_ladder_R_sample",
-                  "oracle_ladder_X_sample", "oracle_mp2_amplitudes", "oracle_amplitude_update"):
+                  "oracle_ladder_X_sample", "oracle_ladder_tau_gradient_range", "oracle_mp2_amplitudes",
+                  "oracle_amplitude_update"):
             getattr(lib, f).restype = ctypes.c_int
         _lib = lib
     return _lib
@@ -113,6 +116,22 @@ def adjoint_range(o, v, n, L, tau, w, p_lo, p_hi, X=None):
 def adjoint(o, v, n, L, tau, w):
     """X [v][v][n] = dE/dL with E = sum w * R(L, tau), general (no symmetry assumed)."""
     return adjoint_range(o, v, n, L, tau, w, 0, v)
+
+
+def tau_gradient_range(o, v, n, L, w, c_lo, c_hi, G=None):
+    """G_ij^cd = sum_ab w_ij^ab (ac|bd) for rows c in [c_lo, c_hi) (others untouched)."""
+    L = _f64(L, (v, v, n)); w = _f64(w, (o, o, v, v))
+    if G is None:
+        G = np.zeros((o, o, v, v))
+    rc = load().oracle_ladder_tau_gradient_range(o, v, n, _p(L), _p(w), c_lo, c_hi, _p(G))
+    if rc != 0:
+        raise RuntimeError("oracle_ladder_tau_gradient_range failed")
+    return G
+
+
+def tau_gradient(o, v, n, L, w):
+    """G [o][o][v][v] = dE/dtau with E = sum w * R(L, tau) (the transposed ladder), general L."""
+    return tau_gradient_range(o, v, n, L, w, 0, v)
 
 
 def R_sample(o, v, n, L, tau, ab):

@@ -705,63 +705,10 @@ int ensure_branch_streams(int dev) {
     return LADDER_OK;
 }
 
-}  // namespace
-
-extern "C" {
-
-void ladder_default_options(ladder_options* o) {
-    if (!o) return;
-    memset(o, 0, sizeof *o);
-    o->precision = LADDER_FP64;
-}
-
-const char* ladder_strerror(int code) {
-    switch (code) {
-        case LADDER_OK: return "success";
-        case LADDER_EINVAL: return "invalid argument";
-        case LADDER_EWORKSPACE: return "workspace too small";
-        case LADDER_EUNSUPPORTED: return "unsupported option";
-        case LADDER_EHIP: return "HIP runtime error";
-        default: return "unknown error code";
-    }
-}
-
-const char* ladder_last_error(void) { return g_last_error.c_str(); }
-
-int ladder_workspace_size(int64_t o, int64_t v, int64_t n, const ladder_options* opts, size_t* bytes) {
-    g_last_error.clear();
-    if (!bytes) return fail(LADDER_EINVAL, "bytes is NULL");
-    Sizes s;
-    ladder_options op;
+// Forward ladder on validated arguments (ladder_forward, ladder_tau_gradient).
+int forward_impl(int64_t o, int64_t v, int64_t n, const double* L, const double* tau, const double* tbar, double beta,
+                 double* R, double* E, char* w, const Plan& p, const Sizes& s, hipStream_t st) {
     int rc;
-    if ((rc = check_dims(o, v, n, s)) || (rc = get_opts(opts, op)) || (rc = check_split_dims(s, n, op))) return rc;
-    *bytes = make_plan(o, v, n, op, s).total;
-    return LADDER_OK;
-}
-
-int ladder_forward(int64_t o, int64_t v, int64_t n, const double* L, const double* tau, const double* tbar,
-                   double beta, double* R, double* E, void* ws, size_t ws_bytes, const ladder_options* opts,
-                   void* stream) {
-    g_last_error.clear();
-    Sizes s;
-    ladder_options op;
-    int rc;
-    if ((rc = check_dims(o, v, n, s)) || (rc = get_opts(opts, op)) || (rc = check_split_dims(s, n, op))) return rc;
-    if (!L || !tau || !R || !ws) return fail(LADDER_EINVAL, "L, tau, R and ws must be non-NULL");
-    if (E && !tbar) return fail(LADDER_EINVAL, "E requested but tbar is NULL");
-    if (!aligned8(L) || !aligned8(tau) || !aligned8(R) || (tbar && !aligned8(tbar)) || (E && !aligned8(E)) ||
-        ((uintptr_t)ws % ALIGN))
-        return fail(LADDER_EINVAL, "misaligned pointer (arrays need 8-byte, ws 256-byte alignment)");
-    const Plan p = make_plan(o, v, n, op, s);
-    if (ws_bytes < p.fwd_total) return fail(LADDER_EWORKSPACE, "workspace of %zu bytes, %zu needed", ws_bytes, p.fwd_total);
-    const int64_t tb = s.ovv_elems * 8, lb = s.vvn * 8;
-    if (overlap(R, tb, L, lb) || overlap(R, tb, tau, tb) || overlap(R, tb, tbar, tb) || overlap(R, tb, ws, (int64_t)ws_bytes))
-        return fail(LADDER_EINVAL, "R overlaps an input or the workspace");
-    if (E && (overlap(E, 8, R, tb) || overlap(E, 8, ws, (int64_t)ws_bytes)))
-        return fail(LADDER_EINVAL, "E overlaps R or the workspace");
-
-    hipStream_t st = (hipStream_t)stream;
-    char* w = (char*)ws;
     if (p.pm) return forward_pm(o, v, n, L, tau, tbar, beta, R, E, w, p, s, st);
     double* g = (double*)(w + p.tile_off);
     double* part = (double*)(w + p.part_off);
@@ -816,6 +763,116 @@ int ladder_forward(int64_t o, int64_t v, int64_t n, const double* L, const doubl
         if ((rc = hip_check(hipGetLastError(), "energy reduction launch"))) return rc;
     }
     return LADDER_OK;
+}
+
+// Shared argument checks of ladder_forward and ladder_tau_gradient: out (o^2 v^2
+// doubles) must not overlap the inputs or the workspace.
+int check_forward_args(int64_t o, int64_t v, int64_t n, const double* L, const double* x, const double* tbar, double* out,
+                       double* E, void* ws, size_t ws_bytes, size_t need, const char* out_name, const Sizes& s) {
+    if (!L || !x || !out || !ws) return fail(LADDER_EINVAL, "L, the amplitudes, %s and ws must be non-NULL", out_name);
+    if (E && !tbar) return fail(LADDER_EINVAL, "E requested but tbar is NULL");
+    if (!aligned8(L) || !aligned8(x) || !aligned8(out) || (tbar && !aligned8(tbar)) || (E && !aligned8(E)) ||
+        ((uintptr_t)ws % ALIGN))
+        return fail(LADDER_EINVAL, "misaligned pointer (arrays need 8-byte, ws 256-byte alignment)");
+    if (ws_bytes < need) return fail(LADDER_EWORKSPACE, "workspace of %zu bytes, %zu needed", ws_bytes, need);
+    const int64_t tb = s.ovv_elems * 8, lb = s.vvn * 8;
+    if (overlap(out, tb, L, lb) || overlap(out, tb, x, tb) || overlap(out, tb, tbar, tb) ||
+        overlap(out, tb, ws, (int64_t)ws_bytes))
+        return fail(LADDER_EINVAL, "%s overlaps an input or the workspace", out_name);
+    if (E && (overlap(E, 8, out, tb) || overlap(E, 8, ws, (int64_t)ws_bytes)))
+        return fail(LADDER_EINVAL, "E overlaps %s or the workspace", out_name);
+    (void)o; (void)v; (void)n;
+    return LADDER_OK;
+}
+
+// LT[(c v + a) n + J] = L[(a v + c) n + J]: one workgroup per (a, c) row of n.
+__global__ void transpose_pairs_kernel(const double* __restrict__ L, int64_t v, int64_t n, double* __restrict__ LT) {
+    for (int64_t row = blockIdx.x; row < v * v; row += gridDim.x) {
+        const int64_t a = row / v, c = row % v;
+        const double* src = L + row * n;
+        double* dst = LT + (c * v + a) * n;
+        for (int64_t J = threadIdx.x; J < n; J += blockDim.x) dst[J] = src[J];
+    }
+}
+
+}  // namespace
+
+extern "C" {
+
+void ladder_default_options(ladder_options* o) {
+    if (!o) return;
+    memset(o, 0, sizeof *o);
+    o->precision = LADDER_FP64;
+}
+
+const char* ladder_strerror(int code) {
+    switch (code) {
+        case LADDER_OK: return "success";
+        case LADDER_EINVAL: return "invalid argument";
+        case LADDER_EWORKSPACE: return "workspace too small";
+        case LADDER_EUNSUPPORTED: return "unsupported option";
+        case LADDER_EHIP: return "HIP runtime error";
+        default: return "unknown error code";
+    }
+}
+
+const char* ladder_last_error(void) { return g_last_error.c_str(); }
+
+int ladder_workspace_size(int64_t o, int64_t v, int64_t n, const ladder_options* opts, size_t* bytes) {
+    g_last_error.clear();
+    if (!bytes) return fail(LADDER_EINVAL, "bytes is NULL");
+    Sizes s;
+    ladder_options op;
+    int rc;
+    if ((rc = check_dims(o, v, n, s)) || (rc = get_opts(opts, op)) || (rc = check_split_dims(s, n, op))) return rc;
+    *bytes = make_plan(o, v, n, op, s).total;
+    return LADDER_OK;
+}
+
+int ladder_forward(int64_t o, int64_t v, int64_t n, const double* L, const double* tau, const double* tbar,
+                   double beta, double* R, double* E, void* ws, size_t ws_bytes, const ladder_options* opts,
+                   void* stream) {
+    g_last_error.clear();
+    Sizes s;
+    ladder_options op;
+    int rc;
+    if ((rc = check_dims(o, v, n, s)) || (rc = get_opts(opts, op)) || (rc = check_split_dims(s, n, op))) return rc;
+    const Plan p = make_plan(o, v, n, op, s);
+    if ((rc = check_forward_args(o, v, n, L, tau, tbar, R, E, ws, ws_bytes, p.fwd_total, "R", s))) return rc;
+    return forward_impl(o, v, n, L, tau, tbar, beta, R, E, (char*)ws, p, s, (hipStream_t)stream);
+}
+
+int ladder_tau_gradient_workspace_size(int64_t o, int64_t v, int64_t n, const ladder_options* opts, size_t* bytes) {
+    g_last_error.clear();
+    if (!bytes) return fail(LADDER_EINVAL, "bytes is NULL");
+    Sizes s;
+    ladder_options op;
+    int rc;
+    if ((rc = check_dims(o, v, n, s)) || (rc = get_opts(opts, op)) || (rc = check_split_dims(s, n, op))) return rc;
+    *bytes = align_up(make_plan(o, v, n, op, s).fwd_total) + align_up((size_t)s.vvn * 8);
+    return LADDER_OK;
+}
+
+int ladder_tau_gradient(int64_t o, int64_t v, int64_t n, const double* L, const double* w, double beta, double* G,
+                        void* ws, size_t ws_bytes, const ladder_options* opts, void* stream) {
+    g_last_error.clear();
+    Sizes s;
+    ladder_options op;
+    int rc;
+    if ((rc = check_dims(o, v, n, s)) || (rc = get_opts(opts, op)) || (rc = check_split_dims(s, n, op))) return rc;
+    const Plan p = make_plan(o, v, n, op, s);
+    const size_t lt_off = align_up(p.fwd_total);
+    const size_t need = lt_off + align_up((size_t)s.vvn * 8);
+    if ((rc = check_forward_args(o, v, n, L, w, nullptr, G, nullptr, ws, ws_bytes, need, "G", s))) return rc;
+    hipStream_t st = (hipStream_t)stream;
+    double* LT = (double*)((char*)ws + lt_off);
+    {
+        StageTimer tm(LADDER_STAGE_PACK, 0.0, 16.0 * (double)s.vvn, st);
+        hipLaunchKernelGGL(transpose_pairs_kernel, dim3((unsigned)std::min<int64_t>(s.vv, 1 << 20)), dim3(256), 0, st, L,
+                           v, n, LT);
+        if ((rc = hip_check(hipGetLastError(), "transpose launch"))) return rc;
+    }
+    return forward_impl(o, v, n, LT, w, nullptr, beta, G, nullptr, (char*)ws, p, s, st);
 }
 
 int ladder_adjoint(int64_t o, int64_t v, int64_t n, const double* L, const double* tau, const double* wt,

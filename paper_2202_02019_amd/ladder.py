@@ -25,6 +25,7 @@ DO_ADJOINT = 2
 
 EXPORTS = (
     "ladder_default_options", "ladder_workspace_size", "ladder_forward", "ladder_adjoint",
+    "ladder_tau_gradient_workspace_size", "ladder_tau_gradient",
     "ladder_mp2_amplitudes", "ladder_amplitude_update", "ladder_batched_workspace_size",
     "ladder_batched", "ladder_strerror", "ladder_last_error", "ladder_shutdown",
     "ladder_profile_start", "ladder_profile_stop",
@@ -88,12 +89,15 @@ def _load():
     lib.ladder_workspace_size.argtypes = [i64, i64, i64, op, ctypes.POINTER(sz)]
     lib.ladder_forward.argtypes = [i64, i64, i64, vp, vp, vp, dbl, vp, vp, vp, sz, op, vp]
     lib.ladder_adjoint.argtypes = [i64, i64, i64, vp, vp, vp, dbl, dbl, vp, vp, sz, op, vp]
+    lib.ladder_tau_gradient_workspace_size.argtypes = [i64, i64, i64, op, ctypes.POINTER(sz)]
+    lib.ladder_tau_gradient.argtypes = [i64, i64, i64, vp, vp, dbl, vp, vp, sz, op, vp]
     lib.ladder_mp2_amplitudes.argtypes = [i64, i64, i64, vp, vp, vp, vp]
     lib.ladder_amplitude_update.argtypes = [i64, i64, vp, vp, vp, vp]
     lib.ladder_batched_workspace_size.argtypes = [ctypes.c_int, ctypes.POINTER(_CInstance), ctypes.c_uint32, op,
                                                   ctypes.POINTER(sz)]
     lib.ladder_batched.argtypes = [ctypes.c_int, ctypes.POINTER(_CInstance), ctypes.c_uint32, vp, sz, op, vp]
-    for f in ("ladder_workspace_size", "ladder_forward", "ladder_adjoint", "ladder_mp2_amplitudes",
+    for f in ("ladder_workspace_size", "ladder_forward", "ladder_adjoint", "ladder_tau_gradient_workspace_size",
+              "ladder_tau_gradient", "ladder_mp2_amplitudes",
               "ladder_amplitude_update", "ladder_batched_workspace_size", "ladder_batched"):
         getattr(lib, f).restype = ctypes.c_int
     lib.ladder_strerror.argtypes = [ctypes.c_int]
@@ -204,6 +208,25 @@ def adjoint(L, tau, w, *, o, v, n, X=None, alpha=1.0, beta=0.0, ws=None, opts=No
     return X
 
 
+def tau_gradient_workspace_size(o: int, v: int, n: int, opts=None) -> int:
+    b = ctypes.c_size_t(0)
+    _check(_load().ladder_tau_gradient_workspace_size(o, v, n, ctypes.byref(_opts(opts)), ctypes.byref(b)))
+    return b.value
+
+
+def tau_gradient(L, w, *, o, v, n, G=None, beta=0.0, ws=None, opts=None, stream=None):
+    """G = beta*G + d/dtau sum(w * ladder(L, tau)) = sum_ab w_ij^ab (ac|bd) (the transposed ladder)."""
+    _need(L, "L", (v, v, n)); _need(w, "w", (o, o, v, v))
+    if G is None:
+        G = torch.empty((o, o, v, v), dtype=torch.float64, device=L.device)
+    _need(G, "G", (o, o, v, v))
+    c = _opts(opts)
+    wsb = _workspace(tau_gradient_workspace_size(o, v, n, c), L.device, ws)
+    _check(_load().ladder_tau_gradient(o, v, n, _ptr(L), _ptr(w), float(beta), _ptr(G), _ptr(wsb),
+                                       wsb.numel() * wsb.element_size(), ctypes.byref(c), _stream(stream)))
+    return G
+
+
 def mp2_amplitudes(Lov, eps, *, o, v, n, t=None, stream=None):
     _need(Lov, "Lov", (o, v, n)); _need(eps, "eps", (o + v,))
     if t is None:
@@ -272,8 +295,9 @@ class LadderEnergy(torch.autograd.Function):
     """E(L, tau, tbar) = sum tbar * ladder(L, tau) with the library adjoint as backward.
 
     backward gives dE/dL = X (hand-written adjoint, g recomputed per batch, nothing
-    of the forward kept but the inputs) and dE/dtbar = R.  dE/dtau (the transposed
-    ladder) is not provided: asking for it raises.
+    of the forward kept but the inputs), dE/dtau = the transposed ladder of tbar and
+    dE/dtbar = R.  With the default options the inputs must be pair-symmetric (the
+    +/- packed path); pass Options(flags=FLAG_GENERAL) otherwise.
     """
 
     @staticmethod
@@ -288,15 +312,15 @@ class LadderEnergy(torch.autograd.Function):
     def backward(ctx, gE):
         L, tau, tbar, R = ctx.saved_tensors
         o, v, n = ctx.dims
+        gL = gtau = gt = None
         if ctx.needs_input_grad[1]:
-            raise NotImplementedError("dE/dtau (the transposed ladder) is not implemented")
-        gL = gt = None
+            gtau = tau_gradient(L, tbar, o=o, v=v, n=n, opts=ctx.opts) * gE
         if ctx.needs_input_grad[0]:
             X = adjoint(L, tau, tbar, o=o, v=v, n=n, opts=ctx.opts)
             gL = X * gE
         if ctx.needs_input_grad[2]:
             gt = R * gE
-        return gL, None, gt, None, None
+        return gL, gtau, gt, None, None
 
 
 def ladder_energy(L, tau, tbar, dims, opts=None):

@@ -83,6 +83,31 @@ def test_adjoint_validation():
     assert adj(opts=_opts(precision=-1)) == EUNSUPPORTED
 
 
+def test_tau_gradient_validation():
+    lib = _lib()
+    o, v, n = 2, 3, 4
+
+    def tg(L=FAKE, w=2 * FAKE, G=4 * FAKE, ws=8 * FAKE, wsb=1 << 40, opts=None, **kw):
+        d = dict(dict(o=o, v=v, n=n), **kw)
+        return lib.ladder_tau_gradient(d["o"], d["v"], d["n"], L, w, 0.0, G, ws, wsb, opts or _opts(), None)
+
+    assert tg(n=0) == EINVAL
+    assert tg(L=None) == EINVAL
+    assert tg(w=None) == EINVAL
+    assert tg(G=None) == EINVAL
+    assert tg(G=2 * FAKE) == EINVAL                              # G aliases w
+    assert tg(G=FAKE + 16) == EINVAL                             # G overlaps L
+    assert tg(ws=8 * FAKE + 64) == EINVAL
+    assert tg(opts=_opts(precision=3)) == EUNSUPPORTED
+    # the workspace holds the forward's plus the transposed L
+    fb, tb = ctypes.c_size_t(0), ctypes.c_size_t(0)
+    assert lib.ladder_workspace_size(o, v, n, _opts(), ctypes.byref(fb)) == 0
+    assert lib.ladder_tau_gradient_workspace_size(o, v, n, _opts(), ctypes.byref(tb)) == 0
+    assert tb.value >= v * v * n * 8
+    assert tg(wsb=tb.value - 1) == EWORKSPACE
+    assert lib.ladder_tau_gradient_workspace_size(o, v, n, _opts(), None) == EINVAL
+
+
 def test_amplitude_entry_validation():
     lib = _lib()
     assert lib.ladder_mp2_amplitudes(0, 2, 2, FAKE, 2 * FAKE, 3 * FAKE, None) == EINVAL

@@ -426,3 +426,72 @@ def test_autograd_workload_split_forward(dev):
         fd = (Ep - Em) / (2 * h)
         print("autograd workload: FD (%d,%d,%d) %.12e  X %.12e" % (a, c, j, fd, X[a, c, j]))
         assert abs(fd - X[a, c, j]) <= 1e-6 * scale
+
+
+# ------------------------------------------------------------------ transposed ladder (dE/dtau)
+def run_tg(dev, o, v, n, L, w, opts=None, beta=0.0, G0=None):
+    Gg = None if G0 is None else g(G0, dev)
+    G = P.tau_gradient(g(L, dev), g(w, dev), o=o, v=v, n=n, G=Gg, beta=beta, opts=opts)
+    torch.cuda.synchronize()
+    return G.cpu().numpy()
+
+
+@pytest.mark.parametrize("flags", PATHS)
+@pytest.mark.parametrize("o,v,n,seed", [(2, 5, 3, 31), (3, 4, 2, 32), (1, 3, 1, 33)])
+def test_tau_gradient_integer_bitwise(dev, o, v, n, seed, flags):
+    L, _, w = integer_inputs(seed, o, v, n)  # L is not symmetric in (a, c)
+    assert not np.array_equal(L, L.transpose(1, 0, 2)) or v == 1
+    for S in (0, 3):
+        opts = P.Options(flags=flags) if S == 0 else P.Options(precision=P.SPLIT_BF16, n_slices=S, flags=flags)
+        G = run_tg(dev, o, v, n, L, w, opts)
+        assert np.array_equal(G, oracle.tau_gradient(o, v, n, L, w)), S
+
+
+@pytest.mark.parametrize("flags", PATHS)
+@pytest.mark.parametrize("o,v,n,nA", [(4, 20, 60, 0), (5, 37, 70, 4), (2, 129, 17, 64), (1, 23, 9, 5)])
+def test_tau_gradient_matches_oracle(dev, o, v, n, nA, flags):
+    L, _, w = gaussian_inputs(34 + v, o, v, n)
+    Gr = oracle.tau_gradient(o, v, n, L, w)
+    G = run_tg(dev, o, v, n, L, w, P.Options(flags=flags, n_abatch=nA))
+    Gs = run_tg(dev, o, v, n, L, w, P.Options(precision=P.SPLIT_BF16, n_slices=5, flags=flags, n_abatch=nA))
+    print("tau_gradient o=%d v=%d n=%d: fp64 %.3e split %.3e" % (o, v, n, err_norm(G, Gr), err_norm(Gs, Gr)))
+    assert err_norm(G, Gr) <= TOL
+    assert err_norm(Gs, Gr) <= SPLIT_TOL_RX
+
+
+def test_tau_gradient_general_flag_and_beta(dev):
+    o, v, n = 3, 17, 23
+    L, _, w = gaussian_inputs(35, o, v, n, symmetric=False)
+    Gr = oracle.tau_gradient(o, v, n, L, w)
+    G0 = np.random.default_rng(36).standard_normal((o, o, v, v))
+    G = run_tg(dev, o, v, n, L, w, P.Options(flags=P.FLAG_GENERAL), beta=-0.5, G0=G0)
+    assert err_norm(G, Gr - 0.5 * G0) <= TOL
+
+
+def test_autograd_tau_gradient(dev):
+    """dE/dtau from ladder_energy's backward equals the oracle's transposed ladder."""
+    o, v, n = 3, 21, 25
+    L, tau, w = gaussian_inputs(37, o, v, n)
+    tg = g(tau, dev).requires_grad_(True)
+    Lg = g(L, dev).requires_grad_(True)
+    E = P.ladder_energy(Lg, tg, g(w, dev), (o, v, n))
+    (2.0 * E).backward()
+    Gr = oracle.tau_gradient(o, v, n, L, w)
+    Xr = oracle.adjoint(o, v, n, L, tau, w)
+    assert err_norm(tg.grad.cpu().numpy(), 2.0 * Gr) <= TOL
+    assert err_norm(Lg.grad.cpu().numpy(), 2.0 * Xr) <= TOL
+    # E is linear in tau: <tau, dE/dtau> = E
+    assert err_rel(float((tg.detach() * tg.grad).sum()) / 2.0, float(E.detach())) <= TOL
+
+
+def test_tau_gradient_autograd_workload_sampled(dev):
+    """o=40, v=350, n=1200 (the autograd workload): split path, rows c sampled against the oracle."""
+    o, v, n = 40, 350, 1200
+    L, tau, tbar, _, _ = oracle.make_inputs(o, v, n, 5)
+    G = run_tg(dev, o, v, n, L, tbar, P.Options(precision=P.SPLIT_BF16))
+    rows = [0, 1, 117, 349]
+    for c in rows:
+        Gr = oracle.matrix.tau_gradient(o, v, n, L, tbar, c_range=(c, c + 1))
+        e = err_norm(G[:, :, c:c + 1, :], Gr)
+        print("tau_gradient autograd workload row c=%d: err %.3e" % (c, e))
+        assert e <= SPLIT_TOL_RX

@@ -30,6 +30,9 @@ class _Matrix:
     def adjoint(self, o, v, n, L, tau, w):
         return self._m.adjoint(o, v, n, L, tau, w)
 
+    def tau_gradient(self, o, v, n, L, w):
+        return self._m.tau_gradient(o, v, n, L, w)
+
     def __getattr__(self, name):
         return getattr(self._c, name)
 
@@ -231,6 +234,59 @@ def test_finite_differences(impl, symmetric):
         assert abs(fd - X[a, c, J]) <= 1e-9 * max(1.0, abs(X).max()), (a, c, J, fd, X[a, c, J])
 
 
+# ---------------------------------------------------------------- transposed ladder
+def test_tau_gradient_contracts_to_energy(impl):
+    """E is linear in tau, so sum_ijcd tau_ij^cd dE/dtau_ij^cd = E (generic, non-symmetric L)."""
+    o, v, n = 3, 5, 4
+    L, tau, w = rnd(41, v, v, n), rnd(42, o, o, v, v), rnd(43, o, o, v, v)
+    _, E = impl.forward(o, v, n, L, tau, w)
+    G = impl.tau_gradient(o, v, n, L, w)
+    assert abs(np.sum(tau * G) - E) <= 1e-13 * np.sum(np.abs(tau * G))
+    # a transposed L would give a different contraction: the pin is sensitive to it
+    GT = impl.tau_gradient(o, v, n, L.transpose(1, 0, 2), w)
+    assert abs(np.sum(tau * GT) - E) > 1e-3 * abs(E)
+
+
+@pytest.mark.parametrize("seed", [44, 45])
+def test_tau_gradient_integer_unit_differences(impl, seed):
+    """With integer data every value is exact: E(tau + e_k) - E(tau) = G_k for every k."""
+    o, v, n = 2, 3, 2
+    rng = np.random.default_rng(seed)
+    L = rng.integers(-3, 4, (v, v, n)).astype(float)
+    tau = rng.integers(-3, 4, (o, o, v, v)).astype(float)
+    w = rng.integers(-3, 4, (o, o, v, v)).astype(float)
+    G = impl.tau_gradient(o, v, n, L, w)
+    _, E0 = impl.forward(o, v, n, L, tau, w)
+    for k in np.ndindex(o, o, v, v):
+        t1 = tau.copy()
+        t1[k] += 1.0
+        _, E1 = impl.forward(o, v, n, L, t1, w)
+        assert E1 - E0 == G[k], (k, E1 - E0, G[k])
+
+
+def test_tau_gradient_symmetric_L_is_the_ladder(impl):
+    """With L^J_ac = L^J_ca, (ac|bd) = (ca|db), so G(L, w) equals the forward ladder of w."""
+    o, v, n = 2, 6, 3
+    L0 = rnd(46, v, v, n)
+    L = L0 + L0.transpose(1, 0, 2)
+    w = rnd(47, o, o, v, v)
+    G = impl.tau_gradient(o, v, n, L, w)
+    R, _ = impl.forward(o, v, n, L, w)
+    np.testing.assert_allclose(G, R, rtol=0, atol=1e-13 * np.abs(R).max())
+    # and it does not hold for a non-symmetric L
+    G0 = impl.tau_gradient(o, v, n, L0, w)
+    R0, _ = impl.forward(o, v, n, L0, w)
+    assert np.abs(G0 - R0).max() > 1e-3 * np.abs(R0).max()
+
+
+def test_tau_gradient_pair_symmetry(impl):
+    """(ac|bd) = (bd|ac) makes G pair-symmetric whenever w is."""
+    o, v, n = 3, 4, 3
+    L, w = rnd(48, v, v, n), pair_sym(rnd(49, o, o, v, v))
+    G = impl.tau_gradient(o, v, n, L, w)
+    np.testing.assert_allclose(G, G.transpose(1, 0, 3, 2), rtol=0, atol=1e-13 * np.abs(G).max())
+
+
 # ---------------------------------------------------------------- ranges and samples
 def test_ranges_and_samples_agree_with_full(oracle_lib):
     o, v, n = 2, 7, 4
@@ -248,6 +304,12 @@ def test_ranges_and_samples_agree_with_full(oracle_lib):
     Xs = oracle_lib.X_sample(o, v, n, L, tau, w, ab)
     for k, (p, q) in enumerate(ab):
         np.testing.assert_allclose(Xs[k], X[p, q], rtol=0, atol=1e-14 * np.abs(X).max())
+    G = oracle_lib.tau_gradient(o, v, n, L, w)
+    Gr = oracle_lib.tau_gradient_range(o, v, n, L, w, 1, 4)
+    assert np.array_equal(Gr[:, :, 1:4], G[:, :, 1:4]) and not Gr[:, :, :1].any() and not Gr[:, :, 4:].any()
+    import oracle
+    Gm = oracle.matrix.tau_gradient(o, v, n, L, w, c_range=(1, 4))
+    np.testing.assert_allclose(Gm, G[:, :, 1:4], rtol=0, atol=1e-13 * np.abs(G).max())
 
 
 def test_bad_arguments_raise(oracle_lib):
