@@ -76,8 +76,9 @@ def main():
     ap.add_argument("--cpu-rows", type=int, default=1, help="a (and p) rows the CPU baseline computes; 0 = skip")
     ap.add_argument("--no-compare", action="store_true",
                     help="skip the untimed FP64 leg that the split path is compared with")
-    ap.add_argument("--tau-gradient", action="store_true",
-                    help="also time the transposed ladder (dE/dtau) once on the same inputs and check a sampled row")
+    ap.add_argument("--next-rows", action="store_true",
+                    help="also time the transposed ladder (dE/dtau), the metric contraction V and the MO "
+                         "back-transformation once on the same inputs, with sampled checks")
     ap.add_argument("--copy-probe", action="store_true",
                     help="run a 1 GiB device copy first (reference kernel for the HBM traffic counters)")
     args = ap.parse_args()
@@ -128,8 +129,8 @@ def main():
     prec = P.FP64 if args.precision == "fp64" else P.SPLIT_BF16
     opts = P.Options(precision=prec, n_slices=args.slices, n_abatch=args.n_abatch)
     wsb = P.workspace_size(o, v, n, opts)
-    if args.tau_gradient:
-        wsb = max(wsb, P.tau_gradient_workspace_size(o, v, n, opts))
+    if args.next_rows:
+        wsb = max(wsb, P.tau_gradient_workspace_size(o, v, n, opts), P.back_transform_workspace_size(v, n))
     ws = torch.empty(wsb, dtype=torch.uint8, device=dev)
     torch.cuda.synchronize()
     print("bench: %s o=%d v=%d n=%d precision=%s inputs ready in %.1fs, workspace %.2f GiB"
@@ -208,8 +209,10 @@ def main():
         del R64, X64, ws64
         print("bench: fp64 comparison step %.1f s" % (ms64 / 1e3), file=sys.stderr, flush=True)
 
-    tgrad = None
-    if args.tau_gradient:
+    nxt = None
+    if args.next_rows:
+        import oracle
+        nxt = {}
         # dE/dtau = transposed ladder of tbar; nominal flops as the forward (2 n v^4 + 2 o^2 v^4)
         G = torch.empty_like(R)
         torch.cuda.synchronize()
@@ -219,14 +222,45 @@ def main():
         torch.cuda.synchronize()
         mst = ev0.elapsed_time(ev1)
         Ft = 2.0 * n * v ** 4 + 2.0 * o * o * v ** 4
-        import oracle
-        c0 = time.time()
         Gr = oracle.matrix.tau_gradient(o, v, n, L.cpu().numpy(), tbar.cpu().numpy(), c_range=(0, 1))
-        tgrad = {"ms": mst, "nominal_flops": Ft, "tflops": Ft / (mst * 1e-3) / 1e12,
-                 "err_sample_row_c0": float(np.abs(G[:, :, :1, :].cpu().numpy() - Gr).max() / np.abs(Gr).max()),
-                 "oracle_row_seconds": time.time() - c0}
+        nxt["tau_gradient"] = {"ms": mst, "nominal_flops": Ft, "tflops": Ft / (mst * 1e-3) / 1e12,
+                               "err_sample_row_c0": float(np.abs(G[:, :, :1, :].cpu().numpy() - Gr).max()
+                                                          / np.abs(Gr).max())}
         del G
-        print("bench: tau gradient %.1f s" % (mst / 1e3), file=sys.stderr, flush=True)
+        # V = L^T W with W = X/2 (Z := L): trace V must equal E
+        torch.cuda.synchronize()
+        ev0.record(stream)
+        V = P.metric_contraction(L, X, v=v, n=n, alpha=0.5)
+        ev1.record(stream)
+        torch.cuda.synchronize()
+        msv = ev0.elapsed_time(ev1)
+        Fv = 2.0 * n * n * v * v
+        nxt["metric_contraction"] = {"ms": msv, "flops": Fv, "tflops": Fv / (msv * 1e-3) / 1e12,
+                                     "err_trace_V_vs_E": abs(float(torch.trace(V)) - float(E)) / abs(float(E))}
+        del V
+        # MO back-transformation of W = X/2 with seeded x, y = 1 + noise
+        gen = torch.Generator(device=dev)
+        gen.manual_seed(seed)
+        xm = torch.eye(v, dtype=torch.float64, device=dev) + 0.1 * torch.randn(
+            (v, v), dtype=torch.float64, device=dev, generator=gen) / v ** 0.5
+        ym = torch.eye(v, dtype=torch.float64, device=dev) + 0.1 * torch.randn(
+            (v, v), dtype=torch.float64, device=dev, generator=gen) / v ** 0.5
+        Wmo = torch.empty_like(X)
+        torch.cuda.synchronize()
+        ev0.record(stream)
+        P.back_transform(xm, ym, X, v=v, n=n, Wmo=Wmo, alpha=0.5, ws=ws)
+        ev1.record(stream)
+        torch.cuda.synchronize()
+        msb = ev0.elapsed_time(ev1)
+        Fb = 4.0 * v ** 3 * n
+        K = n // 2
+        Wr = 0.5 * oracle.matrix.back_transform(v, 1, xm.cpu().numpy(), ym.cpu().numpy(), X[:, :, K:K + 1].cpu().numpy())
+        nxt["back_transform"] = {"ms": msb, "flops": Fb, "tflops": Fb / (msb * 1e-3) / 1e12,
+                                 "err_sample_K": float(np.abs(Wmo[:, :, K:K + 1].cpu().numpy() - Wr).max()
+                                                       / np.abs(Wr).max())}
+        del Wmo
+        print("bench: next rows: tau gradient %.1f s, V %.1f ms, back-transform %.1f ms"
+              % (mst / 1e3, msv, msb), file=sys.stderr, flush=True)
 
     cpu = None
     errs = {}
@@ -266,7 +300,7 @@ def main():
         "executed_gemm_flops": executed,
         "executed_gemm_tflops": executed / (ms * 1e-3) / 1e12,
         "fp64_comparison": compare,
-        "tau_gradient": tgrad,
+        "next_rows": nxt,
     }
     out.update(errs)
     print(json.dumps(out))

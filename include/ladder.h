@@ -141,6 +141,39 @@ int ladder_tau_gradient(int64_t o, int64_t v, int64_t n, const double* L, const 
                         double* G, void* ws, size_t ws_bytes, const ladder_options* opts, void* stream);
 
 /*
+ * Gradient intermediates of Sec. II A built from the V^4 density block.
+ *
+ * W: ladder_adjoint called with Z in place of L and alpha = 1/2 returns
+ *   W^K_ac = sum_bd d_acbd Z^K_bd,   d_acbd = sum_ij w_ij^ab tau_ij^cd,
+ * the three-index density intermediate W^K_pq = sum_rs d_pqrs Z^K_rs restricted
+ * to the virtual-virtual block (Z^K_rs = sum_L (S^-1)_KL (L|rs), layout [v][v][n]
+ * like L; pair-symmetric amplitudes, or LADDER_FLAG_GENERAL, which returns the
+ * average of sum_rs d_pqrs Z_rs and sum_rs d_rspq Z_rs).
+ *
+ * ladder_metric_contraction: the two-index intermediate
+ *   V = beta * V + alpha * V',  V'_MN = sum_pq Z^M_pq W^N_pq      (V: [n][n], row M)
+ * over the v^2 virtual pairs given (one FP64 MFMA GEMM, M = N = n, K = v^2).
+ * V must not overlap Z or W.  With beta == 0, V is not read.
+ */
+int ladder_metric_contraction(int64_t v, int64_t n, const double* Z, const double* W, double alpha,
+                              double beta, double* V, void* stream);
+
+/*
+ * MO back-transformation of the three-index intermediate (Sec. II A, applied
+ * before the contraction with the differentiated MO integrals):
+ *   Wmo = beta * Wmo + alpha * Wmo',  Wmo'^K_pq = sum_rs x_rp y_sq W^K_rs
+ * for the virtual-virtual block: x, y are [v][v] row-major (x[r*v + p] = x_rp),
+ * W and Wmo [v][v][n].  Two FP64 MFMA GEMMs (2 v^3 n flops each) through a
+ * [v][v][n] intermediate in the workspace (ladder_back_transform_workspace_size
+ * bytes, 256-byte aligned).  Wmo must not overlap x, y, W or ws.  With
+ * beta == 0, Wmo is not read.
+ */
+int ladder_back_transform_workspace_size(int64_t v, int64_t n, size_t* bytes);
+int ladder_back_transform(int64_t v, int64_t n, const double* x, const double* y, const double* W,
+                          double alpha, double beta, double* Wmo, void* ws, size_t ws_bytes,
+                          void* stream);
+
+/*
  * First-order doubles amplitudes from the occupied-virtual Cholesky block (the
  * synthetic stand-in for converged T2; Cholesky expansion of Sec. II A):
  *   t_ij^ab = (sum_J L^J_ia L^J_jb) / ((eps_i + eps_j) - (eps_a + eps_b)).
@@ -205,7 +238,9 @@ int ladder_batched(int count, const ladder_instance* inst, uint32_t what, void* 
 #define LADDER_STAGE_SLICE 8    /* split mode: FP64 -> BF16 slices */
 #define LADDER_STAGE_PACK 9     /* +/- packing of tau, tbar and the g tile */
 #define LADDER_STAGE_UNPACK 10  /* R and D rebuilt from their packed parts */
-#define LADDER_NUM_STAGES 11
+#define LADDER_STAGE_METRIC 11  /* V = Z^T W (three-index to two-index intermediate) */
+#define LADDER_STAGE_BACKTRANSFORM 12 /* MO back-transformation of W */
+#define LADDER_NUM_STAGES 13
 typedef struct {
     int32_t stage;
     int32_t launches;

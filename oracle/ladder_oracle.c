@@ -22,6 +22,11 @@
  *                                                 the L-built three-index intermediate
  *                                                 (2 W~^J_pq of Sec. II C) restricted to
  *                                                 the V^4 density block of Sec. II B.
+ *   W^K_pq  = sum_rs d_pqrs Z^K_rs,  d_pqrs = sum_ij w_ij^pr tau_ij^qs
+ *                                                 the three-index density intermediate of
+ *                                                 Sec. II A (V^4 block, density of Sec. II B)
+ *   V_MN    = sum_pq Z^M_pq W^N_pq                its two-index partner (Sec. II A)
+ *   Wmo^K_pq = sum_rs x_rp y_sq W^K_rs            the MO back-transformation (Sec. II A)
  *   G_ij^cd = dE/dtau_ij^cd = sum_ab w_ij^ab g_acbd
  *                                                 the transposed ladder: the A2-term part
  *                                                 of the multiplier equations tbar A = -eta
@@ -202,6 +207,63 @@ int oracle_ladder_tau_gradient_range(int64_t o, int64_t v, int64_t n, const doub
 int oracle_ladder_tau_gradient(int64_t o, int64_t v, int64_t n, const double* L, const double* w,
                                double* G) {
     return oracle_ladder_tau_gradient_range(o, v, n, L, w, 0, v, G);
+}
+
+/*
+ * Three-index density intermediate for rows p in [p_lo, p_hi):
+ *   d_pqrs = sum_ij w[i][j][p][r] tau[i][j][q][s]     (V^4 density, Mulliken order)
+ *   W[p][q][K] = sum_r sum_s d_pqrs Z[r][s][K].
+ * Z has the layout of L.  Rows p outside the range are left untouched.
+ */
+int oracle_w_intermediate_range(int64_t o, int64_t v, int64_t n, const double* Z, const double* tau,
+                                const double* w, int64_t p_lo, int64_t p_hi, double* W) {
+    if (bad_dims(o, v, n) || !Z || !tau || !w || !W || p_lo < 0 || p_hi > v || p_lo > p_hi) return -1;
+    const int64_t oo = o * o, vv = v * v;
+#pragma omp parallel for schedule(dynamic, 1)
+    for (int64_t p = p_lo; p < p_hi; ++p) {
+        for (int64_t q = 0; q < v; ++q) {
+            double* out = W + (p * v + q) * n;
+            for (int64_t K = 0; K < n; ++K) out[K] = 0.0;
+            for (int64_t r = 0; r < v; ++r)
+                for (int64_t s = 0; s < v; ++s) {
+                    double d = 0.0;
+                    for (int64_t ij = 0; ij < oo; ++ij) d += w[ij * vv + p * v + r] * tau[ij * vv + q * v + s];
+                    const double* z = Z + (r * v + s) * n;
+                    for (int64_t K = 0; K < n; ++K) out[K] += d * z[K];
+                }
+        }
+    }
+    return 0;
+}
+
+/* V[M][N] = sum_p sum_q Z[p][q][M] W[p][q][N]. */
+int oracle_metric_contraction(int64_t v, int64_t n, const double* Z, const double* W, double* V) {
+    if (bad_dims(1, v, n) || !Z || !W || !V) return -1;
+    const int64_t vv = v * v;
+#pragma omp parallel for schedule(static)
+    for (int64_t M = 0; M < n; ++M)
+        for (int64_t N = 0; N < n; ++N) {
+            double s = 0.0;
+            for (int64_t pq = 0; pq < vv; ++pq) s += Z[pq * n + M] * W[pq * n + N];
+            V[M * n + N] = s;
+        }
+    return 0;
+}
+
+/* Wmo[p][q][K] = sum_r sum_s x[r][p] y[s][q] W[r][s][K], for K in [K_lo, K_hi). */
+int oracle_back_transform_range(int64_t v, int64_t n, const double* x, const double* y, const double* W,
+                                int64_t K_lo, int64_t K_hi, double* Wmo) {
+    if (bad_dims(1, v, n) || !x || !y || !W || !Wmo || K_lo < 0 || K_hi > n || K_lo > K_hi) return -1;
+#pragma omp parallel for schedule(dynamic, 1)
+    for (int64_t p = 0; p < v; ++p)
+        for (int64_t q = 0; q < v; ++q)
+            for (int64_t K = K_lo; K < K_hi; ++K) {
+                double s = 0.0;
+                for (int64_t r = 0; r < v; ++r)
+                    for (int64_t t = 0; t < v; ++t) s += x[r * v + p] * y[t * v + q] * W[(r * v + t) * n + K];
+                Wmo[(p * v + q) * n + K] = s;
+            }
+    return 0;
 }
 
 /*

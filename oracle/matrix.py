@@ -69,3 +69,32 @@ def tau_gradient(o, v, n, L, w, c_range=None):
         h = np.ascontiguousarray(L[:, c, :]) @ Lbd.T       # h[a, (b,d)] = sum_J L^J_ac L^J_bd
         G[:, c - c_lo, :] = W @ h.reshape(v * v, v)        # G_ij^cd = sum_ab w_ij^ab h[(a,b), d]
     return G.reshape(o, o, c_hi - c_lo, v)
+
+
+def w_intermediate(o, v, n, Z, tau, w, p_range=None):
+    """W^K_pq = sum_rs d_pqrs Z^K_rs with d_pqrs = sum_ij w_ij^pr tau_ij^qs, per row p."""
+    Z = np.ascontiguousarray(Z, dtype=np.float64).reshape(v * v, n)        # [(r,s), K]
+    T = np.ascontiguousarray(tau, dtype=np.float64).reshape(o * o, v * v)  # [ij, (q,s)]
+    Wt = np.ascontiguousarray(w, dtype=np.float64).reshape(o * o, v, v)    # [ij, p, r]
+    p_lo, p_hi = (0, v) if p_range is None else p_range
+    out = np.empty((p_hi - p_lo, v, n))
+    for p in range(p_lo, p_hi):
+        d = np.ascontiguousarray(Wt[:, p, :]).T @ T                        # d[r, (q,s)]
+        d = d.reshape(v, v, v).transpose(1, 0, 2).reshape(v, v * v)       # d[q, (r,s)]
+        out[p - p_lo] = d @ Z
+    return out
+
+
+def metric_contraction(v, n, Z, W):
+    """V_MN = sum_pq Z^M_pq W^N_pq."""
+    return np.asarray(Z, dtype=np.float64).reshape(v * v, n).T @ np.asarray(W, dtype=np.float64).reshape(v * v, n)
+
+
+def back_transform(v, n, x, y, W, K_range=None):
+    """Wmo^K_pq = sum_rs x_rp y_sq W^K_rs, one K at a time."""
+    W = np.asarray(W, dtype=np.float64).reshape(v, v, n)
+    K_lo, K_hi = (0, n) if K_range is None else K_range
+    out = np.empty((v, v, K_hi - K_lo))
+    for K in range(K_lo, K_hi):
+        out[:, :, K - K_lo] = x.T @ np.ascontiguousarray(W[:, :, K]) @ y
+    return out

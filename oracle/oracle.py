@@ -22,7 +22,8 @@ LIB = os.path.join(HERE, "liboracle.so")
 
 __all__ = [
     "build", "load", "forward", "adjoint", "forward_range", "adjoint_range", "R_sample",
-    "X_sample", "tau_gradient", "tau_gradient_range", "mp2_amplitudes", "amplitude_update", "make_inputs",
+    "X_sample", "tau_gradient", "tau_gradient_range", "w_intermediate", "w_intermediate_range",
+    "metric_contraction", "back_transform", "back_transform_range", "mp2_amplitudes", "amplitude_update", "make_inputs",
     "num_threads",
     "set_num_threads", "flops_forward", "flops_adjoint", "matrix",
 ]
@@ -53,12 +54,16 @@ def load():
         lib.oracle_ladder_R_sample.argtypes = [i64, i64, i64, dp, dp, i64, vp, dp]
         lib.oracle_ladder_X_sample.argtypes = [i64, i64, i64, dp, dp, dp, i64, vp, dp]
         lib.oracle_ladder_tau_gradient_range.argtypes = [i64, i64, i64, dp, dp, i64, i64, dp]
+        lib.oracle_w_intermediate_range.argtypes = [i64, i64, i64, dp, dp, dp, i64, i64, dp]
+        lib.oracle_metric_contraction.argtypes = [i64, i64, dp, dp, dp]
+        lib.oracle_back_transform_range.argtypes = [i64, i64, dp, dp, dp, i64, i64, dp]
         lib.oracle_mp2_amplitudes.argtypes = [i64, i64, i64, dp, dp, dp]
         lib.oracle_amplitude_update.argtypes = [i64, i64, dp, dp, dp]
         lib.oracle_num_threads.restype = ctypes.c_int
         lib.oracle_set_num_threads.argtypes = [ctypes.c_int]
         for f in ("oracle_ladder_forward_range", "oracle_ladder_adjoint_range", "oracle_ladder_R_sample",
-                  "oracle_ladder_X_sample", "oracle_ladder_tau_gradient_range", "oracle_mp2_amplitudes",
+                  "oracle_ladder_X_sample", "oracle_ladder_tau_gradient_range", "oracle_w_intermediate_range",
+                  "oracle_metric_contraction", "oracle_back_transform_range", "oracle_mp2_amplitudes",
                   "oracle_amplitude_update"):
             getattr(lib, f).restype = ctypes.c_int
         _lib = lib
@@ -132,6 +137,44 @@ def tau_gradient_range(o, v, n, L, w, c_lo, c_hi, G=None):
 def tau_gradient(o, v, n, L, w):
     """G [o][o][v][v] = dE/dtau with E = sum w * R(L, tau) (the transposed ladder), general L."""
     return tau_gradient_range(o, v, n, L, w, 0, v)
+
+
+def w_intermediate_range(o, v, n, Z, tau, w, p_lo, p_hi, W=None):
+    """W^K_pq = sum_rs d_pqrs Z^K_rs (d_pqrs = sum_ij w_ij^pr tau_ij^qs) for rows p in [p_lo, p_hi)."""
+    Z = _f64(Z, (v, v, n)); tau = _f64(tau, (o, o, v, v)); w = _f64(w, (o, o, v, v))
+    if W is None:
+        W = np.zeros((v, v, n))
+    rc = load().oracle_w_intermediate_range(o, v, n, _p(Z), _p(tau), _p(w), p_lo, p_hi, _p(W))
+    if rc != 0:
+        raise RuntimeError("oracle_w_intermediate_range failed")
+    return W
+
+
+def w_intermediate(o, v, n, Z, tau, w):
+    return w_intermediate_range(o, v, n, Z, tau, w, 0, v)
+
+
+def metric_contraction(v, n, Z, W):
+    """V [n][n], V_MN = sum_pq Z^M_pq W^N_pq."""
+    Z = _f64(Z, (v, v, n)); W = _f64(W, (v, v, n))
+    V = np.zeros((n, n))
+    if load().oracle_metric_contraction(v, n, _p(Z), _p(W), _p(V)) != 0:
+        raise RuntimeError("oracle_metric_contraction failed")
+    return V
+
+
+def back_transform_range(v, n, x, y, W, K_lo, K_hi, Wmo=None):
+    """Wmo^K_pq = sum_rs x_rp y_sq W^K_rs for K in [K_lo, K_hi)."""
+    x = _f64(x, (v, v)); y = _f64(y, (v, v)); W = _f64(W, (v, v, n))
+    if Wmo is None:
+        Wmo = np.zeros((v, v, n))
+    if load().oracle_back_transform_range(v, n, _p(x), _p(y), _p(W), K_lo, K_hi, _p(Wmo)) != 0:
+        raise RuntimeError("oracle_back_transform_range failed")
+    return Wmo
+
+
+def back_transform(v, n, x, y, W):
+    return back_transform_range(v, n, x, y, W, 0, n)
 
 
 def R_sample(o, v, n, L, tau, ab):

@@ -956,6 +956,56 @@ int ladder_adjoint(int64_t o, int64_t v, int64_t n, const double* L, const doubl
     return LADDER_OK;
 }
 
+int ladder_metric_contraction(int64_t v, int64_t n, const double* Z, const double* W, double alpha, double beta,
+                              double* V, void* stream) {
+    g_last_error.clear();
+    if (v < 1 || n < 1 || v > 100000 || n > 1000000) return fail(LADDER_EINVAL, "bad dimensions v=%lld n=%lld", (long long)v, (long long)n);
+    if (!Z || !W || !V) return fail(LADDER_EINVAL, "Z, W and V must be non-NULL");
+    if (!aligned8(Z) || !aligned8(W) || !aligned8(V)) return fail(LADDER_EINVAL, "misaligned pointer (8-byte alignment)");
+    const int64_t zb = v * v * n * 8, vb = n * n * 8;
+    if (overlap(V, vb, Z, zb) || overlap(V, vb, W, zb)) return fail(LADDER_EINVAL, "V overlaps Z or W");
+    hipStream_t st = (hipStream_t)stream;
+    StageTimer tm(LADDER_STAGE_METRIC, gemm_flops(n, n, v * v), gemm_bytes(n, n, v * v), st);
+    // A(M, pq) = Z[pq*n + M], B(pq, N) = W[pq*n + N]: both M/N-contiguous
+    EpiStrided ev{V, n, alpha, beta, nullptr, nullptr};
+    return hip_check(launch_gemm<false, false, LADDER_STAGE_METRIC>(Z, n, W, n, n, n, v * v, ev, st), "metric GEMM launch");
+}
+
+int ladder_back_transform_workspace_size(int64_t v, int64_t n, size_t* bytes) {
+    g_last_error.clear();
+    if (!bytes) return fail(LADDER_EINVAL, "bytes is NULL");
+    if (v < 1 || n < 1 || v > 100000 || n > 1000000) return fail(LADDER_EINVAL, "bad dimensions v=%lld n=%lld", (long long)v, (long long)n);
+    *bytes = align_up((size_t)(v * v * n) * 8);
+    return LADDER_OK;
+}
+
+int ladder_back_transform(int64_t v, int64_t n, const double* x, const double* y, const double* W, double alpha,
+                          double beta, double* Wmo, void* ws, size_t ws_bytes, void* stream) {
+    g_last_error.clear();
+    if (v < 1 || n < 1 || v > 100000 || n > 1000000) return fail(LADDER_EINVAL, "bad dimensions v=%lld n=%lld", (long long)v, (long long)n);
+    if (!x || !y || !W || !Wmo || !ws) return fail(LADDER_EINVAL, "x, y, W, Wmo and ws must be non-NULL");
+    if (!aligned8(x) || !aligned8(y) || !aligned8(W) || !aligned8(Wmo) || ((uintptr_t)ws % ALIGN))
+        return fail(LADDER_EINVAL, "misaligned pointer (arrays need 8-byte, ws 256-byte alignment)");
+    const size_t need = align_up((size_t)(v * v * n) * 8);
+    if (ws_bytes < need) return fail(LADDER_EWORKSPACE, "workspace of %zu bytes, %zu needed", ws_bytes, need);
+    const int64_t wb = v * v * n * 8, xb = v * v * 8;
+    if (overlap(Wmo, wb, W, wb) || overlap(Wmo, wb, x, xb) || overlap(Wmo, wb, y, xb) ||
+        overlap(Wmo, wb, ws, (int64_t)ws_bytes) || overlap(W, wb, ws, (int64_t)ws_bytes))
+        return fail(LADDER_EINVAL, "Wmo or W overlaps another array or the workspace");
+    hipStream_t st = (hipStream_t)stream;
+    double* U = (double*)ws;
+    StageTimer tm(LADDER_STAGE_BACKTRANSFORM, 2.0 * gemm_flops(v, v * n, v), 2.0 * gemm_bytes(v, v * n, v), st);
+    // U[s][p][K] = sum_r x_rp W[r][s][K]: A(p, r) = x[r*v + p], B(r, (s,K)) = W[r*v*n + s*n + K]
+    EpiSwapMid e1{U, v, v, n, 1.0, 0.0};
+    hipError_t e = launch_gemm<false, false, LADDER_STAGE_BACKTRANSFORM>(x, v, W, v * n, v, v * n, v, e1, st);
+    int rc;
+    if ((rc = hip_check(e, "back-transform GEMM launch"))) return rc;
+    // Wmo[p][q][K] = sum_s y_sq U[s][p][K]: A(q, s) = y[s*v + q], B(s, (p,K)) = U[s*v*n + p*n + K]
+    EpiSwapMid e2{Wmo, v, v, n, alpha, beta};
+    return hip_check(launch_gemm<false, false, LADDER_STAGE_BACKTRANSFORM>(y, v, U, v * n, v, v * n, v, e2, st),
+                     "back-transform GEMM launch");
+}
+
 int ladder_mp2_amplitudes(int64_t o, int64_t v, int64_t n, const double* Lov, const double* eps, double* t,
                           void* stream) {
     g_last_error.clear();

@@ -25,13 +25,15 @@ DO_ADJOINT = 2
 
 EXPORTS = (
     "ladder_default_options", "ladder_workspace_size", "ladder_forward", "ladder_adjoint",
-    "ladder_tau_gradient_workspace_size", "ladder_tau_gradient",
+    "ladder_tau_gradient_workspace_size", "ladder_tau_gradient", "ladder_metric_contraction",
+    "ladder_back_transform_workspace_size", "ladder_back_transform",
     "ladder_mp2_amplitudes", "ladder_amplitude_update", "ladder_batched_workspace_size",
     "ladder_batched", "ladder_strerror", "ladder_last_error", "ladder_shutdown",
     "ladder_profile_start", "ladder_profile_stop",
 )
 
-STAGE_NAMES = ("gemm_b", "gemm_c", "energy", "gemm_e", "gemm_f", "swap", "mp2", "update", "slice", "pack", "unpack")
+STAGE_NAMES = ("gemm_b", "gemm_c", "energy", "gemm_e", "gemm_f", "swap", "mp2", "update", "slice", "pack", "unpack",
+               "metric", "back_transform")
 
 
 class LadderError(RuntimeError):
@@ -91,13 +93,17 @@ def _load():
     lib.ladder_adjoint.argtypes = [i64, i64, i64, vp, vp, vp, dbl, dbl, vp, vp, sz, op, vp]
     lib.ladder_tau_gradient_workspace_size.argtypes = [i64, i64, i64, op, ctypes.POINTER(sz)]
     lib.ladder_tau_gradient.argtypes = [i64, i64, i64, vp, vp, dbl, vp, vp, sz, op, vp]
+    lib.ladder_metric_contraction.argtypes = [i64, i64, vp, vp, dbl, dbl, vp, vp]
+    lib.ladder_back_transform_workspace_size.argtypes = [i64, i64, ctypes.POINTER(sz)]
+    lib.ladder_back_transform.argtypes = [i64, i64, vp, vp, vp, dbl, dbl, vp, vp, sz, vp]
     lib.ladder_mp2_amplitudes.argtypes = [i64, i64, i64, vp, vp, vp, vp]
     lib.ladder_amplitude_update.argtypes = [i64, i64, vp, vp, vp, vp]
     lib.ladder_batched_workspace_size.argtypes = [ctypes.c_int, ctypes.POINTER(_CInstance), ctypes.c_uint32, op,
                                                   ctypes.POINTER(sz)]
     lib.ladder_batched.argtypes = [ctypes.c_int, ctypes.POINTER(_CInstance), ctypes.c_uint32, vp, sz, op, vp]
     for f in ("ladder_workspace_size", "ladder_forward", "ladder_adjoint", "ladder_tau_gradient_workspace_size",
-              "ladder_tau_gradient", "ladder_mp2_amplitudes",
+              "ladder_tau_gradient", "ladder_metric_contraction", "ladder_back_transform_workspace_size",
+              "ladder_back_transform", "ladder_mp2_amplitudes",
               "ladder_amplitude_update", "ladder_batched_workspace_size", "ladder_batched"):
         getattr(lib, f).restype = ctypes.c_int
     lib.ladder_strerror.argtypes = [ctypes.c_int]
@@ -225,6 +231,41 @@ def tau_gradient(L, w, *, o, v, n, G=None, beta=0.0, ws=None, opts=None, stream=
     _check(_load().ladder_tau_gradient(o, v, n, _ptr(L), _ptr(w), float(beta), _ptr(G), _ptr(wsb),
                                        wsb.numel() * wsb.element_size(), ctypes.byref(c), _stream(stream)))
     return G
+
+
+def w_intermediate(Z, tau, tbar, *, o, v, n, W=None, beta=0.0, ws=None, opts=None, stream=None):
+    """W^K_ac = sum_bd d_acbd Z^K_bd (the V^4 block of the density intermediate): ladder_adjoint
+    with Z in place of L and alpha = 1/2."""
+    return adjoint(Z, tau, tbar, o=o, v=v, n=n, X=W, alpha=0.5, beta=beta, ws=ws, opts=opts, stream=stream)
+
+
+def metric_contraction(Z, W, *, v, n, V=None, alpha=1.0, beta=0.0, stream=None):
+    """V_MN = beta*V + alpha * sum_pq Z^M_pq W^N_pq  ([n][n])."""
+    _need(Z, "Z", (v, v, n)); _need(W, "W", (v, v, n))
+    if V is None:
+        V = torch.empty((n, n), dtype=torch.float64, device=Z.device)
+    _need(V, "V", (n, n))
+    _check(_load().ladder_metric_contraction(v, n, _ptr(Z), _ptr(W), float(alpha), float(beta), _ptr(V),
+                                             _stream(stream)))
+    return V
+
+
+def back_transform_workspace_size(v: int, n: int) -> int:
+    b = ctypes.c_size_t(0)
+    _check(_load().ladder_back_transform_workspace_size(v, n, ctypes.byref(b)))
+    return b.value
+
+
+def back_transform(x, y, W, *, v, n, Wmo=None, alpha=1.0, beta=0.0, ws=None, stream=None):
+    """Wmo^K_pq = beta*Wmo + alpha * sum_rs x_rp y_sq W^K_rs  (x, y: [v][v]; W, Wmo: [v][v][n])."""
+    _need(x, "x", (v, v)); _need(y, "y", (v, v)); _need(W, "W", (v, v, n))
+    if Wmo is None:
+        Wmo = torch.empty((v, v, n), dtype=torch.float64, device=W.device)
+    _need(Wmo, "Wmo", (v, v, n))
+    wsb = _workspace(back_transform_workspace_size(v, n), W.device, ws)
+    _check(_load().ladder_back_transform(v, n, _ptr(x), _ptr(y), _ptr(W), float(alpha), float(beta), _ptr(Wmo),
+                                         _ptr(wsb), wsb.numel() * wsb.element_size(), _stream(stream)))
+    return Wmo
 
 
 def mp2_amplitudes(Lov, eps, *, o, v, n, t=None, stream=None):

@@ -108,6 +108,27 @@ def test_tau_gradient_validation():
     assert lib.ladder_tau_gradient_workspace_size(o, v, n, _opts(), None) == EINVAL
 
 
+def test_intermediate_entry_validation():
+    lib = _lib()
+    v, n = 3, 4
+    assert lib.ladder_metric_contraction(0, n, FAKE, 2 * FAKE, 1.0, 0.0, 3 * FAKE, None) == EINVAL
+    assert lib.ladder_metric_contraction(v, n, None, 2 * FAKE, 1.0, 0.0, 3 * FAKE, None) == EINVAL
+    assert lib.ladder_metric_contraction(v, n, FAKE, 2 * FAKE, 1.0, 0.0, 2 * FAKE + 8, None) == EINVAL  # V overlaps W
+    b = ctypes.c_size_t(0)
+    assert lib.ladder_back_transform_workspace_size(v, n, ctypes.byref(b)) == 0 and b.value >= v * v * n * 8
+    assert lib.ladder_back_transform_workspace_size(v, 0, ctypes.byref(b)) == EINVAL
+
+    def bt(x=FAKE, y=2 * FAKE, W=3 * FAKE, Wmo=4 * FAKE, ws=8 * FAKE, wsb=1 << 30, vv=v):
+        return lib.ladder_back_transform(vv, n, x, y, W, 1.0, 0.0, Wmo, ws, wsb, None)
+
+    assert bt(vv=-1) == EINVAL
+    assert bt(y=None) == EINVAL
+    assert bt(Wmo=3 * FAKE) == EINVAL                            # Wmo aliases W
+    assert bt(ws=8 * FAKE + 8) == EINVAL
+    assert bt(wsb=8) == EWORKSPACE
+    assert bt(ws=3 * FAKE) == EINVAL                             # workspace overlaps W
+
+
 def test_amplitude_entry_validation():
     lib = _lib()
     assert lib.ladder_mp2_amplitudes(0, 2, 2, FAKE, 2 * FAKE, 3 * FAKE, None) == EINVAL

@@ -495,3 +495,67 @@ def test_tau_gradient_autograd_workload_sampled(dev):
         e = err_norm(G[:, :, c:c + 1, :], Gr)
         print("tau_gradient autograd workload row c=%d: err %.3e" % (c, e))
         assert e <= SPLIT_TOL_RX
+
+
+# ------------------------------------------------------------------ gradient intermediates W, V, Wmo
+@pytest.mark.parametrize("flags", PATHS)
+@pytest.mark.parametrize("o,v,n,seed", [(3, 7, 5, 71), (4, 20, 60, 72), (2, 41, 33, 73)])
+def test_w_intermediate_matches_oracle(dev, o, v, n, seed, flags):
+    _, tau, w = gaussian_inputs(seed, o, v, n)
+    Z = np.random.default_rng(seed + 100).standard_normal((v, v, n))
+    Wr = oracle.w_intermediate(o, v, n, Z, tau, w)
+    for opts, tol in ((P.Options(flags=flags), TOL), (P.Options(precision=P.SPLIT_BF16, flags=flags), SPLIT_TOL_RX)):
+        W = P.w_intermediate(g(Z, dev), g(tau, dev), g(w, dev), o=o, v=v, n=n, opts=opts).cpu().numpy()
+        print("W o=%d v=%d n=%d precision=%d: err %.3e" % (o, v, n, opts.precision, err_norm(W, Wr)))
+        assert err_norm(W, Wr) <= tol
+
+
+@pytest.mark.parametrize("v,n,seed", [(1, 1, 74), (3, 2, 75), (20, 60, 76), (37, 70, 77), (129, 17, 78)])
+def test_metric_and_back_transform_integer_bitwise(dev, v, n, seed):
+    rng = np.random.default_rng(seed)
+    Z, W = (rng.integers(-5, 6, (v, v, n)).astype(float) for _ in range(2))
+    x, y = (rng.integers(-3, 4, (v, v)).astype(float) for _ in range(2))
+    V = P.metric_contraction(g(Z, dev), g(W, dev), v=v, n=n).cpu().numpy()
+    assert np.array_equal(V, oracle.metric_contraction(v, n, Z, W))
+    Wmo = P.back_transform(g(x, dev), g(y, dev), g(W, dev), v=v, n=n).cpu().numpy()
+    assert np.array_equal(Wmo, oracle.back_transform(v, n, x, y, W))
+
+
+@pytest.mark.parametrize("v,n,seed", [(20, 60, 79), (150, 600, 80), (131, 257, 81)])
+def test_metric_and_back_transform_match_oracle(dev, v, n, seed):
+    rng = np.random.default_rng(seed)
+    Z, W = rng.standard_normal((v, v, n)), rng.standard_normal((v, v, n))
+    x, y = rng.standard_normal((v, v)) / np.sqrt(v), rng.standard_normal((v, v)) / np.sqrt(v)
+    V0, W0 = rng.standard_normal((n, n)), rng.standard_normal((v, v, n))
+    V = P.metric_contraction(g(Z, dev), g(W, dev), v=v, n=n, V=g(V0, dev), alpha=2.0, beta=-1.0).cpu().numpy()
+    Vr = 2.0 * oracle.matrix.metric_contraction(v, n, Z, W) - V0
+    Wmo = P.back_transform(g(x, dev), g(y, dev), g(W, dev), v=v, n=n, Wmo=g(W0, dev), alpha=0.5, beta=3.0)
+    Wr = 0.5 * oracle.matrix.back_transform(v, n, x, y, W) + 3.0 * W0
+    print("v=%d n=%d: err V %.3e err Wmo %.3e" % (v, n, err_norm(V, Vr), err_norm(Wmo.cpu().numpy(), Wr)))
+    assert err_norm(V, Vr) <= TOL and err_norm(Wmo.cpu().numpy(), Wr) <= TOL
+
+
+def test_metric_and_back_transform_retinal_sampled(dev):
+    """v=657, n=2200 (the retinal shape): sampled blocks of V and slices K of Wmo against the oracle."""
+    v, n = 657, 2200
+    gen = torch.Generator(device=dev)
+    gen.manual_seed(82)
+    Z = torch.randn((v, v, n), dtype=torch.float64, device=dev, generator=gen)
+    W = torch.randn((v, v, n), dtype=torch.float64, device=dev, generator=gen)
+    x = torch.randn((v, v), dtype=torch.float64, device=dev, generator=gen) / v ** 0.5
+    y = torch.randn((v, v), dtype=torch.float64, device=dev, generator=gen) / v ** 0.5
+    V = P.metric_contraction(Z, W, v=v, n=n).cpu().numpy()
+    Wmo = P.back_transform(x, y, W, v=v, n=n)
+    torch.cuda.synchronize()
+    cols = [0, 1, 977, 2199]
+    Zs = Z[:, :, cols].cpu().numpy()
+    Ws = W[:, :, cols].cpu().numpy()
+    Vr = oracle.matrix.metric_contraction(v, len(cols), Zs, Ws)
+    eV = err_norm(V[np.ix_(cols, cols)], Vr)
+    xh, yh = x.cpu().numpy(), y.cpu().numpy()
+    eW = 0.0
+    for K in (0, 1500, 2199):
+        Wr = oracle.matrix.back_transform(v, 1, xh, yh, W[:, :, K:K + 1].cpu().numpy())
+        eW = max(eW, err_norm(Wmo[:, :, K:K + 1].cpu().numpy(), Wr))
+    print("retinal shape: err V %.3e err Wmo %.3e" % (eV, eW))
+    assert eV <= TOL and eW <= TOL

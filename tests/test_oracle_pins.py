@@ -287,6 +287,93 @@ def test_tau_gradient_pair_symmetry(impl):
     np.testing.assert_allclose(G, G.transpose(1, 0, 3, 2), rtol=0, atol=1e-13 * np.abs(G).max())
 
 
+# ---------------------------------------------------------------- gradient intermediates (W, V, MO back-transform)
+@pytest.fixture(params=["c", "matrix"])
+def gi(request, oracle_lib):
+    """The C and numpy versions of W, V and the back-transformation behind one interface."""
+    import oracle
+
+    class C:
+        w = staticmethod(oracle_lib.w_intermediate)
+        v = staticmethod(oracle_lib.metric_contraction)
+        bt = staticmethod(oracle_lib.back_transform)
+
+    class M:
+        w = staticmethod(oracle.matrix.w_intermediate)
+        v = staticmethod(oracle.matrix.metric_contraction)
+        bt = staticmethod(oracle.matrix.back_transform)
+
+    return C if request.param == "c" else M
+
+
+def test_w_intermediate_unit_density(gi):
+    """A single amplitude pair: w = e_ij^ab, tau = e_ij^cd gives d_pqrs = [p=a][r=b][q=c][s=d],
+    so W^K_pq = [p=a][q=c] Z^K_bd exactly."""
+    o, v, n = 2, 5, 3
+    Z = rnd(51, v, v, n)
+    for (i, j, a, b, c, d) in [(0, 1, 2, 4, 1, 3), (1, 1, 0, 0, 4, 2), (1, 0, 3, 1, 1, 3)]:
+        w = np.zeros((o, o, v, v)); w[i, j, a, b] = 1.0
+        tau = np.zeros((o, o, v, v)); tau[i, j, c, d] = 1.0
+        W = gi.w(o, v, n, Z, tau, w)
+        ref = np.zeros((v, v, n)); ref[a, c] = Z[b, d]
+        assert np.array_equal(W, ref), (i, j, a, b, c, d)
+
+
+def test_w_intermediate_with_L_contracts_to_energy(gi, oracle_lib):
+    """With Z = L: sum_K sum_pq L^K_pq W^K_pq = sum_pqrs (pq|rs) d_pqrs = E (Sec. II A energy),
+    and under pair symmetry 2 W = X = dE/dL."""
+    o, v, n = 3, 5, 4
+    L, tau, w = rnd(52, v, v, n), pair_sym(rnd(53, o, o, v, v)), pair_sym(rnd(54, o, o, v, v))
+    _, E = oracle_lib.forward(o, v, n, L, tau, w)
+    W = gi.w(o, v, n, L, tau, w)
+    assert abs(np.sum(L * W) - E) <= 1e-13 * np.sum(np.abs(L * W))
+    X = oracle_lib.adjoint(o, v, n, L, tau, w)
+    np.testing.assert_allclose(2.0 * W, X, rtol=0, atol=1e-13 * np.abs(X).max())
+    # the energy identity holds for generic (non pair-symmetric) inputs too
+    tau2, w2 = rnd(55, o, o, v, v), rnd(56, o, o, v, v)
+    _, E2 = oracle_lib.forward(o, v, n, L, tau2, w2)
+    W2 = gi.w(o, v, n, L, tau2, w2)
+    assert abs(np.sum(L * W2) - E2) <= 1e-13 * np.sum(np.abs(L * W2))
+
+
+def test_metric_contraction(gi, oracle_lib):
+    """Rank-one closed form, V(Z, W)^T = V(W, Z), and with Z = L, W = W(L): trace V = E."""
+    v, n = 4, 3
+    u, t = rnd(57, v, v), rnd(58, v, v)
+    Z = np.zeros((v, v, n)); Z[:, :, 2] = u
+    W = np.zeros((v, v, n)); W[:, :, 0] = t
+    V = gi.v(v, n, Z, W)
+    ref = np.zeros((n, n)); ref[2, 0] = np.sum(u * t)
+    np.testing.assert_allclose(V, ref, rtol=0, atol=1e-14)
+    Z, W = rnd(59, v, v, n), rnd(60, v, v, n)
+    np.testing.assert_allclose(gi.v(v, n, Z, W).T, gi.v(v, n, W, Z), rtol=0, atol=1e-14)
+    o = 2
+    L, tau, w = rnd(61, v, v, n), rnd(62, o, o, v, v), rnd(63, o, o, v, v)
+    _, E = oracle_lib.forward(o, v, n, L, tau, w)
+    Vl = gi.v(v, n, L, gi.w(o, v, n, L, tau, w))
+    assert abs(np.trace(Vl) - E) <= 1e-13 * np.abs(Vl).sum()
+
+
+def test_back_transform(gi):
+    """Identity and permutation matrices act exactly; two transformations compose:
+    BT(x2, y2, BT(x1, y1, W)) = BT(x1 x2, y1 y2, W); y = 1 leaves x^T W per K."""
+    v, n = 5, 3
+    W = rnd(64, v, v, n)
+    I = np.eye(v)
+    assert np.array_equal(gi.bt(v, n, I, I, W), W)
+    p1, p2 = np.random.default_rng(65).permutation(v), np.random.default_rng(66).permutation(v)
+    P1, P2 = I[p1].T, I[p2].T      # P[r][p] = [r = p1[p]]
+    assert np.array_equal(gi.bt(v, n, P1, P2, W), W[p1][:, p2])
+    x1, y1, x2, y2 = rnd(67, v, v), rnd(68, v, v), rnd(69, v, v), rnd(70, v, v)
+    two = gi.bt(v, n, x2, y2, gi.bt(v, n, x1, y1, W))
+    one = gi.bt(v, n, x1 @ x2, y1 @ y2, W)
+    np.testing.assert_allclose(two, one, rtol=0, atol=1e-12 * np.abs(one).max())
+    xo = gi.bt(v, n, x1, I, W)
+    np.testing.assert_allclose(xo, np.einsum("rp,rqK->pqK", x1, W), rtol=0, atol=1e-13 * np.abs(xo).max())
+    # x and y are not interchangeable
+    assert np.abs(gi.bt(v, n, x1, y1, W) - gi.bt(v, n, y1, x1, W)).max() > 1e-3
+
+
 # ---------------------------------------------------------------- ranges and samples
 def test_ranges_and_samples_agree_with_full(oracle_lib):
     o, v, n = 2, 7, 4
