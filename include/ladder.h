@@ -174,6 +174,21 @@ int ladder_back_transform(int64_t v, int64_t n, const double* x, const double* y
                           void* stream);
 
 /*
+ * Excited-state doubles amplitudes U for the excited-state V^4 density
+ * d^es_abcd = O^(2)_abcd(L_2, U) (Appendix A), from the ground-state T_2, the
+ * excited-state R_2 and the reference weight R_0.  The paper defines U twice:
+ *   LADDER_U_TABLE    (0): U = T_2 R_0 + R_2                  (table of intermediates, Sec. II B)
+ *   LADDER_U_APPENDIX (1): U = T_2 R_0 / 2 + Rt_2, Rt_ij^ab = 2 R_ij^ab - R_ji^ab   (Appendix A)
+ * The excited-state V^4 contribution to the three-index intermediate is then
+ * ladder_adjoint(Z or L, U, L_2).  U may equal T (in place) but must not overlap
+ * R2.  Pair-symmetric T and R2 give pair-symmetric U in both modes.  FP64.
+ */
+#define LADDER_U_TABLE 0
+#define LADDER_U_APPENDIX 1
+int ladder_excited_amplitudes(int64_t o, int64_t v, double R0, const double* T, const double* R2, int mode,
+                              double* U, void* stream);
+
+/*
  * First-order doubles amplitudes from the occupied-virtual Cholesky block (the
  * synthetic stand-in for converged T2; Cholesky expansion of Sec. II A):
  *   t_ij^ab = (sum_J L^J_ia L^J_jb) / ((eps_i + eps_j) - (eps_a + eps_b)).

@@ -267,6 +267,28 @@ int oracle_back_transform_range(int64_t v, int64_t n, const double* x, const dou
 }
 
 /*
+ * Excited-state amplitudes entering the excited-state V^4 density
+ * d^es_abcd = O^(2)_abcd(L_2, U) (Appendix A); the paper gives two definitions:
+ *   mode 0 (table of intermediates): U_ij^ab = R0 T_ij^ab + R_ij^ab
+ *   mode 1 (Appendix A):             U_ij^ab = (R0/2) T_ij^ab + (2 R_ij^ab - R_ji^ab)
+ */
+int oracle_excited_amplitudes(int64_t o, int64_t v, double R0, const double* T, const double* R2, int mode,
+                              double* U) {
+    if (bad_dims(o, v, 1) || !T || !R2 || !U || (mode != 0 && mode != 1)) return -1;
+    for (int64_t i = 0; i < o; ++i)
+        for (int64_t j = 0; j < o; ++j)
+            for (int64_t a = 0; a < v; ++a)
+                for (int64_t b = 0; b < v; ++b) {
+                    const int64_t x = ((i * o + j) * v + a) * v + b, xs = ((j * o + i) * v + a) * v + b;
+                    if (mode == 0)
+                        U[x] = R0 * T[x] + R2[x];
+                    else
+                        U[x] = 0.5 * R0 * T[x] + (2.0 * R2[x] - R2[xs]);
+                }
+    return 0;
+}
+
+/*
  * Adjoint for the range p in [p_lo, p_hi), general (no pair symmetry assumed):
  *   D1[b][q][d] = sum_ij w_ij^pb tau_ij^qd
  *   D2[b][d][q] = sum_ij w_ij^bp tau_ij^dq

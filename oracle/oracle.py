@@ -23,7 +23,7 @@ LIB = os.path.join(HERE, "liboracle.so")
 __all__ = [
     "build", "load", "forward", "adjoint", "forward_range", "adjoint_range", "R_sample",
     "X_sample", "tau_gradient", "tau_gradient_range", "w_intermediate", "w_intermediate_range",
-    "metric_contraction", "back_transform", "back_transform_range", "mp2_amplitudes", "amplitude_update", "make_inputs",
+    "metric_contraction", "back_transform", "back_transform_range", "excited_amplitudes", "mp2_amplitudes", "amplitude_update", "make_inputs",
     "num_threads",
     "set_num_threads", "flops_forward", "flops_adjoint", "matrix",
 ]
@@ -56,6 +56,7 @@ def load():
         lib.oracle_ladder_tau_gradient_range.argtypes = [i64, i64, i64, dp, dp, i64, i64, dp]
         lib.oracle_w_intermediate_range.argtypes = [i64, i64, i64, dp, dp, dp, i64, i64, dp]
         lib.oracle_metric_contraction.argtypes = [i64, i64, dp, dp, dp]
+        lib.oracle_excited_amplitudes.argtypes = [i64, i64, ctypes.c_double, dp, dp, ctypes.c_int, dp]
         lib.oracle_back_transform_range.argtypes = [i64, i64, dp, dp, dp, i64, i64, dp]
         lib.oracle_mp2_amplitudes.argtypes = [i64, i64, i64, dp, dp, dp]
         lib.oracle_amplitude_update.argtypes = [i64, i64, dp, dp, dp]
@@ -63,7 +64,8 @@ def load():
         lib.oracle_set_num_threads.argtypes = [ctypes.c_int]
         for f in ("oracle_ladder_forward_range", "oracle_ladder_adjoint_range", "oracle_ladder_R_sample",
                   "oracle_ladder_X_sample", "oracle_ladder_tau_gradient_range", "oracle_w_intermediate_range",
-                  "oracle_metric_contraction", "oracle_back_transform_range", "oracle_mp2_amplitudes",
+                  "oracle_metric_contraction", "oracle_back_transform_range", "oracle_excited_amplitudes",
+                  "oracle_mp2_amplitudes",
                   "oracle_amplitude_update"):
             getattr(lib, f).restype = ctypes.c_int
         _lib = lib
@@ -175,6 +177,15 @@ def back_transform_range(v, n, x, y, W, K_lo, K_hi, Wmo=None):
 
 def back_transform(v, n, x, y, W):
     return back_transform_range(v, n, x, y, W, 0, n)
+
+
+def excited_amplitudes(o, v, R0, T, R2, mode):
+    """U for the excited-state V^4 density (mode 0: R0 T + R2; mode 1: R0 T/2 + 2 R2 - R2(i<->j))."""
+    T = _f64(T, (o, o, v, v)); R2 = _f64(R2, (o, o, v, v))
+    U = np.zeros((o, o, v, v))
+    if load().oracle_excited_amplitudes(o, v, float(R0), _p(T), _p(R2), int(mode), _p(U)) != 0:
+        raise RuntimeError("oracle_excited_amplitudes failed")
+    return U
 
 
 def R_sample(o, v, n, L, tau, ab):

@@ -407,6 +407,20 @@ __global__ void amplitude_update_kernel(const double* __restrict__ eps, const do
     }
 }
 
+// Excited-state amplitudes: mode 0: U = R0 T + R2; mode 1: U = (R0/2) T + 2 R2 - R2(i<->j).
+__global__ void excited_amplitudes_kernel(double R0, const double* __restrict__ T, const double* __restrict__ R2,
+                                          int mode, double* __restrict__ U, int64_t o, int64_t v) {
+    const int64_t total = o * o * v * v, vv = v * v;
+    for (int64_t x = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; x < total; x += (int64_t)gridDim.x * blockDim.x) {
+        if (mode == 0) {
+            U[x] = R0 * T[x] + R2[x];
+        } else {
+            const int64_t ab = x % vv, ij = x / vv, i = ij / o, j = ij % o;
+            U[x] = 0.5 * R0 * T[x] + (2.0 * R2[x] - R2[(j * o + i) * vv + ab]);
+        }
+    }
+}
+
 // Grid of the tiled packing kernels: tile pairs in x, rows over (y, z).
 dim3 pm_grid(int64_t v, int64_t rows) {
     const int64_t gy = std::min<int64_t>(std::max<int64_t>(rows, 1), 65535);
@@ -1035,6 +1049,24 @@ int ladder_amplitude_update(int64_t o, int64_t v, const double* eps, const doubl
     hipLaunchKernelGGL(amplitude_update_kernel, dim3(grid_for(s.ovv_elems)), dim3(256), 0, (hipStream_t)stream, eps, R,
                        t, o, v);
     return hip_check(hipGetLastError(), "amplitude update launch");
+}
+
+int ladder_excited_amplitudes(int64_t o, int64_t v, double R0, const double* T, const double* R2, int mode, double* U,
+                              void* stream) {
+    g_last_error.clear();
+    Sizes s;
+    int rc;
+    if ((rc = check_dims(o, v, 1, s))) return rc;
+    if (mode != LADDER_U_TABLE && mode != LADDER_U_APPENDIX) return fail(LADDER_EUNSUPPORTED, "mode %d", mode);
+    if (!T || !R2 || !U) return fail(LADDER_EINVAL, "T, R2 and U must be non-NULL");
+    if (!aligned8(T) || !aligned8(R2) || !aligned8(U)) return fail(LADDER_EINVAL, "misaligned pointer");
+    const int64_t b = s.ovv_elems * 8;
+    if (overlap(U, b, R2, b) || (U != T && overlap(U, b, T, b)))
+        return fail(LADDER_EINVAL, "U overlaps R2 (or partially overlaps T)");
+    StageTimer tm(LADDER_STAGE_UPDATE, 3.0 * (double)s.ovv_elems, 24.0 * (double)s.ovv_elems, (hipStream_t)stream);
+    hipLaunchKernelGGL(excited_amplitudes_kernel, dim3(grid_for(s.ovv_elems)), dim3(256), 0, (hipStream_t)stream, R0, T,
+                       R2, mode, U, o, v);
+    return hip_check(hipGetLastError(), "excited amplitudes launch");
 }
 
 int ladder_batched_workspace_size(int count, const ladder_instance* inst, uint32_t what, const ladder_options* opts,

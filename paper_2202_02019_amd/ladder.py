@@ -22,11 +22,13 @@ FLAG_GENERAL = 1
 FLAG_DENSE = 2
 DO_FORWARD = 1
 DO_ADJOINT = 2
+U_TABLE = 0
+U_APPENDIX = 1
 
 EXPORTS = (
     "ladder_default_options", "ladder_workspace_size", "ladder_forward", "ladder_adjoint",
     "ladder_tau_gradient_workspace_size", "ladder_tau_gradient", "ladder_metric_contraction",
-    "ladder_back_transform_workspace_size", "ladder_back_transform",
+    "ladder_back_transform_workspace_size", "ladder_back_transform", "ladder_excited_amplitudes",
     "ladder_mp2_amplitudes", "ladder_amplitude_update", "ladder_batched_workspace_size",
     "ladder_batched", "ladder_strerror", "ladder_last_error", "ladder_shutdown",
     "ladder_profile_start", "ladder_profile_stop",
@@ -96,6 +98,7 @@ def _load():
     lib.ladder_metric_contraction.argtypes = [i64, i64, vp, vp, dbl, dbl, vp, vp]
     lib.ladder_back_transform_workspace_size.argtypes = [i64, i64, ctypes.POINTER(sz)]
     lib.ladder_back_transform.argtypes = [i64, i64, vp, vp, vp, dbl, dbl, vp, vp, sz, vp]
+    lib.ladder_excited_amplitudes.argtypes = [i64, i64, dbl, vp, vp, ctypes.c_int, vp, vp]
     lib.ladder_mp2_amplitudes.argtypes = [i64, i64, i64, vp, vp, vp, vp]
     lib.ladder_amplitude_update.argtypes = [i64, i64, vp, vp, vp, vp]
     lib.ladder_batched_workspace_size.argtypes = [ctypes.c_int, ctypes.POINTER(_CInstance), ctypes.c_uint32, op,
@@ -103,7 +106,7 @@ def _load():
     lib.ladder_batched.argtypes = [ctypes.c_int, ctypes.POINTER(_CInstance), ctypes.c_uint32, vp, sz, op, vp]
     for f in ("ladder_workspace_size", "ladder_forward", "ladder_adjoint", "ladder_tau_gradient_workspace_size",
               "ladder_tau_gradient", "ladder_metric_contraction", "ladder_back_transform_workspace_size",
-              "ladder_back_transform", "ladder_mp2_amplitudes",
+              "ladder_back_transform", "ladder_excited_amplitudes", "ladder_mp2_amplitudes",
               "ladder_amplitude_update", "ladder_batched_workspace_size", "ladder_batched"):
         getattr(lib, f).restype = ctypes.c_int
     lib.ladder_strerror.argtypes = [ctypes.c_int]
@@ -266,6 +269,16 @@ def back_transform(x, y, W, *, v, n, Wmo=None, alpha=1.0, beta=0.0, ws=None, str
     _check(_load().ladder_back_transform(v, n, _ptr(x), _ptr(y), _ptr(W), float(alpha), float(beta), _ptr(Wmo),
                                          _ptr(wsb), wsb.numel() * wsb.element_size(), _stream(stream)))
     return Wmo
+
+
+def excited_amplitudes(T, R2, R0, *, o, v, mode=U_APPENDIX, U=None, stream=None):
+    """U for the excited-state V^4 density: U_TABLE: R0 T + R2; U_APPENDIX: R0 T / 2 + 2 R2 - R2(i<->j)."""
+    _need(T, "T", (o, o, v, v)); _need(R2, "R2", (o, o, v, v))
+    if U is None:
+        U = torch.empty((o, o, v, v), dtype=torch.float64, device=T.device)
+    _need(U, "U", (o, o, v, v))
+    _check(_load().ladder_excited_amplitudes(o, v, float(R0), _ptr(T), _ptr(R2), int(mode), _ptr(U), _stream(stream)))
+    return U
 
 
 def mp2_amplitudes(Lov, eps, *, o, v, n, t=None, stream=None):

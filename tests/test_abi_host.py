@@ -136,6 +136,10 @@ def test_amplitude_entry_validation():
     assert lib.ladder_mp2_amplitudes(2, 2, 2, FAKE, 2 * FAKE, FAKE, None) == EINVAL  # t overlaps Lov
     assert lib.ladder_amplitude_update(2, 2, None, FAKE, 2 * FAKE, None) == EINVAL
     assert lib.ladder_amplitude_update(2, 2, 3 * FAKE, FAKE + 8, FAKE, None) == EINVAL  # partial overlap
+    assert lib.ladder_excited_amplitudes(2, 2, 1.0, FAKE, 2 * FAKE, 2, 3 * FAKE, None) == EUNSUPPORTED  # mode
+    assert lib.ladder_excited_amplitudes(2, 2, 1.0, None, 2 * FAKE, 0, 3 * FAKE, None) == EINVAL
+    assert lib.ladder_excited_amplitudes(2, 2, 1.0, FAKE, 2 * FAKE, 0, 2 * FAKE, None) == EINVAL  # U is R2
+    assert lib.ladder_excited_amplitudes(2, 2, 1.0, FAKE, 2 * FAKE, 0, FAKE + 8, None) == EINVAL  # partial overlap
 
 
 def test_strerror_and_options():

@@ -559,3 +559,26 @@ def test_metric_and_back_transform_retinal_sampled(dev):
         eW = max(eW, err_norm(Wmo[:, :, K:K + 1].cpu().numpy(), Wr))
     print("retinal shape: err V %.3e err Wmo %.3e" % (eV, eW))
     assert eV <= TOL and eW <= TOL
+
+
+# ------------------------------------------------------------------ excited-state V^4 density
+@pytest.mark.parametrize("mode", [P.U_TABLE, P.U_APPENDIX])
+def test_excited_amplitudes_and_density(dev, mode):
+    """U on the GPU equals the oracle's (dyadic inputs: exact), and the excited-state V^4
+    contribution ladder_adjoint(L, U, L2) matches the oracle chain."""
+    o, v, n = 4, 20, 30
+    rng = np.random.default_rng(90 + mode)
+    T = np.round(rng.standard_normal((o, o, v, v)) * 64) / 64
+    R2 = np.round(rng.standard_normal((o, o, v, v)) * 64) / 64
+    T, R2 = 0.5 * (T + T.transpose(1, 0, 3, 2)), 0.5 * (R2 + R2.transpose(1, 0, 3, 2))
+    U = P.excited_amplitudes(g(T, dev), g(R2, dev), 0.75, o=o, v=v, mode=mode).cpu().numpy()
+    Ur = oracle.excited_amplitudes(o, v, 0.75, T, R2, mode)
+    assert np.array_equal(U, Ur)
+    L, _, L2 = gaussian_inputs(92, o, v, n)
+    X = P.adjoint(g(L, dev), g(U, dev), g(L2, dev), o=o, v=v, n=n).cpu().numpy()
+    Xr = oracle.adjoint(o, v, n, L, Ur, L2)
+    assert err_norm(X, Xr) <= TOL
+    # in place: U written over T
+    Tg = g(T, dev)
+    P.excited_amplitudes(Tg, g(R2, dev), 0.75, o=o, v=v, mode=mode, U=Tg)
+    assert np.array_equal(Tg.cpu().numpy(), Ur)

@@ -374,6 +374,26 @@ def test_back_transform(gi):
     assert np.abs(gi.bt(v, n, x1, y1, W) - gi.bt(v, n, y1, x1, W)).max() > 1e-3
 
 
+# ---------------------------------------------------------------- excited-state amplitudes
+def test_excited_amplitudes(oracle_lib):
+    """Special cases of both readings: R0 = 0 or R2 = 0 isolate one term; a unit R2 at
+    (i, j, a, b), i != j, gives 2 there and -1 at (j, i, a, b) in the Appendix reading;
+    pair-symmetric T and R2 give a pair-symmetric U."""
+    o, v = 3, 4
+    T, R2 = rnd(81, o, o, v, v), rnd(82, o, o, v, v)
+    assert np.array_equal(oracle_lib.excited_amplitudes(o, v, 0.0, T, R2, 0), R2)
+    assert np.array_equal(oracle_lib.excited_amplitudes(o, v, 0.75, T, np.zeros_like(R2), 0), 0.75 * T)
+    assert np.array_equal(oracle_lib.excited_amplitudes(o, v, 0.75, T, np.zeros_like(R2), 1), 0.375 * T)
+    E1 = np.zeros((o, o, v, v)); E1[0, 2, 1, 3] = 1.0
+    U = oracle_lib.excited_amplitudes(o, v, 0.3, np.zeros_like(T), E1, 1)
+    ref = np.zeros_like(U); ref[0, 2, 1, 3] = 2.0; ref[2, 0, 1, 3] = -1.0
+    assert np.array_equal(U, ref)
+    Ts, Rs = pair_sym(T), pair_sym(R2)
+    for mode in (0, 1):
+        U = oracle_lib.excited_amplitudes(o, v, 0.9, Ts, Rs, mode)
+        np.testing.assert_allclose(U, U.transpose(1, 0, 3, 2), rtol=0, atol=1e-15)
+
+
 # ---------------------------------------------------------------- ranges and samples
 def test_ranges_and_samples_agree_with_full(oracle_lib):
     o, v, n = 2, 7, 4
