@@ -200,8 +200,13 @@ struct Plan {
     SlicedBuf tp_cd, tm_cd, gp_sl, gm_sl;                               // forward, split
     size_t a_wp = 0, a_wm = 0, a_tp = 0, a_tm = 0, a_dp = 0, a_dm = 0;  // adjoint, FP64
     SlicedBuf wp_ij, wm_ij, tp_ij, tm_ij;                               // adjoint, split
+    // split-K partial tiles of the long-K split GEMMs (GEMM-C on the +/- path, GEMM-F)
+    size_t f_skp = 0, a_skp = 0;
+    int64_t f_skp_elems = 0, a_skp_elems = 0;
     size_t fwd_total = 0, adj_total = 0, total = 0;
 };
+
+constexpr int64_t KSPLIT_MAX = 4;
 
 constexpr int PM_UNPACK_GRID = 1024;  // blocks of the R unpack kernel (one energy partial each)
 
@@ -258,6 +263,8 @@ Plan make_plan(int64_t o, int64_t v, int64_t n, const ladder_options& op, const 
             p.tm_cd = take_sliced(f, p.S, std::max<int64_t>(p.Q2o, 1), std::max<int64_t>(p.Q2v, 1));
             p.gp_sl = take_sliced(f, p.S, p.NP, p.P2v);
             p.gm_sl = take_sliced(f, p.S, std::max<int64_t>(p.NM, 1), std::max<int64_t>(p.Q2v, 1));
+            p.f_skp_elems = KSPLIT_MAX * std::max(p.P2o * p.NP, p.Q2o * p.NM);
+            p.f_skp = f.take((size_t)p.f_skp_elems * 8);
         }
     }
     p.fwd_total = f.top;
@@ -289,6 +296,10 @@ Plan make_plan(int64_t o, int64_t v, int64_t n, const ladder_options& op, const 
             p.L_bd = take_sliced(d, p.S, n, s.vv);
         }
     }
+    if (p.S) {
+        p.a_skp_elems = KSPLIT_MAX * nA * v * n;
+        p.a_skp = d.take((size_t)p.a_skp_elems * 8);
+    }
     p.adj_total = d.top;
     (void)common;
     p.total = std::max(p.fwd_total, p.adj_total);
@@ -319,9 +330,46 @@ SplitOperand view(char* ws, const SlicedBuf& b, int64_t row0) {
 
 template <int S, int STAGE, class Epi>
 hipError_t launch_split_s(const SplitShape& sh, const Epi& epi, hipStream_t st) {
-    hipLaunchKernelGGL((gemm_split_kernel<S, Epi, STAGE>), dim3((unsigned)tiles(sh.M, sh.N)), dim3(SPLIT_THREADS), 0, st,
-                       sh, epi);
+    hipLaunchKernelGGL((gemm_split_kernel<S, Epi, STAGE>), dim3((unsigned)(tiles(sh.M, sh.N) * sh.ksplit)),
+                       dim3(SPLIT_THREADS), 0, st, sh, epi);
+    if (sh.ksplit > 1) {
+        const int64_t blocks = std::min<int64_t>((sh.M * sh.N + 255) / 256, 4096);
+        hipLaunchKernelGGL((splitk_reduce_kernel<Epi>), dim3((unsigned)blocks), dim3(256), 0, st, sh.part, sh.M, sh.N,
+                           sh.ksplit, epi);
+    }
     return hipGetLastError();
+}
+
+// Compute units of the current device (cached per device).
+int64_t device_cus() {
+    static int64_t cus[64] = {0};
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return 256;
+    if (!cus[dev]) {
+        int c = 0;
+        cus[dev] = (hipDeviceGetAttribute(&c, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess && c > 0) ? c : 256;
+    }
+    return cus[dev];
+}
+
+// Split-K factor for a split GEMM whose epilogue needs no per-tile energy partial:
+// the number of K-splits s (whole 256-chunks each, at most KSPLIT_MAX, s*M*N partial
+// doubles within `room`) that minimises the waves of workgroups per unit of work,
+// ceil(tiles*s / CUs) / s, taken only when it saves at least 4% over s = 1.
+int64_t choose_ksplit(int64_t M, int64_t N, int64_t K, int64_t room) {
+    const int64_t T = tiles(M, N), cus = device_cus(), nch = split_nchunk(K);
+    double best = (double)((T + cus - 1) / cus);
+    const double base = best;
+    int64_t pick = 1;
+    for (int64_t s = 2; s <= std::min(KSPLIT_MAX, nch); ++s) {
+        if (s * M * N > room) break;
+        const double c = (double)((T * s + cus - 1) / cus) / (double)s;
+        if (c < best * 0.99) {
+            best = c;
+            pick = s;
+        }
+    }
+    return best <= 0.96 * base ? pick : 1;
 }
 
 template <int STAGE, class Epi>
@@ -521,6 +569,8 @@ int forward_pm(int64_t o, int64_t v, int64_t n, const double* L, const double* t
                 e = launch_gemm<true, true, LADDER_STAGE_GEMM_C>(sign ? tm : tp, K, sign ? gm : gp, K, M, N, K, er, st);
             } else {
                 SplitShape sh{view(w, sign ? p.tm_cd : p.tp_cd, 0), view(w, sign ? gms : gps, 0), M, N, K};
+                sh.ksplit = choose_ksplit(M, N, K, p.f_skp_elems);
+                sh.part = (double*)(w + p.f_skp);
                 e = launch_split<LADDER_STAGE_GEMM_C>(S, sh, er, st);
             }
             if ((rc = hip_check(e, "GEMM-C launch"))) return rc;
@@ -610,6 +660,8 @@ int adjoint_pm(int64_t o, int64_t v, int64_t n, const double* L, const double* t
                 SlicedBuf tl = p.tile_sl;
                 tl.R = nA * v;
                 SplitShape sh{view(w, tl, 0), view(w, p.L_bd, 0), nA * v, n, s.vv};
+                sh.ksplit = choose_ksplit(nA * v, n, s.vv, p.a_skp_elems);
+                sh.part = (double*)(w + p.a_skp);
                 e = launch_split<LADDER_STAGE_GEMM_F>(S, sh, ex, st);
             }
             if ((rc = hip_check(e, "GEMM-F launch"))) return rc;
@@ -962,6 +1014,8 @@ int ladder_adjoint(int64_t o, int64_t v, int64_t n, const double* L, const doubl
                 SlicedBuf tl = p.tile_sl;
                 tl.R = nA * v;
                 SplitShape sh{view(w, tl, 0), view(w, p.L_bd, 0), nA * v, n, s.vv};
+                sh.ksplit = choose_ksplit(nA * v, n, s.vv, p.a_skp_elems);
+                sh.part = (double*)(w + p.a_skp);
                 e = launch_split<LADDER_STAGE_GEMM_F>(S, sh, ex, st);
             }
             if ((rc = hip_check(e, "GEMM-F launch"))) return rc;

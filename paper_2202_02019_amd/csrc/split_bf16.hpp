@@ -179,8 +179,16 @@ struct SplitOperand {
 
 struct SplitShape {
     SplitOperand a, b;
-    int64_t M, N, K;  // K = real length (chunks and padding follow from it)
+    int64_t M, N, K;      // K = real length (chunks and padding follow from it)
+    int64_t ksplit = 1;   // > 1: the chunks are dealt to ksplit workgroups per tile, each of
+    double* part = nullptr;  // which stores its raw FP64 sum at part[split][M][N]
 };
+
+// Chunks [c0, c1) of split s out of ksplit (contiguous, as even as possible).
+__host__ __device__ inline void split_chunk_range(int64_t nch, int64_t ksplit, int64_t s, int64_t& c0, int64_t& c1) {
+    c0 = nch * s / ksplit;
+    c1 = nch * (s + 1) / ksplit;
+}
 
 // 512 threads = 8 waves in a 4 x 2 grid; wave (wm, wn) owns rows wm*32 .. +32 and
 // columns wn*64 .. +64 of the 128 x 128 tile (two 32x32 MFMA blocks), so two
@@ -248,12 +256,19 @@ __global__ __launch_bounds__(SPLIT_THREADS) void gemm_split_kernel(SplitShape sh
     const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);  // wave-uniform: keeps the roles in SGPRs
     const int wm = wave >> 1, wn = wave & 1;
     TileMap tmap{(sh.M + SPLIT_BM - 1) / SPLIT_BM, (sh.N + SPLIT_BN - 1) / SPLIT_BN};
+    const int64_t T = tmap.tiles_m * tmap.tiles_n;
+    const int64_t ksplit = sh.ksplit;
+    const int64_t split = (int64_t)blockIdx.x / T;  // grid = T * ksplit; one split's tiles are consecutive
     int64_t ti, tj;
-    map_tile(blockIdx.x, (int64_t)gridDim.x, tmap, ti, tj);
+    map_tile((int64_t)blockIdx.x - split * T, T, tmap, ti, tj);
     const int64_t m0 = ti * SPLIT_BM, n0 = tj * SPLIT_BN;
     const int64_t Kp = split_kpad(sh.K);
-    const int64_t nk = Kp / SPLIT_BK;
     constexpr int STEPS_PER_CHUNK = SPLIT_KC / SPLIT_BK;
+    // K-steps [kbeg, kend) of this workgroup: whole chunks, so chunk parity and exponents are unchanged
+    int64_t c0, c1;
+    split_chunk_range(split_nchunk(sh.K), ksplit, split, c0, c1);
+    const int64_t kbeg = c0 * STEPS_PER_CHUNK;
+    const int64_t kend = (c1 * STEPS_PER_CHUNK < Kp / SPLIT_BK) ? c1 * STEPS_PER_CHUNK : Kp / SPLIT_BK;
 
     // DMA role: waves 0-3 load A, 4-7 load B; wave w%4 covers slots 64*(w%4) .. +64
     // (rows 32*(w%4) .. +32) of every slice.  Lane i fills slot 64*(w%4) + i.
@@ -303,12 +318,12 @@ __global__ __launch_bounds__(SPLIT_THREADS) void gemm_split_kernel(SplitShape sh
 
     // One K-step on ring buffer `cur`, while step kt+2 is loaded into `nxt`.
     auto step = [&](SplitRing<S>& cur, SplitRing<S>& nxt, int64_t kt) {
-        if (kt + 1 < nk)  // this wave's step-kt loads are done once at most S (step kt+1) remain
+        if (kt + 1 < kend)  // this wave's step-kt loads are done once at most S (step kt+1) remain
             __builtin_amdgcn_s_waitcnt((S & 0xF) | ((S >> 4) << 14) | (0x7 << 4) | (0xF << 8));
         else
             __builtin_amdgcn_s_waitcnt((0x7 << 4) | (0xF << 8));
         __builtin_amdgcn_s_barrier();  // every wave's step-kt loads landed; step kt-1 reads are finished
-        if (kt + 2 < nk) dma(nxt, kt + 2);
+        if (kt + 2 < kend) dma(nxt, kt + 2);
 
         bx8 bq[S][2];
 #pragma unroll
@@ -328,7 +343,7 @@ __global__ __launch_bounds__(SPLIT_THREADS) void gemm_split_kernel(SplitShape sh
             }
         }
 
-        if (((kt + 1) % STEPS_PER_CHUNK) == 0 || kt + 1 == nk) {  // fold the exact FP32 chunk sums into FP64
+        if (((kt + 1) % STEPS_PER_CHUNK) == 0 || kt + 1 == kend) {  // fold the exact FP32 chunk sums into FP64
             const int par = (int)((kt / STEPS_PER_CHUNK) & 1);
             const int eb0 = lexp[par][1][wn * 64 + (lane & 31)];
             const int eb1 = lexp[par][1][wn * 64 + 32 + (lane & 31)];
@@ -352,16 +367,30 @@ __global__ __launch_bounds__(SPLIT_THREADS) void gemm_split_kernel(SplitShape sh
         }
     };
 
-    dma(ring0, 0);
-    if (nk > 1) dma(ring1, 1);
-    for (int64_t kt = 0; kt < nk; kt += 3) {
-        step(ring0, ring2, kt);
-        if (kt + 1 < nk) step(ring1, ring0, kt + 1);
-        if (kt + 2 < nk) step(ring2, ring1, kt + 2);
+    if (kbeg < kend) {  // uniform per workgroup; a split may own no chunk only when ksplit > chunks
+        dma(ring0, kbeg);
+        if (kbeg + 1 < kend) dma(ring1, kbeg + 1);
+        for (int64_t kt = kbeg; kt < kend; kt += 3) {
+            step(ring0, ring2, kt);
+            if (kt + 1 < kend) step(ring1, ring0, kt + 1);
+            if (kt + 2 < kend) step(ring2, ring1, kt + 2);
+        }
     }
 
     // D layout of v_mfma_f32_32x32x16_bf16 (measured on gfx950): lane l, element r
     // holds row 8*(r/4) + 4*(l/32) + r%4, column l%32.
+    if (ksplit > 1) {  // raw partial sums; the reduction kernel applies the epilogue
+        double* part = sh.part + split * sh.M * sh.N;
+#pragma unroll
+        for (int bj = 0; bj < 2; ++bj)
+#pragma unroll
+            for (int r = 0; r < 16; ++r) {
+                const int64_t m = m0 + wm * 32 + 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);
+                const int64_t n = n0 + wn * 64 + 32 * bj + (lane & 31);
+                if (m < sh.M && n < sh.N) part[m * sh.N + n] = acc64[bj][r];
+            }
+        return;
+    }
     typename Epi::Local loc = epi.begin();
 #pragma unroll
     for (int bj = 0; bj < 2; ++bj)
@@ -371,6 +400,22 @@ __global__ __launch_bounds__(SPLIT_THREADS) void gemm_split_kernel(SplitShape sh
             const int64_t n = n0 + wn * 64 + 32 * bj + (lane & 31);
             if (m < sh.M && n < sh.N) epi.put(loc, m, n, acc64[bj][r]);
         }
+    epi.finish(loc, blockIdx.x);
+}
+
+// Sums the ksplit partial tiles of a split-K GEMM in split order (deterministic)
+// and hands every element to the epilogue.  Any grid; needs all threads of a
+// block in finish.
+template <class Epi>
+__global__ __launch_bounds__(256) void splitk_reduce_kernel(const double* __restrict__ part, int64_t M, int64_t N,
+                                                            int64_t ksplit, Epi epi) {
+    typename Epi::Local loc = epi.begin();
+    const int64_t MN = M * N;
+    for (int64_t x = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; x < MN; x += (int64_t)gridDim.x * blockDim.x) {
+        double s = part[x];
+        for (int64_t k = 1; k < ksplit; ++k) s += part[k * MN + x];
+        epi.put(loc, x / N, x % N, s);
+    }
     epi.finish(loc, blockIdx.x);
 }
 
