@@ -167,7 +167,7 @@ struct SlicedBuf {
     size_t s_off = 0, e_off = 0;
     int64_t R = 0, K = 0;
 };
-size_t slice_bytes(int S, int64_t R, int64_t K) { return (size_t)S * (size_t)R * (size_t)split_kpad(K) * 2; }
+size_t slice_bytes(int S, int64_t R, int64_t K) { return (size_t)S * (size_t)split_slice_stride(R, K) * 2; }
 size_t exp_bytes(int64_t R, int64_t K) { return (size_t)split_nchunk(K) * (size_t)R * 4; }
 SlicedBuf take_sliced(Arena& a, int S, int64_t R, int64_t K) {
     SlicedBuf b;
@@ -320,9 +320,10 @@ hipError_t launch_gemm(const double* A, int64_t lda, const double* B, int64_t ld
 SplitOperand view(char* ws, const SlicedBuf& b, int64_t row0) {
     SplitOperand v;
     const int64_t Kp = split_kpad(b.K);
-    v.s = (const unsigned short*)(ws + b.s_off) + row0 * 16;
-    v.slice_stride = b.R * Kp;
-    v.kstride = b.R * 16;
+    v.s = (const unsigned short*)(ws + b.s_off);
+    v.slice_stride = split_slice_stride(b.R, b.K);
+    v.row_off = row0;
+    v.nkb = Kp / 16;
     v.e = (const int*)(ws + b.e_off) + row0;
     v.e_ld = b.R;
     return v;
@@ -497,6 +498,9 @@ int check_split_dims(const Sizes& s, int64_t n, const ladder_options& op) {
     const int64_t kmax = std::max(std::max(s.vv, s.oo), n);
     if ((s.vv / 16 + 1) * split_nchunk(kmax) >= (int64_t(1) << 31))
         return fail(LADDER_EUNSUPPORTED, "split precision: v^2 * max(v^2, o^2, n) too large for the slicer grid");
+    // the GEMM's 32-bit per-lane offsets span two panels of the longest k
+    if (2 * (split_kpad(kmax) / 16) * SPLIT_PANEL * 16 * 2 + 4096 >= (int64_t(1) << 32))
+        return fail(LADDER_EUNSUPPORTED, "split precision: max(v^2, o^2, n) too large for the panel offsets");
     return LADDER_OK;
 }
 

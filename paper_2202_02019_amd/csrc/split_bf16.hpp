@@ -76,13 +76,21 @@ __device__ inline void write_slices(double x, int e, unsigned short* out, int64_
 }
 
 // ---------------------------------------------------------------- slicers
-// Slice layout ("k-blocked"): slice p of an R-row operand is R x Kp BF16 values
-// (Kp = split_kpad(K), zero beyond K) stored as Kp/16 blocks of [R rows][16 k]:
-// element (r, k) of slice p sits at  p*R*Kp + (k/16)*R*16 + r*16 + k%16.
-// One GEMM K-step (16 k) of a 128-row tile is then one contiguous 4 KB run, so
-// every cache line the tile loads is used whole in the same step.
+// Slice layout ("panel-major, k-blocked"): the rows of an operand are grouped in
+// panels of 128; slice p stores, panel after panel, the Kp/16 k-blocks of the
+// panel as [128 rows][16 k] BF16 (Kp = split_kpad(K), zero beyond K):
+//   element (r, k) of slice p at  p*slice_stride + ((r/128)*nkb + k/16)*2048 + (r%128)*16 + k%16,
+// nkb = Kp/16, slice_stride = panels*128*Kp (rows padded to whole panels).  One
+// GEMM K-step (16 k) of a 128-row tile is then a contiguous 4 KB run (two runs
+// when the tile straddles a panel boundary), and a tile's walk over K stays
+// inside one or two contiguous panels, which keeps address translation local.
 // Exponents: [nchunk][R] (chunk stride exp_ld).
-__host__ __device__ inline int64_t split_index(int64_t r, int64_t k, int64_t R) { return (k >> 4) * R * 16 + r * 16 + (k & 15); }
+constexpr int SPLIT_PANEL = 128;
+__host__ __device__ inline int64_t split_panels(int64_t R) { return (R + SPLIT_PANEL - 1) / SPLIT_PANEL; }
+__host__ __device__ inline int64_t split_slice_stride(int64_t R, int64_t K) { return split_panels(R) * SPLIT_PANEL * split_kpad(K); }
+__host__ __device__ inline int64_t split_index(int64_t r, int64_t k, int64_t nkb) {
+    return ((r >> 7) * nkb + (k >> 4)) * (SPLIT_PANEL * 16) + (r & 127) * 16 + (k & 15);
+}
 
 // K-contiguous source: element (r, k) at src[r*ld + k], r < R, k < K.
 // One workgroup per 16 rows and one chunk: thread (rr, kk) = (t/16, t%16) holds
@@ -112,11 +120,11 @@ __global__ __launch_bounds__(256) void slice_rows_kernel(const double* __restric
     if (r >= R) return;
     const int e = chunk_exponent(mx);
     if (kk == 0) exps[ch * exp_ld + r] = e;
-    const int64_t slice_stride = R * Kp;
+    const int64_t slice_stride = split_slice_stride(R, K), nkb = Kp / 16;
 #pragma unroll
     for (int kb = 0; kb < NKB; ++kb) {
         const int64_t k = ch * SPLIT_KC + 16 * kb + kk;
-        if (k < Kp) write_slices<S>(x[kb], e, slices + split_index(r, k, R), slice_stride);
+        if (k < Kp) write_slices<S>(x[kb], e, slices + split_index(r, k, nkb), slice_stride);
     }
 }
 
@@ -154,7 +162,7 @@ __global__ __launch_bounds__(256) void slice_cols_kernel(const double* __restric
     if (part == 0 && r0 + rr < R) exps[ch * exp_ld + r0 + rr] = ex[rr];
     // writes: thread (wr, kk) = (t/16, t%16) covers rows wr and wr + 16 of every
     // k-block, so a block's 32 rows x 16 k go out as one 1 KB run per slice
-    const int64_t slice_stride = R * Kp;
+    const int64_t slice_stride = split_slice_stride(R, K), nkb = Kp / 16;
     const int wr = tid >> 4, kk = tid & 15;
     for (int kb = 0; kb < SPLIT_KC / 16; ++kb) {
         const int64_t k = k0 + 16 * kb + kk;
@@ -163,16 +171,17 @@ __global__ __launch_bounds__(256) void slice_cols_kernel(const double* __restric
         for (int h = 0; h < 2; ++h) {
             const int row = wr + 16 * h;
             const int64_t r = r0 + row;
-            if (r < R) write_slices<S>(tile[16 * kb + kk][row], ex[row], slices + split_index(r, k, R), slice_stride);
+            if (r < R) write_slices<S>(tile[16 * kb + kk][row], ex[row], slices + split_index(r, k, nkb), slice_stride);
         }
     }
 }
 
 // ---------------------------------------------------------------- split GEMM
 struct SplitOperand {
-    const unsigned short* s;  // slice 0, k-block 0, row 0 of this operand view
-    int64_t slice_stride;     // elements between slices (R * Kp of the sliced buffer)
-    int64_t kstride;          // elements between 16-k blocks (R * 16 of the sliced buffer); rows are 16 apart
+    const unsigned short* s;  // slice 0 of the whole sliced buffer (panel-major layout)
+    int64_t slice_stride;     // elements between slices (split_slice_stride of the buffer)
+    int64_t row_off;          // first buffer row of this view
+    int64_t nkb;              // k-blocks per panel, Kp / 16
     const int* e;             // exponent of (row 0, chunk 0) of this view
     int64_t e_ld;             // chunk stride of the exponent array
 };
@@ -280,10 +289,15 @@ __global__ __launch_bounds__(SPLIT_THREADS) void gemm_split_kernel(SplitShape sh
     const int slot = 64 * dq + lane;
     const int drow = slot >> 1;
     const int dhalf = (slot & 1) ^ (((drow >> 2) ^ (drow >> 3)) & 1);
-    // rows past the edge load a valid row; their results are never stored
-    const unsigned dvoff = (unsigned)(((drow < last ? drow : last) * 16 + 8 * dhalf) * 2);
-    const unsigned short* dbase = (const unsigned short*)uniform_ptr(op.s + row0 * 16);
-    const int64_t dkstride = op.kstride;
+    // rows past the edge load a valid row; their results are never stored.  The
+    // tile's rows lie in panel pbase or pbase + 1 of the buffer.
+    const int64_t abs0 = op.row_off + row0;
+    const int64_t pbase = abs0 / SPLIT_PANEL;
+    const int64_t arow = abs0 + (drow < last ? drow : last);
+    const unsigned dvoff = (unsigned)((((arow / SPLIT_PANEL) - pbase) * op.nkb * (SPLIT_PANEL * 16) +
+                                       (arow % SPLIT_PANEL) * 16 + 8 * dhalf) * 2);
+    const unsigned short* dbase = (const unsigned short*)uniform_ptr(op.s + pbase * op.nkb * (SPLIT_PANEL * 16));
+    constexpr int64_t dkstride = SPLIT_PANEL * 16;
     const int64_t dstride = op.slice_stride;
     const int64_t e_ld = op.e_ld;
     const int erow = 64 * dq + lane;
