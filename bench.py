@@ -76,6 +76,8 @@ def main():
     ap.add_argument("--cpu-rows", type=int, default=1, help="a (and p) rows the CPU baseline computes; 0 = skip")
     ap.add_argument("--no-compare", action="store_true",
                     help="skip the untimed FP64 leg that the split path is compared with")
+    ap.add_argument("--dense", action="store_true",
+                    help="dense contraction instead of the +/- packed one (LADDER_FLAG_DENSE)")
     ap.add_argument("--next-rows", action="store_true",
                     help="also time the transposed ladder (dE/dtau), the metric contraction V and the MO "
                          "back-transformation once on the same inputs, with sampled checks")
@@ -127,7 +129,8 @@ def main():
     X = torch.empty_like(L)
     E = torch.empty((), dtype=torch.float64, device=dev)
     prec = P.FP64 if args.precision == "fp64" else P.SPLIT_BF16
-    opts = P.Options(precision=prec, n_slices=args.slices, n_abatch=args.n_abatch)
+    opts = P.Options(precision=prec, n_slices=args.slices, n_abatch=args.n_abatch,
+                     flags=P.FLAG_DENSE if args.dense else 0)
     wsb = P.workspace_size(o, v, n, opts)
     if args.next_rows:
         wsb = max(wsb, P.tau_gradient_workspace_size(o, v, n, opts), P.back_transform_workspace_size(v, n))
@@ -164,22 +167,26 @@ def main():
     value = F / (ms * 1e-3) / 1e12
 
     dom_name, dom = max(stages.items(), key=lambda kv: kv[1]["total_ms"])
-    dtype_peak = "fp64" if args.precision == "fp64" else "bf16"
-    achieved = dom["flops"] / dom["launches"] / (dom["avg_ms"] * 1e-3) / 1e12
-    default_shape = args.slices in (0, 5) and args.n_abatch == (8 if args.precision == "split" else 16)
+    # FP64-equivalent rate of the dominant stage: 2 M N K flops per launch over its mean launch time
+    fp64_equiv = dom["flops"] / dom["launches"] / (dom["avg_ms"] * 1e-3) / 1e12
+    default_shape = (args.slices in (0, 5) and not args.dense
+                     and args.n_abatch == (8 if args.precision == "split" else 16))
     traffic = measured_traffic(name, args.precision, dom_name) if default_shape else None
-    roofline = {"bound": "mfma", "kernel": dom_name, "achieved": achieved, "peak": PEAK[dtype_peak],
-                "unit": "TFLOP/s", "frac": achieved / PEAK[dtype_peak], "traffic": traffic,
-                "traffic_unit": "bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-kernel scaled)",
-                "algorithmic_bytes": dom["bytes"] / dom["launches"],
-                "avg_launch_ms": dom["avg_ms"], "launches_per_step": dom["launches"] / steps}
     if args.precision == "split":
+        # the split method's unit of work: S(S+1)/2 BF16 slice products per FP64-equivalent MAC
         S = args.slices or 5
         prods = S * (S + 1) // 2
-        # BF16 MFMA work actually issued: every slice pair (p, q) with p + q < S
-        roofline["slice_products"] = prods
-        roofline["executed_bf16_tflops"] = achieved * prods
-        roofline["frac_executed"] = achieved * prods / PEAK["bf16"]
+        achieved, peak = fp64_equiv * prods, PEAK["bf16"]
+    else:
+        prods, achieved, peak = 1, fp64_equiv, PEAK["fp64"]
+    roofline = {"bound": "mfma", "kernel": dom_name, "achieved": achieved, "peak": peak,
+                "unit": "TFLOP/s", "frac": achieved / peak, "traffic": traffic,
+                "traffic_unit": "bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-kernel scaled)",
+                "algorithmic_bytes": dom["bytes"] / dom["launches"],
+                "avg_launch_ms": dom["avg_ms"], "launches_per_step": dom["launches"] / steps,
+                "slice_products": prods if args.precision == "split" else None,
+                "fp64_equivalent_tflops": fp64_equiv,
+                "fp64_equivalent_frac_of_fp64_peak": fp64_equiv / PEAK["fp64"]}
     stage_summary = {k: {"ms_per_step": s["total_ms"] / steps, "launches_per_step": s["launches"] / steps,
                          "tflops": (s["flops"] / (s["total_ms"] * 1e-3) / 1e12) if s["total_ms"] > 0 else None}
                      for k, s in stages.items()}
@@ -188,7 +195,8 @@ def main():
     compare = None
     if args.precision == "split" and not args.no_compare:
         # the same step on the FP64 MFMA path, untimed for `value`
-        o64 = P.Options(precision=P.FP64, n_abatch=16 if name == "retinal" else 0)
+        o64 = P.Options(precision=P.FP64, n_abatch=16 if name == "retinal" else 0,
+                        flags=P.FLAG_DENSE if args.dense else 0)
         ws64 = torch.empty(P.workspace_size(o, v, n, o64), dtype=torch.uint8, device=dev) if \
             P.workspace_size(o, v, n, o64) > ws.numel() else ws
         R64 = torch.empty_like(R)
@@ -291,7 +299,8 @@ def main():
         "vs_baseline": None, "dtype": "f64" if args.precision == "fp64" else "bf16-split/f64",
         "data": "synthetic",
         "config": {"workload": name, "o": o, "v": v, "n_chol": n, "seed": seed, "precision": args.precision,
-                   "n_slices": args.slices, "n_abatch": args.n_abatch, "nominal_flops": F},
+                   "n_slices": args.slices, "n_abatch": args.n_abatch, "nominal_flops": F,
+                   "path": "dense" if args.dense else "+/- packed"},
         "energy": float(E.cpu()),
         "roofline": roofline, "stages": stage_summary, "cpu_baseline": cpu,
         "frac_fp64_peak": value / PEAK["fp64"],
@@ -318,7 +327,8 @@ def run_batched(args):
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
     prec = P.FP64 if args.precision == "fp64" else P.SPLIT_BF16
-    opts = P.Options(precision=prec, n_slices=args.slices, n_abatch=args.n_abatch)
+    opts = P.Options(precision=prec, n_slices=args.slices, n_abatch=args.n_abatch,
+                     flags=P.FLAG_DENSE if args.dense else 0)
     insts = []
     t0 = time.time()
     for m, (o, v, n) in enumerate(sizes):
