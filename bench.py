@@ -34,6 +34,27 @@ WORKLOADS = {
 PEAK = {"fp64": 78.6, "bf16": 2516.6}  # dense MFMA TFLOP/s, MI355X
 
 
+TUNED_CACHE = os.path.join(ROOT, "paper_2202_02019_amd", "tuned_mi355x.jsonl")
+
+
+def tuned_batch(path, o, v, n, precision, slices, flags):
+    """The batch size a ladder_autotune cache file holds for this shape and options (last line
+    wins, as in ladder_autotune_load), or None."""
+    if not path or not os.path.exists(path):
+        return None
+    found = None
+    with open(path) as fh:
+        for line in fh:
+            try:
+                d = json.loads(line)
+            except ValueError:
+                continue
+            if (d.get("o"), d.get("v"), d.get("n"), d.get("precision"), d.get("n_slices"), d.get("flags")) == \
+                    (o, v, n, precision, slices if precision == 1 else 0, flags):
+                found = d.get("n_abatch")
+    return found
+
+
 def gemm_source_hash():
     """First 16 hex digits of the SHA-256 of the GEMM kernel sources (the code the
     stored HBM-traffic counters were taken on)."""
@@ -76,6 +97,13 @@ def main():
     ap.add_argument("--cpu-rows", type=int, default=1, help="a (and p) rows the CPU baseline computes; 0 = skip")
     ap.add_argument("--no-compare", action="store_true",
                     help="skip the untimed FP64 leg that the split path is compared with")
+    ap.add_argument("--autotune", default=None, metavar="CACHE",
+                    help="choose the virtual-batch size with ladder_autotune before the timed region (within the "
+                         "free HBM) and append the choice to CACHE (JSON lines); with --n-abatch 0 the timed "
+                         "step then uses it")
+    ap.add_argument("--tuned", default=TUNED_CACHE, metavar="CACHE",
+                    help="load tuned batch sizes from CACHE (ladder_autotune_load) before running; "
+                         "default: the committed MI355X cache; 'none' to skip")
     ap.add_argument("--dense", action="store_true",
                     help="dense contraction instead of the +/- packed one (LADDER_FLAG_DENSE)")
     ap.add_argument("--next-rows", action="store_true",
@@ -103,8 +131,17 @@ def main():
     if args.shape:
         o, v, n = (int(x) for x in args.shape.split(","))
         name = "probe"
-    if args.n_abatch == 0 and name == "retinal":
+    prec_code = 0 if args.precision == "fp64" else 1
+    flags = 2 if args.dense else 0
+    nA_source = "explicit" if args.n_abatch else "library default"
+    tuned = None
+    if args.n_abatch == 0 and not args.autotune and args.tuned not in (None, "none"):
+        tuned = tuned_batch(args.tuned, o, v, n, prec_code, args.slices or 5, flags)
+        if tuned:
+            nA_source = "autotune cache " + os.path.relpath(args.tuned, ROOT)
+    if args.n_abatch == 0 and tuned is None and not args.autotune and name == "retinal":
         args.n_abatch = 8 if args.precision == "split" else 16  # a few large virtual batches fit in 288 GB
+        nA_source = "fixed fallback"
     big = nominal_flops(o, v, n) > 1e14
     huge = nominal_flops(o, v, n) > 1e15  # a single step takes minutes: no warm-up by default
     steps = args.steps if args.steps is not None else (1 if big else 10)
@@ -131,6 +168,21 @@ def main():
     prec = P.FP64 if args.precision == "fp64" else P.SPLIT_BF16
     opts = P.Options(precision=prec, n_slices=args.slices, n_abatch=args.n_abatch,
                      flags=P.FLAG_DENSE if args.dense else 0)
+    tune_s = None
+    if tuned:
+        P.autotune_load(args.tuned)
+    if args.autotune:
+        # the tuner may try any batch size whose workspace fits the free HBM (less a margin)
+        free, _ = torch.cuda.mem_get_info()
+        wst = torch.empty(max(free - (6 << 30), 1 << 20), dtype=torch.uint8, device=dev)
+        c0 = time.time()
+        tuned = P.autotune(L, tau, tbar, o=o, v=v, n=n, ws=wst, R=R, X=X, opts=opts, cache_path=args.autotune)
+        torch.cuda.synchronize()
+        tune_s = time.time() - c0
+        nA_source = "ladder_autotune (%.1f s)" % tune_s
+        del wst
+        torch.cuda.empty_cache()
+        print("bench: autotune chose n_abatch = %d in %.1f s" % (tuned, tune_s), file=sys.stderr, flush=True)
     wsb = P.workspace_size(o, v, n, opts)
     if args.next_rows:
         wsb = max(wsb, P.tau_gradient_workspace_size(o, v, n, opts), P.back_transform_workspace_size(v, n))
@@ -169,8 +221,8 @@ def main():
     dom_name, dom = max(stages.items(), key=lambda kv: kv[1]["total_ms"])
     # FP64-equivalent rate of the dominant stage: 2 M N K flops per launch over its mean launch time
     fp64_equiv = dom["flops"] / dom["launches"] / (dom["avg_ms"] * 1e-3) / 1e12
-    default_shape = (args.slices in (0, 5) and not args.dense
-                     and args.n_abatch == (8 if args.precision == "split" else 16))
+    nA_eff = args.n_abatch or tuned
+    default_shape = (args.slices in (0, 5) and not args.dense and nA_eff == (8 if args.precision == "split" else 16))
     traffic = measured_traffic(name, args.precision, dom_name) if default_shape else None
     if args.precision == "split":
         # the split method's unit of work: S(S+1)/2 BF16 slice products per FP64-equivalent MAC
@@ -299,7 +351,8 @@ def main():
         "vs_baseline": None, "dtype": "f64" if args.precision == "fp64" else "bf16-split/f64",
         "data": "synthetic",
         "config": {"workload": name, "o": o, "v": v, "n_chol": n, "seed": seed, "precision": args.precision,
-                   "n_slices": args.slices, "n_abatch": args.n_abatch, "nominal_flops": F,
+                   "n_slices": args.slices, "n_abatch": nA_eff or 0, "n_abatch_source": nA_source,
+                   "nominal_flops": F,
                    "path": "dense" if args.dense else "+/- packed"},
         "energy": float(E.cpu()),
         "roofline": roofline, "stages": stage_summary, "cpu_baseline": cpu,
@@ -342,6 +395,22 @@ def run_batched(args):
         insts.append(dict(o=o, v=v, n=n, L=L, tau=tau, tbar=tbar, R=torch.empty_like(tau),
                           E=torch.empty((), dtype=torch.float64, device=dev), X=torch.empty_like(L)))
     what = P.DO_FORWARD | P.DO_ADJOINT
+    tuned_src = None
+    if args.n_abatch == 0 and args.autotune:
+        # tune every instance shape once (each on its own data), appending to the cache
+        c0 = time.time()
+        free, _ = torch.cuda.mem_get_info()
+        wst = torch.empty(min(max(free // 2, 1 << 20), 64 << 30), dtype=torch.uint8, device=dev)
+        for d in insts:
+            P.autotune(d["L"], d["tau"], d["tbar"], o=d["o"], v=d["v"], n=d["n"], ws=wst, R=d["R"], X=d["X"],
+                       opts=opts, cache_path=args.autotune)
+        torch.cuda.synchronize()
+        del wst
+        torch.cuda.empty_cache()
+        tuned_src = "ladder_autotune (%.1f s)" % (time.time() - c0)
+    elif args.n_abatch == 0 and args.tuned not in (None, "none") and os.path.exists(args.tuned):
+        if P.autotune_load(args.tuned) > 0:
+            tuned_src = "autotune cache " + os.path.relpath(args.tuned, ROOT)
     ws = torch.empty(P.batched_workspace_size(insts, what, opts), dtype=torch.uint8, device=dev)
     F = sum(nominal_flops(o, v, n) for o, v, n in sizes)
     torch.cuda.synchronize()
@@ -376,7 +445,9 @@ def run_batched(args):
         "ms_per_step": ms, "s_per_iter": ms / 1e3, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
         "dtype": "f64" if args.precision == "fp64" else "bf16-split/f64", "data": "synthetic",
         "config": {"workload": "batched", "instances": 64, "sizes_seed": 4, "data_seeds": "1000+m",
-                   "precision": args.precision, "n_abatch": args.n_abatch, "nominal_flops": F},
+                   "precision": args.precision, "n_abatch": args.n_abatch,
+                   "n_abatch_source": tuned_src or ("explicit" if args.n_abatch else "library default"),
+                   "nominal_flops": F},
         "sequential_ms": ms_seq, "sequential_tflops": F / (ms_seq * 1e-3) / 1e12, "graph_speedup": ms_seq / ms,
         "roofline": None, "cpu_baseline": None,
     }

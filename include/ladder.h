@@ -123,6 +123,31 @@ int ladder_adjoint(int64_t o, int64_t v, int64_t n, const double* L, const doubl
                    size_t ws_bytes, const ladder_options* opts, void* stream);
 
 /*
+ * Autotuner for the virtual-batch size (the batch of Sec. II B, whose size the
+ * paper leaves open).  For this shape and these options (n_abatch must be 0) it
+ * times, on the caller's data and stream, each candidate batch size whose
+ * workspace fits ws_bytes: the default one, powers of two and the cap (v/4 on the
+ * +/- path, v/2 otherwise).  Each candidate runs the per-call work alone and two
+ * sample batches (the first and the middle one) of forward + adjoint; the whole
+ * call is estimated from the modelled GEMM work of every batch.  The fastest is
+ * kept in a process-wide table, returned in *n_abatch (if not NULL) and, when
+ * cache_path is not NULL, appended to that file as one JSON line.  R and X are
+ * overwritten with partial results (tbar is used as the adjoint weight).
+ * From then on, calls with n_abatch = 0 for the same (o, v, n, precision,
+ * n_slices, flags) use the tuned size whenever its workspace fits the one they are
+ * given, and ladder_workspace_size / ladder_batched_workspace_size report the
+ * larger of the tuned and default workspaces.  Synchronises the stream.
+ * ladder_autotune_load reads such a file (lines of other devices are skipped,
+ * later lines win; *n_loaded = lines taken, may be NULL); ladder_autotune_reset
+ * forgets every tuned entry.
+ */
+int ladder_autotune(int64_t o, int64_t v, int64_t n, const double* L, const double* tau, const double* tbar,
+                    double* R, double* X, void* ws, size_t ws_bytes, const ladder_options* opts,
+                    const char* cache_path, int64_t* n_abatch, void* stream);
+int ladder_autotune_load(const char* cache_path, int* n_loaded);
+void ladder_autotune_reset(void);
+
+/*
  * Transposed ladder: the gradient of the ladder energy with respect to the
  * amplitudes, i.e. the A2-term contribution to the multiplier equations
  * (tbar A = -eta, Sec. II A):

@@ -28,7 +28,9 @@
 #include <string.h>
 
 #include <algorithm>
+#include <map>
 #include <mutex>
+#include <tuple>
 #include <string>
 #include <vector>
 
@@ -186,6 +188,7 @@ SlicedBuf take_sliced(Arena& a, int S, int64_t R, int64_t K) {
 struct Plan {
     int S = 0;  // 0: FP64
     int64_t nA = 0, nbatch = 0;
+    int64_t b_lo = 0, b_hi = 0;          // batches this call runs (all of them except when timing samples)
     size_t tile_off = 0;                 // FP64 g_A or D_A, nA*v^3 doubles
     SlicedBuf tile_sl;                   // split: slices of the tile (rows nA*v, K = v^2)
     size_t part_off = 0, part_per_batch = 0;
@@ -226,6 +229,8 @@ Plan make_plan(int64_t o, int64_t v, int64_t n, const ladder_options& op, const 
     if (nA > v) nA = v;
     p.nA = nA;
     p.nbatch = (v + nA - 1) / nA;
+    p.b_lo = 0;
+    p.b_hi = p.nbatch;
 
     Arena a;
     p.tile_off = a.take((size_t)(nA * s.vvv) * 8);
@@ -304,6 +309,75 @@ Plan make_plan(int64_t o, int64_t v, int64_t n, const ladder_options& op, const 
     (void)common;
     p.total = std::max(p.fwd_total, p.adj_total);
     return p;
+}
+
+// ---------------------------------------------------------------- autotuned batch sizes
+// ladder_autotune measures candidate virtual-batch sizes on the caller's data and
+// keeps the fastest per shape and options; later calls with n_abatch = 0 use it
+// whenever its workspace fits the one they are given.
+struct TuneKey {
+    int64_t o, v, n;
+    int32_t precision, slices;
+    uint32_t flags;
+    bool operator<(const TuneKey& b) const {
+        return std::tie(o, v, n, precision, slices, flags) < std::tie(b.o, b.v, b.n, b.precision, b.slices, b.flags);
+    }
+};
+std::mutex g_tune_mu;
+std::map<TuneKey, int64_t> g_tuned;
+int64_t g_tune_gen = 0;  // bumped on every change: part of the batched graph cache key
+
+TuneKey tune_key(int64_t o, int64_t v, int64_t n, const ladder_options& op) {
+    return TuneKey{o, v, n, op.precision, op.precision == LADDER_SPLIT_BF16 ? op.n_slices : 0, op.flags};
+}
+
+bool tuned_batch(const TuneKey& k, int64_t& nA) {
+    std::lock_guard<std::mutex> g(g_tune_mu);
+    auto it = g_tuned.find(k);
+    if (it == g_tuned.end()) return false;
+    nA = it->second;
+    return true;
+}
+
+// The plan of a call.  An explicit n_abatch wins; otherwise the tuned batch size of
+// this shape and options when there is one and its workspace fits ws_bytes, else the
+// default.  For a size query (sizing = true) the larger of the two plans is returned,
+// so that a workspace of that size runs the tuned plan.
+Plan choose_plan(int64_t o, int64_t v, int64_t n, const ladder_options& op, const Sizes& s, size_t ws_bytes,
+                 bool sizing) {
+    Plan def = make_plan(o, v, n, op, s);
+    int64_t t = 0;
+    if (op.n_abatch != 0 || !tuned_batch(tune_key(o, v, n, op), t)) return def;
+    ladder_options o2 = op;
+    o2.n_abatch = t;
+    Plan tp = make_plan(o, v, n, o2, s);
+    if (sizing) return tp.total >= def.total ? tp : def;
+    return tp.total <= ws_bytes ? tp : def;
+}
+
+// Executed GEMM flops of batch bi of a plan (both directions), the work model that
+// turns the timed sample batches into an estimate for the whole call.
+double batch_work(const Plan& p, int64_t o, int64_t v, int64_t n, const Sizes& s, bool general, int64_t bi) {
+    const int64_t a0 = bi * p.nA, nA = std::min(p.nA, v - a0);
+    if (p.pm) {
+        const double NPb = (double)pm_gp_off(nA, v, a0), NMb = (double)pm_gm_off(nA, v, a0);
+        return gemm_flops(nA * v, (v - a0) * v, n) + 2.0 * ((double)p.P2o * NPb * p.P2v + (double)p.Q2o * NMb * p.Q2v) +
+               2.0 * (double)(nA * v) * ((double)p.P2v * p.P2o + (double)p.Q2v * p.Q2o) + gemm_flops(nA * v, n, s.vv);
+    }
+    (void)o;
+    return gemm_flops(nA * v, s.vv, n) + gemm_flops(s.oo, nA * v, s.vv) + (general ? 2.0 : 1.0) * gemm_flops(nA * v, s.vv, s.oo) +
+           gemm_flops(nA * v, n, s.vv);
+}
+
+// "gfx950:256" (architecture and compute units), the device field of the cache file.
+std::string device_tag() {
+    int dev = 0;
+    hipDeviceProp_t prop;
+    if (hipGetDevice(&dev) != hipSuccess || hipGetDeviceProperties(&prop, dev) != hipSuccess) return "unknown";
+    std::string arch(prop.gcnArchName);
+    const size_t c = arch.find(':');
+    if (c != std::string::npos) arch.resize(c);
+    return arch + ":" + std::to_string(prop.multiProcessorCount);
 }
 
 // ---------------------------------------------------------------- launches
@@ -529,7 +603,7 @@ int forward_pm(int64_t o, int64_t v, int64_t n, const double* L, const double* t
         if ((rc = slice_into(S, false, tp, p.P2v, w, p.tp_cd, st))) return rc;
         if (minus && (rc = slice_into(S, false, tm, p.Q2v, w, p.tm_cd, st))) return rc;
     }
-    for (int64_t bi = 0; bi < p.nbatch; ++bi) {
+    for (int64_t bi = p.b_lo; bi < p.b_hi; ++bi) {
         const int64_t a0 = bi * p.nA;
         const int64_t nA = std::min(p.nA, v - a0);
         const int64_t NPb = pm_gp_off(nA, v, a0), NMb = pm_gm_off(nA, v, a0);
@@ -624,7 +698,7 @@ int adjoint_pm(int64_t o, int64_t v, int64_t n, const double* L, const double* t
         }
         if ((rc = slice_into(S, true, L, n, w, p.L_bd, st))) return rc;
     }
-    for (int64_t bi = 0; bi < p.nbatch; ++bi) {
+    for (int64_t bi = p.b_lo; bi < p.b_hi; ++bi) {
         const int64_t a0 = bi * p.nA;
         const int64_t nA = std::min(p.nA, v - a0);
         for (int sign = 0; sign < (minus ? 2 : 1); ++sign) {
@@ -713,6 +787,8 @@ int batch_plan(int count, const ladder_instance* inst, uint32_t what, const ladd
         if ((what & LADDER_DO_ADJOINT) && (!x.X || !x.tbar)) return fail(LADDER_EINVAL, "instance %d: X and tbar are needed", i);
         if (x.E && !x.tbar) return fail(LADDER_EINVAL, "instance %d: E requested but tbar is NULL", i);
         ladder_options oi = bp.op;
+        int64_t tuned = 0;
+        if (oi.n_abatch == 0 && tuned_batch(tune_key(x.o, x.v, x.n, oi), tuned)) oi.n_abatch = tuned;
         if (oi.n_abatch == 0) {
             int64_t per_a = s.vvv * 8;
             if (oi.precision == LADDER_SPLIT_BF16) per_a += (int64_t)(slice_bytes(oi.n_slices, x.v, s.vv) + exp_bytes(x.v, s.vv));
@@ -787,7 +863,7 @@ int forward_impl(int64_t o, int64_t v, int64_t n, const double* L, const double*
         if ((rc = slice_into(S, false, L, n, w, p.L_J, st))) return rc;
         if ((rc = slice_into(S, false, tau, s.vv, w, p.tau_cd, st))) return rc;
     }
-    for (int64_t bi = 0; bi < p.nbatch; ++bi) {
+    for (int64_t bi = p.b_lo; bi < p.b_hi; ++bi) {
         const int64_t a0 = bi * p.nA;
         const int64_t nA = std::min(p.nA, v - a0);
         {
@@ -895,7 +971,7 @@ int ladder_workspace_size(int64_t o, int64_t v, int64_t n, const ladder_options*
     ladder_options op;
     int rc;
     if ((rc = check_dims(o, v, n, s)) || (rc = get_opts(opts, op)) || (rc = check_split_dims(s, n, op))) return rc;
-    *bytes = make_plan(o, v, n, op, s).total;
+    *bytes = choose_plan(o, v, n, op, s, SIZE_MAX, true).total;
     return LADDER_OK;
 }
 
@@ -907,7 +983,7 @@ int ladder_forward(int64_t o, int64_t v, int64_t n, const double* L, const doubl
     ladder_options op;
     int rc;
     if ((rc = check_dims(o, v, n, s)) || (rc = get_opts(opts, op)) || (rc = check_split_dims(s, n, op))) return rc;
-    const Plan p = make_plan(o, v, n, op, s);
+    const Plan p = choose_plan(o, v, n, op, s, ws_bytes, false);
     if ((rc = check_forward_args(o, v, n, L, tau, tbar, R, E, ws, ws_bytes, p.fwd_total, "R", s))) return rc;
     return forward_impl(o, v, n, L, tau, tbar, beta, R, E, (char*)ws, p, s, (hipStream_t)stream);
 }
@@ -919,7 +995,7 @@ int ladder_tau_gradient_workspace_size(int64_t o, int64_t v, int64_t n, const la
     ladder_options op;
     int rc;
     if ((rc = check_dims(o, v, n, s)) || (rc = get_opts(opts, op)) || (rc = check_split_dims(s, n, op))) return rc;
-    *bytes = align_up(make_plan(o, v, n, op, s).fwd_total) + align_up((size_t)s.vvn * 8);
+    *bytes = align_up(choose_plan(o, v, n, op, s, SIZE_MAX, true).fwd_total) + align_up((size_t)s.vvn * 8);
     return LADDER_OK;
 }
 
@@ -930,7 +1006,9 @@ int ladder_tau_gradient(int64_t o, int64_t v, int64_t n, const double* L, const 
     ladder_options op;
     int rc;
     if ((rc = check_dims(o, v, n, s)) || (rc = get_opts(opts, op)) || (rc = check_split_dims(s, n, op))) return rc;
-    const Plan p = make_plan(o, v, n, op, s);
+    // the transposed L sits after the forward region: pick the plan whose region leaves room for it
+    Plan p = choose_plan(o, v, n, op, s, ws_bytes, false);
+    if (align_up(p.fwd_total) + align_up((size_t)s.vvn * 8) > ws_bytes) p = make_plan(o, v, n, op, s);
     const size_t lt_off = align_up(p.fwd_total);
     const size_t need = lt_off + align_up((size_t)s.vvn * 8);
     if ((rc = check_forward_args(o, v, n, L, w, nullptr, G, nullptr, ws, ws_bytes, need, "G", s))) return rc;
@@ -945,25 +1023,15 @@ int ladder_tau_gradient(int64_t o, int64_t v, int64_t n, const double* L, const 
     return forward_impl(o, v, n, LT, w, nullptr, beta, G, nullptr, (char*)ws, p, s, st);
 }
 
-int ladder_adjoint(int64_t o, int64_t v, int64_t n, const double* L, const double* tau, const double* wt,
-                   double alpha, double beta, double* X, void* ws, size_t ws_bytes, const ladder_options* opts,
-                   void* stream) {
-    g_last_error.clear();
-    Sizes s;
-    ladder_options op;
-    int rc;
-    if ((rc = check_dims(o, v, n, s)) || (rc = get_opts(opts, op)) || (rc = check_split_dims(s, n, op))) return rc;
-    if (!L || !tau || !wt || !X || !ws) return fail(LADDER_EINVAL, "L, tau, w, X and ws must be non-NULL");
-    if (!aligned8(L) || !aligned8(tau) || !aligned8(wt) || !aligned8(X) || ((uintptr_t)ws % ALIGN))
-        return fail(LADDER_EINVAL, "misaligned pointer (arrays need 8-byte, ws 256-byte alignment)");
-    const Plan p = make_plan(o, v, n, op, s);
-    if (ws_bytes < p.adj_total) return fail(LADDER_EWORKSPACE, "workspace of %zu bytes, %zu needed", ws_bytes, p.adj_total);
-    const int64_t tb = s.ovv_elems * 8, lb = s.vvn * 8;
-    if (overlap(X, lb, L, lb) || overlap(X, lb, tau, tb) || overlap(X, lb, wt, tb) || overlap(X, lb, ws, (int64_t)ws_bytes))
-        return fail(LADDER_EINVAL, "X overlaps an input or the workspace");
+}  // extern "C"
 
-    hipStream_t st = (hipStream_t)stream;
-    char* w = (char*)ws;
+namespace {
+
+// Adjoint on validated arguments (ladder_adjoint, ladder_autotune).
+int adjoint_impl(int64_t o, int64_t v, int64_t n, const double* L, const double* tau, const double* wt, double alpha,
+                 double beta, double* X, char* w, const Plan& p, const Sizes& s, const ladder_options& op,
+                 hipStream_t st) {
+    int rc;
     if (p.pm) return adjoint_pm(o, v, n, L, tau, wt, alpha, beta, X, w, p, s, st);
     double* D = (double*)(w + p.tile_off);
     const bool general = (op.flags & LADDER_FLAG_GENERAL) != 0;
@@ -985,7 +1053,7 @@ int ladder_adjoint(int64_t o, int64_t v, int64_t n, const double* L, const doubl
             if ((rc = slice_into(S, true, pt, s.vv, w, p.ptau_ij, st))) return rc;
         }
     }
-    for (int64_t bi = 0; bi < p.nbatch; ++bi) {
+    for (int64_t bi = p.b_lo; bi < p.b_hi; ++bi) {
         const int64_t a0 = bi * p.nA;
         const int64_t nA = std::min(p.nA, v - a0);
         for (int term = 0; term < (general ? 2 : 1); ++term) {
@@ -1026,6 +1094,169 @@ int ladder_adjoint(int64_t o, int64_t v, int64_t n, const double* L, const doubl
         }
     }
     return LADDER_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int ladder_adjoint(int64_t o, int64_t v, int64_t n, const double* L, const double* tau, const double* wt,
+                   double alpha, double beta, double* X, void* ws, size_t ws_bytes, const ladder_options* opts,
+                   void* stream) {
+    g_last_error.clear();
+    Sizes s;
+    ladder_options op;
+    int rc;
+    if ((rc = check_dims(o, v, n, s)) || (rc = get_opts(opts, op)) || (rc = check_split_dims(s, n, op))) return rc;
+    if (!L || !tau || !wt || !X || !ws) return fail(LADDER_EINVAL, "L, tau, w, X and ws must be non-NULL");
+    if (!aligned8(L) || !aligned8(tau) || !aligned8(wt) || !aligned8(X) || ((uintptr_t)ws % ALIGN))
+        return fail(LADDER_EINVAL, "misaligned pointer (arrays need 8-byte, ws 256-byte alignment)");
+    const Plan p = choose_plan(o, v, n, op, s, ws_bytes, false);
+    if (ws_bytes < p.adj_total) return fail(LADDER_EWORKSPACE, "workspace of %zu bytes, %zu needed", ws_bytes, p.adj_total);
+    const int64_t tb = s.ovv_elems * 8, lb = s.vvn * 8;
+    if (overlap(X, lb, L, lb) || overlap(X, lb, tau, tb) || overlap(X, lb, wt, tb) || overlap(X, lb, ws, (int64_t)ws_bytes))
+        return fail(LADDER_EINVAL, "X overlaps an input or the workspace");
+    return adjoint_impl(o, v, n, L, tau, wt, alpha, beta, X, (char*)ws, p, s, op, (hipStream_t)stream);
+}
+
+int ladder_autotune(int64_t o, int64_t v, int64_t n, const double* L, const double* tau, const double* tbar, double* R,
+                    double* X, void* ws, size_t ws_bytes, const ladder_options* opts, const char* cache_path,
+                    int64_t* n_abatch, void* stream) {
+    g_last_error.clear();
+    Sizes s;
+    ladder_options op;
+    int rc;
+    if ((rc = check_dims(o, v, n, s)) || (rc = get_opts(opts, op)) || (rc = check_split_dims(s, n, op))) return rc;
+    if (op.n_abatch != 0) return fail(LADDER_EINVAL, "autotune needs n_abatch = 0 (it chooses the batch size)");
+    if (!tbar || !X) return fail(LADDER_EINVAL, "tbar and X must be non-NULL");
+    const int64_t tb = s.ovv_elems * 8, lb = s.vvn * 8;
+    if (!aligned8(X) || overlap(X, lb, L, lb) || overlap(X, lb, tau, tb) || overlap(X, lb, tbar, tb) ||
+        overlap(X, lb, R, tb) || overlap(X, lb, ws, (int64_t)ws_bytes))
+        return fail(LADDER_EINVAL, "X misaligned or overlapping an input, R or the workspace");
+    const bool packed = !(op.flags & (LADDER_FLAG_GENERAL | LADDER_FLAG_DENSE));
+    const bool general = (op.flags & LADDER_FLAG_GENERAL) != 0;
+    const int64_t cap = std::max<int64_t>(1, packed ? (v + 3) / 4 : (v + 1) / 2);
+    std::vector<int64_t> cand{make_plan(o, v, n, op, s).nA};
+    for (int64_t c = 1; c < cap; c *= 2) cand.push_back(c);
+    cand.push_back(cap);
+    std::sort(cand.begin(), cand.end());
+    cand.erase(std::unique(cand.begin(), cand.end()), cand.end());
+    std::vector<Plan> plans;
+    for (int64_t c : cand) {
+        ladder_options oc = op;
+        oc.n_abatch = c;
+        Plan p = make_plan(o, v, n, oc, s);
+        if (p.total <= ws_bytes) plans.push_back(p);
+    }
+    if (plans.empty()) {
+        const Plan p1 = make_plan(o, v, n, op, s);
+        return fail(LADDER_EWORKSPACE, "workspace of %zu bytes fits no candidate (default needs %zu)", ws_bytes, p1.total);
+    }
+    if ((rc = check_forward_args(o, v, n, L, tau, tbar, R, nullptr, ws, ws_bytes, 0, "R", s))) return rc;
+    hipStream_t st = (hipStream_t)stream;
+    char* w = (char*)ws;
+    hipEvent_t e0, e1;
+    if ((rc = hip_check(hipEventCreate(&e0), "event create"))) return rc;
+    if ((rc = hip_check(hipEventCreate(&e1), "event create"))) {
+        (void)hipEventDestroy(e0);
+        return rc;
+    }
+    // forward + adjoint over batches [b_lo, b_hi) of plan p; milliseconds
+    auto timed = [&](Plan p, int64_t b_lo, int64_t b_hi, float& ms) -> int {
+        p.b_lo = b_lo;
+        p.b_hi = b_hi;
+        int r;
+        if ((r = hip_check(hipEventRecord(e0, st), "event record"))) return r;
+        if ((r = forward_impl(o, v, n, L, tau, tbar, 0.0, R, nullptr, w, p, s, st))) return r;
+        if ((r = adjoint_impl(o, v, n, L, tau, tbar, 1.0, 0.0, X, w, p, s, op, st))) return r;
+        if ((r = hip_check(hipEventRecord(e1, st), "event record"))) return r;
+        if ((r = hip_check(hipEventSynchronize(e1), "event sync"))) return r;
+        return hip_check(hipEventElapsedTime(&ms, e0, e1), "event time");
+    };
+    float ms = 0.0f;
+    double best_est = 0.0;
+    int64_t best = plans[0].nA;
+    rc = timed(plans[0], 0, std::min<int64_t>(1, plans[0].nbatch), ms);  // warm-up
+    for (size_t i = 0; i < plans.size() && !rc; ++i) {
+        const Plan& p = plans[i];
+        float t_pro = 0.0f;
+        if ((rc = timed(p, 0, 0, t_pro))) break;  // per-call work only (packing, slicing of the inputs)
+        const int64_t samples[2] = {0, p.nbatch / 2};
+        double t_s = 0.0, w_s = 0.0, w_all = 0.0;
+        for (int k = 0; k < (p.nbatch > 1 ? 2 : 1); ++k) {
+            if ((rc = timed(p, samples[k], samples[k] + 1, ms))) break;
+            t_s += std::max(0.0, (double)ms - (double)t_pro);
+            w_s += batch_work(p, o, v, n, s, general, samples[k]);
+        }
+        if (rc) break;
+        for (int64_t b = 0; b < p.nbatch; ++b) w_all += batch_work(p, o, v, n, s, general, b);
+        const double est = (double)t_pro + (w_s > 0.0 ? t_s / w_s * w_all : 0.0);
+        if (i == 0 || est < best_est) {
+            best_est = est;
+            best = p.nA;
+        }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (rc) return rc;
+    {
+        std::lock_guard<std::mutex> g(g_tune_mu);
+        g_tuned[tune_key(o, v, n, op)] = best;
+        ++g_tune_gen;
+    }
+    if (n_abatch) *n_abatch = best;
+    if (cache_path) {
+        FILE* f = fopen(cache_path, "a");
+        if (!f) return fail(LADDER_EINVAL, "cannot append to %s", cache_path);
+        fprintf(f,
+                "{\"device\": \"%s\", \"o\": %lld, \"v\": %lld, \"n\": %lld, \"precision\": %d, \"n_slices\": %d, "
+                "\"flags\": %u, \"n_abatch\": %lld, \"est_ms\": %.1f}\n",
+                device_tag().c_str(), (long long)o, (long long)v, (long long)n, (int)op.precision,
+                op.precision == LADDER_SPLIT_BF16 ? (int)op.n_slices : 0, (unsigned)op.flags, (long long)best, best_est);
+        fclose(f);
+    }
+    return LADDER_OK;
+}
+
+int ladder_autotune_load(const char* cache_path, int* n_loaded) {
+    g_last_error.clear();
+    if (!cache_path) return fail(LADDER_EINVAL, "cache_path is NULL");
+    FILE* f = fopen(cache_path, "r");
+    if (!f) return fail(LADDER_EINVAL, "cannot read %s", cache_path);
+    const std::string dev = device_tag();
+    char line[1024];
+    int count = 0;
+    auto field = [&](const char* key, long long& out) -> bool {
+        const char* q = strstr(line, key);
+        if (!q) return false;
+        q = strchr(q + strlen(key), ':');
+        return q && sscanf(q + 1, " %lld", &out) == 1;
+    };
+    while (fgets(line, sizeof line, f)) {
+        const char* d = strstr(line, "\"device\"");
+        const char* colon = d ? strchr(d + 8, ':') : nullptr;
+        if (!colon) continue;
+        const char* q1 = strchr(colon, '"');
+        const char* q2 = q1 ? strchr(q1 + 1, '"') : nullptr;
+        if (!q2 || std::string(q1 + 1, q2) != dev) continue;
+        long long o = 0, v = 0, n = 0, prec = 0, sl = 0, fl = 0, nA = 0;
+        if (!field("\"o\"", o) || !field("\"v\"", v) || !field("\"n\"", n) || !field("\"precision\"", prec) ||
+            !field("\"n_slices\"", sl) || !field("\"flags\"", fl) || !field("\"n_abatch\"", nA) || nA < 1 || nA > v)
+            continue;
+        std::lock_guard<std::mutex> g(g_tune_mu);
+        g_tuned[TuneKey{o, v, n, (int32_t)prec, (int32_t)sl, (uint32_t)fl}] = nA;  // later lines win
+        ++g_tune_gen;
+        ++count;
+    }
+    fclose(f);
+    if (n_loaded) *n_loaded = count;
+    return LADDER_OK;
+}
+
+void ladder_autotune_reset(void) {
+    std::lock_guard<std::mutex> g(g_tune_mu);
+    g_tuned.clear();
+    ++g_tune_gen;
 }
 
 int ladder_metric_contraction(int64_t v, int64_t n, const double* Z, const double* W, double alpha, double beta,
@@ -1148,8 +1379,13 @@ int ladder_batched(int count, const ladder_instance* inst, uint32_t what, void* 
     if (ws_bytes < bp.total) return fail(LADDER_EWORKSPACE, "workspace of %zu bytes, %zu needed", ws_bytes, bp.total);
 
     // Cache key: everything the captured launches depend on.
+    int64_t gen;
+    {
+        std::lock_guard<std::mutex> g(g_tune_mu);
+        gen = g_tune_gen;
+    }
     std::vector<int64_t> key = {count, (int64_t)what, (int64_t)(uintptr_t)ws, (int64_t)ws_bytes, bp.op.precision,
-                                bp.op.n_slices, bp.op.n_abatch, (int64_t)bp.op.flags};
+                                bp.op.n_slices, bp.op.n_abatch, (int64_t)bp.op.flags, gen};
     for (int i = 0; i < count; ++i) {
         const ladder_instance& x = inst[i];
         for (int64_t f : {x.o, x.v, x.n, (int64_t)(uintptr_t)x.L, (int64_t)(uintptr_t)x.tau, (int64_t)(uintptr_t)x.tbar,

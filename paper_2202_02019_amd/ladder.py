@@ -27,7 +27,8 @@ U_APPENDIX = 1
 
 EXPORTS = (
     "ladder_default_options", "ladder_workspace_size", "ladder_forward", "ladder_adjoint",
-    "ladder_tau_gradient_workspace_size", "ladder_tau_gradient", "ladder_metric_contraction",
+    "ladder_tau_gradient_workspace_size", "ladder_tau_gradient", "ladder_autotune", "ladder_autotune_load",
+    "ladder_autotune_reset", "ladder_metric_contraction",
     "ladder_back_transform_workspace_size", "ladder_back_transform", "ladder_excited_amplitudes",
     "ladder_mp2_amplitudes", "ladder_amplitude_update", "ladder_batched_workspace_size",
     "ladder_batched", "ladder_strerror", "ladder_last_error", "ladder_shutdown",
@@ -95,6 +96,11 @@ def _load():
     lib.ladder_adjoint.argtypes = [i64, i64, i64, vp, vp, vp, dbl, dbl, vp, vp, sz, op, vp]
     lib.ladder_tau_gradient_workspace_size.argtypes = [i64, i64, i64, op, ctypes.POINTER(sz)]
     lib.ladder_tau_gradient.argtypes = [i64, i64, i64, vp, vp, dbl, vp, vp, sz, op, vp]
+    lib.ladder_autotune.argtypes = [i64, i64, i64, vp, vp, vp, vp, vp, vp, sz, op, ctypes.c_char_p,
+                                    ctypes.POINTER(i64), vp]
+    lib.ladder_autotune_load.argtypes = [ctypes.c_char_p, ctypes.POINTER(ctypes.c_int)]
+    lib.ladder_autotune_reset.argtypes = []
+    lib.ladder_autotune_reset.restype = None
     lib.ladder_metric_contraction.argtypes = [i64, i64, vp, vp, dbl, dbl, vp, vp]
     lib.ladder_back_transform_workspace_size.argtypes = [i64, i64, ctypes.POINTER(sz)]
     lib.ladder_back_transform.argtypes = [i64, i64, vp, vp, vp, dbl, dbl, vp, vp, sz, vp]
@@ -105,7 +111,8 @@ def _load():
                                                   ctypes.POINTER(sz)]
     lib.ladder_batched.argtypes = [ctypes.c_int, ctypes.POINTER(_CInstance), ctypes.c_uint32, vp, sz, op, vp]
     for f in ("ladder_workspace_size", "ladder_forward", "ladder_adjoint", "ladder_tau_gradient_workspace_size",
-              "ladder_tau_gradient", "ladder_metric_contraction", "ladder_back_transform_workspace_size",
+              "ladder_tau_gradient", "ladder_autotune", "ladder_autotune_load", "ladder_metric_contraction",
+              "ladder_back_transform_workspace_size",
               "ladder_back_transform", "ladder_excited_amplitudes", "ladder_mp2_amplitudes",
               "ladder_amplitude_update", "ladder_batched_workspace_size", "ladder_batched"):
         getattr(lib, f).restype = ctypes.c_int
@@ -234,6 +241,35 @@ def tau_gradient(L, w, *, o, v, n, G=None, beta=0.0, ws=None, opts=None, stream=
     _check(_load().ladder_tau_gradient(o, v, n, _ptr(L), _ptr(w), float(beta), _ptr(G), _ptr(wsb),
                                        wsb.numel() * wsb.element_size(), ctypes.byref(c), _stream(stream)))
     return G
+
+
+def autotune(L, tau, tbar, *, o, v, n, ws, R=None, X=None, opts=None, cache_path=None, stream=None):
+    """Times candidate virtual-batch sizes within the workspace `ws` and keeps the fastest for later
+    calls with n_abatch = 0 (ladder_autotune).  Returns the chosen batch size.  R and X (allocated if
+    None) receive partial results."""
+    _need(L, "L", (v, v, n)); _need(tau, "tau", (o, o, v, v)); _need(tbar, "tbar", (o, o, v, v))
+    if R is None:
+        R = torch.empty((o, o, v, v), dtype=torch.float64, device=L.device)
+    if X is None:
+        X = torch.empty((v, v, n), dtype=torch.float64, device=L.device)
+    c = _opts(opts)
+    nA = ctypes.c_int64(0)
+    path = None if cache_path is None else os.fsencode(cache_path)
+    _check(_load().ladder_autotune(o, v, n, _ptr(L), _ptr(tau), _ptr(tbar), _ptr(R), _ptr(X), _ptr(ws),
+                                   ws.numel() * ws.element_size(), ctypes.byref(c), path, ctypes.byref(nA),
+                                   _stream(stream)))
+    return nA.value
+
+
+def autotune_load(cache_path) -> int:
+    """Loads tuned batch sizes of this device from a JSON-lines file; returns the number taken."""
+    k = ctypes.c_int(0)
+    _check(_load().ladder_autotune_load(os.fsencode(cache_path), ctypes.byref(k)))
+    return k.value
+
+
+def autotune_reset() -> None:
+    _load().ladder_autotune_reset()
 
 
 def w_intermediate(Z, tau, tbar, *, o, v, n, W=None, beta=0.0, ws=None, opts=None, stream=None):

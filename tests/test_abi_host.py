@@ -129,6 +129,50 @@ def test_intermediate_entry_validation():
     assert bt(ws=3 * FAKE) == EINVAL                             # workspace overlaps W
 
 
+def test_autotune_validation_and_cache(tmp_path):
+    """Argument checks run before any HIP call; the cache file is parsed line by line (other
+    devices' lines and junk are skipped) and a tuned batch size changes the ragged-batch plan."""
+    import torch
+    lib = _lib()
+    nA = ctypes.c_int64(0)
+
+    def tune(opts=None, tbar=3 * FAKE, X=5 * FAKE, wsb=1 << 40):
+        return lib.ladder_autotune(4, 20, 60, FAKE, 2 * FAKE, tbar, 4 * FAKE, X, 8 * FAKE, wsb, opts or _opts(),
+                                   None, ctypes.byref(nA), None)
+
+    assert tune(opts=_opts(n_abatch=3)) == EINVAL
+    assert tune(tbar=None) == EINVAL
+    assert tune(X=FAKE) == EINVAL                                # X aliases L
+    assert tune(wsb=64) == EWORKSPACE
+    assert lib.ladder_autotune_load(None, None) == EINVAL
+    assert lib.ladder_autotune_load(str(tmp_path / "missing.jsonl").encode(), None) == EINVAL
+    if torch.cuda.is_available():
+        pytest.skip("the cache lines below are written for a host without a GPU (device tag 'unknown')")
+    f = tmp_path / "tune.jsonl"
+    f.write_text('{"device": "unknown", "o": 4, "v": 20, "n": 60, "precision": 0, "n_slices": 0, "flags": 0, '
+                 '"n_abatch": 3, "est_ms": 1.0}\n'
+                 '{"device": "gfx950:256", "o": 4, "v": 20, "n": 60, "precision": 0, "n_slices": 0, "flags": 0, '
+                 '"n_abatch": 7, "est_ms": 1.0}\n'
+                 'not a cache line\n'
+                 '{"device": "unknown", "o": 4, "v": 20, "n": 60, "precision": 0, "n_slices": 0, "flags": 0, '
+                 '"n_abatch": 999, "est_ms": 1.0}\n')
+    arr = (B._CInstance * 1)()
+    arr[0] = B._CInstance(4, 20, 60, FAKE, 2 * FAKE, 3 * FAKE, 4 * FAKE, 5 * FAKE, 6 * FAKE)
+
+    def bws():
+        b = ctypes.c_size_t(0)
+        assert lib.ladder_batched_workspace_size(1, arr, 3, _opts(), ctypes.byref(b)) == 0
+        return b.value
+
+    P.autotune_reset()
+    before = bws()
+    assert P.autotune_load(str(f)) == 1                          # the foreign device, junk and n_abatch > v are skipped
+    tuned = bws()
+    P.autotune_reset()
+    assert bws() == before
+    assert tuned < before                                        # 3 virtual indices per batch instead of 10
+
+
 def test_amplitude_entry_validation():
     lib = _lib()
     assert lib.ladder_mp2_amplitudes(0, 2, 2, FAKE, 2 * FAKE, 3 * FAKE, None) == EINVAL

@@ -582,3 +582,36 @@ def test_excited_amplitudes_and_density(dev, mode):
     Tg = g(T, dev)
     P.excited_amplitudes(Tg, g(R2, dev), 0.75, o=o, v=v, mode=mode, U=Tg)
     assert np.array_equal(Tg.cpu().numpy(), Ur)
+
+
+# ------------------------------------------------------------------ autotuned batch size
+@pytest.mark.parametrize("precision", [P.FP64, P.SPLIT_BF16])
+def test_autotune_then_default_calls_use_it(dev, tmp_path, precision):
+    """The tuner picks a batch size within the workspace it is given, writes a cache line that
+    reloads, and the following default calls (n_abatch = 0) run that plan and still match the oracle."""
+    o, v, n = 5, 53, 70
+    L, tau, w = gaussian_inputs(95, o, v, n)
+    Lg, tg, wg = g(L, dev), g(tau, dev), g(w, dev)
+    opts = P.Options(precision=precision)
+    P.autotune_reset()
+    cap = (v + 3) // 4
+    ws = torch.empty(P.workspace_size(o, v, n, P.Options(precision=precision, n_abatch=cap)), dtype=torch.uint8,
+                     device=dev)
+    cache = tmp_path / "tune.jsonl"
+    nA = P.autotune(Lg, tg, wg, o=o, v=v, n=n, ws=ws, opts=opts, cache_path=str(cache))
+    assert 1 <= nA <= cap
+    line = cache.read_text().strip().splitlines()[-1]
+    assert '"n_abatch": %d' % nA in line and '"v": 53' in line
+    assert P.workspace_size(o, v, n, opts) <= ws.numel()
+    R, E, X = run(dev, o, v, n, L, tau, w, opts)
+    Rr, Er = oracle.forward(o, v, n, L, tau, w)
+    Xr = oracle.adjoint(o, v, n, L, tau, w)
+    tol_rx, tol_e = (TOL, TOL) if precision == P.FP64 else (SPLIT_TOL_RX, None)
+    assert err_norm(R, Rr) <= tol_rx and err_norm(X, Xr) <= tol_rx
+    if tol_e is None:
+        assert err_E_terms(E, Er, w, Rr) <= SPLIT_TOL_E
+    else:
+        assert err_rel(E, Er) <= tol_e
+    P.autotune_reset()
+    assert P.autotune_load(str(cache)) == 1
+    P.autotune_reset()
