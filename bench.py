@@ -184,8 +184,6 @@ def main():
         torch.cuda.empty_cache()
         print("bench: autotune chose n_abatch = %d in %.1f s" % (tuned, tune_s), file=sys.stderr, flush=True)
     wsb = P.workspace_size(o, v, n, opts)
-    if args.next_rows:
-        wsb = max(wsb, P.tau_gradient_workspace_size(o, v, n, opts), P.back_transform_workspace_size(v, n))
     ws = torch.empty(wsb, dtype=torch.uint8, device=dev)
     torch.cuda.synchronize()
     print("bench: %s o=%d v=%d n=%d precision=%s inputs ready in %.1fs, workspace %.2f GiB"
@@ -247,10 +245,16 @@ def main():
     compare = None
     if args.precision == "split" and not args.no_compare:
         # the same step on the FP64 MFMA path, untimed for `value`
-        o64 = P.Options(precision=P.FP64, n_abatch=16 if name == "retinal" else 0,
+        # the FP64 leg takes its batch size from the tuned table when the cache has one for it
+        t64 = tuned_batch(args.tuned if args.tuned not in (None, "none") else None, o, v, n, 0, 0, flags)
+        if t64:
+            P.autotune_load(args.tuned)
+        o64 = P.Options(precision=P.FP64, n_abatch=0 if t64 else (16 if name == "retinal" else 0),
                         flags=P.FLAG_DENSE if args.dense else 0)
-        ws64 = torch.empty(P.workspace_size(o, v, n, o64), dtype=torch.uint8, device=dev) if \
-            P.workspace_size(o, v, n, o64) > ws.numel() else ws
+        # the FP64 leg gets its own workspace in place of the split one (never both at once)
+        del ws
+        torch.cuda.empty_cache()
+        ws64 = torch.empty(P.workspace_size(o, v, n, o64), dtype=torch.uint8, device=dev)
         R64 = torch.empty_like(R)
         E64 = torch.empty((), dtype=torch.float64, device=dev)
         X64 = torch.empty_like(X)
@@ -263,21 +267,31 @@ def main():
         ms64 = ev0.elapsed_time(ev1)
         e64 = float(E64.cpu())
         compare = {"fp64_ms_per_step": ms64, "fp64_tflops": F / (ms64 * 1e-3) / 1e12, "speedup_vs_fp64": ms64 / ms,
+                   "fp64_n_abatch": t64 or o64.n_abatch,
                    "err_E_vs_fp64": abs(float(E.cpu()) - e64) / abs(e64),
                    "err_R_vs_fp64": float((R - R64).abs().max() / R64.abs().max()),
                    "err_X_vs_fp64": float((X - X64).abs().max() / X64.abs().max())}
         del R64, X64, ws64
+        torch.cuda.empty_cache()
+        ws = torch.empty(wsb, dtype=torch.uint8, device=dev)
         print("bench: fp64 comparison step %.1f s" % (ms64 / 1e3), file=sys.stderr, flush=True)
 
     nxt = None
     if args.next_rows:
         import oracle
         nxt = {}
+        # its own workspace (at retinal scale with the batch of 8, so that G fits beside it)
+        opts_n = P.Options(precision=prec, n_slices=args.slices, n_abatch=8 if name == "retinal" else args.n_abatch,
+                           flags=P.FLAG_DENSE if args.dense else 0)
+        del ws
+        torch.cuda.empty_cache()
+        ws = torch.empty(max(P.tau_gradient_workspace_size(o, v, n, opts_n), P.back_transform_workspace_size(v, n)),
+                         dtype=torch.uint8, device=dev)
         # dE/dtau = transposed ladder of tbar; nominal flops as the forward (2 n v^4 + 2 o^2 v^4)
         G = torch.empty_like(R)
         torch.cuda.synchronize()
         ev0.record(stream)
-        P.tau_gradient(L, tbar, o=o, v=v, n=n, G=G, ws=ws, opts=opts)
+        P.tau_gradient(L, tbar, o=o, v=v, n=n, G=G, ws=ws, opts=opts_n)
         ev1.record(stream)
         torch.cuda.synchronize()
         mst = ev0.elapsed_time(ev1)
