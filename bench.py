@@ -66,16 +66,17 @@ def gemm_source_hash():
     return h.hexdigest()[:16]
 
 
-def measured_traffic(workload, precision, kernel):
+def measured_traffic(workload, precision, kernel, n_abatch):
     """HBM bytes per launch of `kernel` from the committed rocprofv3 FETCH_SIZE /
-    WRITE_SIZE summary for this workload, or None when there is none or the GEMM
-    sources have changed since the counters were taken."""
+    WRITE_SIZE summary for this workload, or None when there is none, it was taken
+    at another virtual-batch size, or the GEMM sources have changed since."""
     path = os.path.join(ROOT, "profiles", "traffic_%s_%s_pm.json" % (workload, precision))
     if not os.path.exists(path):
         return None
     with open(path) as fh:
         rec = json.load(fh)
-    if rec.get("sources_sha256_16") != gemm_source_hash() or kernel not in rec.get("kernels", {}):
+    if rec.get("sources_sha256_16") != gemm_source_hash() or kernel not in rec.get("kernels", {}) or \
+            rec.get("n_abatch") != n_abatch:
         return None
     return rec["kernels"][kernel]["bytes"]
 
@@ -220,8 +221,8 @@ def main():
     # FP64-equivalent rate of the dominant stage: 2 M N K flops per launch over its mean launch time
     fp64_equiv = dom["flops"] / dom["launches"] / (dom["avg_ms"] * 1e-3) / 1e12
     nA_eff = args.n_abatch or tuned
-    default_shape = (args.slices in (0, 5) and not args.dense and nA_eff == (8 if args.precision == "split" else 16))
-    traffic = measured_traffic(name, args.precision, dom_name) if default_shape else None
+    default_shape = args.slices in (0, 5) and not args.dense
+    traffic = measured_traffic(name, args.precision, dom_name, nA_eff) if default_shape else None
     if args.precision == "split":
         # the split method's unit of work: S(S+1)/2 BF16 slice products per FP64-equivalent MAC
         S = args.slices or 5
@@ -251,9 +252,16 @@ def main():
             P.autotune_load(args.tuned)
         o64 = P.Options(precision=P.FP64, n_abatch=0 if t64 else (16 if name == "retinal" else 0),
                         flags=P.FLAG_DENSE if args.dense else 0)
-        # the FP64 leg gets its own workspace in place of the split one (never both at once)
+        # the FP64 leg gets its own workspace in place of the split one (never both at once),
+        # with the tuned batch only if it fits beside R64 and X64
         del ws
         torch.cuda.empty_cache()
+        free, _ = torch.cuda.mem_get_info()
+        extra = (R.numel() + X.numel()) * 8 + (4 << 30)
+        if t64 and P.workspace_size(o, v, n, o64) + extra > free:
+            t64 = None
+            o64 = P.Options(precision=P.FP64, n_abatch=16 if name == "retinal" else 0,
+                            flags=P.FLAG_DENSE if args.dense else 0)
         ws64 = torch.empty(P.workspace_size(o, v, n, o64), dtype=torch.uint8, device=dev)
         R64 = torch.empty_like(R)
         E64 = torch.empty((), dtype=torch.float64, device=dev)
@@ -413,8 +421,9 @@ def run_batched(args):
     if args.n_abatch == 0 and args.autotune:
         # tune every instance shape once (each on its own data), appending to the cache
         c0 = time.time()
+        # each instance's plan must leave room for the graph's branch slots side by side
         free, _ = torch.cuda.mem_get_info()
-        wst = torch.empty(min(max(free // 2, 1 << 20), 64 << 30), dtype=torch.uint8, device=dev)
+        wst = torch.empty(max(free // 6, 1 << 20), dtype=torch.uint8, device=dev)
         for d in insts:
             P.autotune(d["L"], d["tau"], d["tbar"], o=d["o"], v=d["v"], n=d["n"], ws=wst, R=d["R"], X=d["X"],
                        opts=opts, cache_path=args.autotune)
