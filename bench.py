@@ -463,13 +463,17 @@ def run_batched(args):
     print("bench: graph %.1f ms per batch" % ms, file=sys.stderr, flush=True)
     # the same work as 64 sequential forward + adjoint calls on one stream
     wsq = torch.empty(max(P.workspace_size(d["o"], d["v"], d["n"], opts) for d in insts), dtype=torch.uint8, device=dev)
-    ev0.record(stream)
-    for d in insts:
+    evs = [torch.cuda.Event(enable_timing=True) for _ in range(len(insts) + 1)]
+    evs[0].record(stream)
+    for k, d in enumerate(insts):
         P.forward(d["L"], d["tau"], d["tbar"], o=d["o"], v=d["v"], n=d["n"], R=d["R"], E=d["E"], ws=wsq, opts=opts)
         P.adjoint(d["L"], d["tau"], d["tbar"], o=d["o"], v=d["v"], n=d["n"], X=d["X"], ws=wsq, opts=opts)
-    ev1.record(stream)
+        evs[k + 1].record(stream)
     torch.cuda.synchronize()
-    ms_seq = ev0.elapsed_time(ev1)
+    ms_seq = evs[0].elapsed_time(evs[-1])
+    per_inst = [{"o": d["o"], "v": d["v"], "n": d["n"], "ms": evs[k].elapsed_time(evs[k + 1]),
+                 "tflops": nominal_flops(d["o"], d["v"], d["n"]) / (evs[k].elapsed_time(evs[k + 1]) * 1e-3) / 1e12}
+                for k, d in enumerate(insts)]
     out = {
         "metric": "ladder fwd+adjoint TFLOP/s & s/iter, split-BF16 vs FP64 at <=1e-10 rel err in E",
         "value": F / (ms * 1e-3) / 1e12, "unit": "TFLOP/s", "n_gpus": 1, "steps": steps, "warmup": warmup,
@@ -480,6 +484,7 @@ def run_batched(args):
                    "n_abatch_source": tuned_src or ("explicit" if args.n_abatch else "library default"),
                    "nominal_flops": F},
         "sequential_ms": ms_seq, "sequential_tflops": F / (ms_seq * 1e-3) / 1e12, "graph_speedup": ms_seq / ms,
+        "sequential_per_instance": per_inst,
         "roofline": None, "cpu_baseline": None,
     }
     print(json.dumps(out))

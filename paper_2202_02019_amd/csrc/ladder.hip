@@ -203,6 +203,7 @@ struct Plan {
     SlicedBuf tp_cd, tm_cd, gp_sl, gm_sl;                               // forward, split
     size_t a_wp = 0, a_wm = 0, a_tp = 0, a_tm = 0, a_dp = 0, a_dm = 0;  // adjoint, FP64
     SlicedBuf wp_ij, wm_ij, tp_ij, tm_ij;                               // adjoint, split
+    SlicedBuf L_b;                                                      // adjoint, split: L rows (b in batch) along K
     // split-K partial tiles of the long-K split GEMMs (GEMM-C on the +/- path, GEMM-F)
     size_t f_skp = 0, a_skp = 0;
     int64_t f_skp_elems = 0, a_skp_elems = 0;
@@ -234,7 +235,14 @@ Plan make_plan(int64_t o, int64_t v, int64_t n, const ladder_options& op, const 
 
     Arena a;
     p.tile_off = a.take((size_t)(nA * s.vvv) * 8);
-    if (p.S) p.tile_sl = take_sliced(a, p.S, nA * v, s.vv);
+    if (p.S) {
+        // slices of the batch tile: rows n_A v along K = v^2 (GEMM-F of the dense path and the
+        // packed path's tile (alpha)), or rows v^2 along K = n_A v (tile (beta)); room for either
+        p.tile_sl.R = nA * v;
+        p.tile_sl.K = s.vv;
+        p.tile_sl.s_off = a.take(std::max(slice_bytes(p.S, nA * v, s.vv), slice_bytes(p.S, s.vv, nA * v)));
+        p.tile_sl.e_off = a.take(std::max(exp_bytes(nA * v, s.vv), exp_bytes(s.vv, nA * v)));
+    }
     const size_t common = a.top;
 
     const bool general = (op.flags & LADDER_FLAG_GENERAL) != 0;
@@ -287,22 +295,23 @@ Plan make_plan(int64_t o, int64_t v, int64_t n, const ladder_options& op, const 
             }
         }
     } else {
-        p.a_wp = d.take((size_t)(p.P2o * s.vv) * 8);
-        p.a_wm = d.take((size_t)(p.Q2o * s.vv) * 8 + 8);
+        p.a_wp = d.take((size_t)(p.P2o * p.P2v) * 8);
+        p.a_wm = d.take((size_t)(p.Q2o * p.Q2v) * 8 + 8);
         p.a_tp = d.take((size_t)(p.P2o * p.P2v) * 8);
         p.a_tm = d.take((size_t)(p.Q2o * p.Q2v) * 8 + 8);
         p.a_dp = d.take((size_t)(nA * v * p.P2v) * 8);
         p.a_dm = d.take((size_t)(nA * v * p.Q2v) * 8 + 8);
         if (p.S) {
-            p.wp_ij = take_sliced(d, p.S, s.vv, p.P2o);
-            p.wm_ij = take_sliced(d, p.S, s.vv, std::max<int64_t>(p.Q2o, 1));
+            p.wp_ij = take_sliced(d, p.S, p.P2v, p.P2o);
+            p.wm_ij = take_sliced(d, p.S, std::max<int64_t>(p.Q2v, 1), std::max<int64_t>(p.Q2o, 1));
             p.tp_ij = take_sliced(d, p.S, p.P2v, p.P2o);
             p.tm_ij = take_sliced(d, p.S, std::max<int64_t>(p.Q2v, 1), std::max<int64_t>(p.Q2o, 1));
             p.L_bd = take_sliced(d, p.S, n, s.vv);
+            p.L_b = take_sliced(d, p.S, n, nA * v);
         }
     }
     if (p.S) {
-        p.a_skp_elems = KSPLIT_MAX * nA * v * n;
+        p.a_skp_elems = KSPLIT_MAX * nA * v * n;  // split-K only where ksplit * M * n fits (choose_ksplit)
         p.a_skp = d.take((size_t)p.a_skp_elems * 8);
     }
     p.adj_total = d.top;
@@ -359,10 +368,12 @@ Plan choose_plan(int64_t o, int64_t v, int64_t n, const ladder_options& op, cons
 // turns the timed sample batches into an estimate for the whole call.
 double batch_work(const Plan& p, int64_t o, int64_t v, int64_t n, const Sizes& s, bool general, int64_t bi) {
     const int64_t a0 = bi * p.nA, nA = std::min(p.nA, v - a0);
-    if (p.pm) {
+    if (p.pm) {  // forward over a in [a0, a0+nA); adjoint over b in [a0, a0+nA) with rows a <= b
         const double NPb = (double)pm_gp_off(nA, v, a0), NMb = (double)pm_gm_off(nA, v, a0);
+        const int64_t A = a0 + nA;
+        const double rowsP = (double)(pm_P2(A) - pm_P2(a0)), rowsQ = (double)(pm_Q2(A) - pm_Q2(a0));
         return gemm_flops(nA * v, (v - a0) * v, n) + 2.0 * ((double)p.P2o * NPb * p.P2v + (double)p.Q2o * NMb * p.Q2v) +
-               2.0 * (double)(nA * v) * ((double)p.P2v * p.P2o + (double)p.Q2v * p.Q2o) + gemm_flops(nA * v, n, s.vv);
+               2.0 * (rowsP * p.P2v * p.P2o + rowsQ * p.Q2v * p.Q2o) + 2.0 * gemm_flops(nA * v, n, A * v);
     }
     (void)o;
     return gemm_flops(nA * v, s.vv, n) + gemm_flops(s.oo, nA * v, s.vv) + (general ? 2.0 : 1.0) * gemm_flops(nA * v, s.vv, s.oo) +
@@ -494,6 +505,11 @@ int slice_into(int S, bool transposed, const double* src, int64_t ld, char* ws, 
 __global__ void fill_zero_kernel(double* __restrict__ x, int64_t count) {
     for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < count; t += (int64_t)gridDim.x * blockDim.x)
         x[t] = 0.0;
+}
+
+__global__ void scale_kernel(double* __restrict__ x, int64_t count, double f) {
+    for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < count; t += (int64_t)gridDim.x * blockDim.x)
+        x[t] *= f;
 }
 
 // out_ij^ab = in_ji^ba
@@ -670,9 +686,12 @@ int forward_pm(int64_t o, int64_t v, int64_t n, const double* L, const double* t
     return LADDER_OK;
 }
 
-// Adjoint with the packing: D+ = w+^T tau+ over (i<=j) and D- = w-^T tau- over
-// (i<j), on the (c<=d) / (c<d) columns only; the unpack kernel rebuilds the D
-// tile [(a,c),(b,d)] that GEMM-F contracts with L.
+// Adjoint with the packing (pm_pack.hpp): the density is formed only on its rows
+// a <= b, D+ = Wp^T tau+ on rows P(a,b) and D- = Wm^T tau- on rows Q(a,b), batch by
+// batch of b; each batch's rows feed X twice, through tile (alpha) (X rows of the
+// batch's b, K over a < b0 + nB) and tile (beta) (X rows a < b0 + nB, K over the
+// batch's b).  X is scaled by beta once, then every contribution is added in a fixed
+// order (deterministic).
 int adjoint_pm(int64_t o, int64_t v, int64_t n, const double* L, const double* tau, const double* wt, double alpha,
                double beta, double* X, char* w, const Plan& p, const Sizes& s, hipStream_t st) {
     int rc;
@@ -681,64 +700,81 @@ int adjoint_pm(int64_t o, int64_t v, int64_t n, const double* L, const double* t
     double *wp = (double*)(w + p.a_wp), *wm = (double*)(w + p.a_wm), *tp = (double*)(w + p.a_tp),
            *tm = (double*)(w + p.a_tm), *dp = (double*)(w + p.a_dp), *dm = (double*)(w + p.a_dm);
     {
-        StageTimer tm_(LADDER_STAGE_PACK, 0.0, 16.0 * (double)(pm_amp_count(o, v) + pm_w_count(o, v)), st);
+        StageTimer tm_(LADDER_STAGE_PACK, 0.0, 16.0 * (double)(2 * pm_amp_count(o, v)), st);
         pm_pack_amp(tau, o, v, tp, tm, st);
-        hipLaunchKernelGGL(pm_pack_w_tiled_kernel, pm_grid(v, p.P2o), dim3(256), 0, st, wt, o, v, p.P2o, 1, wp);
-        if (p.Q2o > 0)
-            hipLaunchKernelGGL(pm_pack_w_tiled_kernel, pm_grid(v, p.Q2o), dim3(256), 0, st, wt, o, v, p.Q2o, 0, wm);
+        const PmRows rw{2, o, 0, 0};
+        hipLaunchKernelGGL(pm_pack_sym_tiled_kernel, pm_grid(v, p.P2o), dim3(256), 0, st, wt, v, rw, p.P2o, 1, wp);
+        if (p.Q2o > 0 && p.Q2v > 0)
+            hipLaunchKernelGGL(pm_pack_sym_tiled_kernel, pm_grid(v, p.Q2o), dim3(256), 0, st, wt, v, rw, p.Q2o, 0, wm);
         if ((rc = hip_check(hipGetLastError(), "pack launch"))) return rc;
+    }
+    {   // X = beta X (not read when beta = 0); every product below adds to it
+        if (beta == 0.0) hipLaunchKernelGGL(fill_zero_kernel, dim3(grid_for(s.vvn)), dim3(256), 0, st, X, s.vvn);
+        else if (beta != 1.0) hipLaunchKernelGGL(scale_kernel, dim3(grid_for(s.vvn)), dim3(256), 0, st, X, s.vvn, beta);
+        if ((rc = hip_check(hipGetLastError(), "scale launch"))) return rc;
     }
     const bool minus = p.Q2o > 0 && p.Q2v > 0;
     if (S) {
-        if ((rc = slice_into(S, true, wp, s.vv, w, p.wp_ij, st))) return rc;
+        if ((rc = slice_into(S, true, wp, p.P2v, w, p.wp_ij, st))) return rc;
         if ((rc = slice_into(S, true, tp, p.P2v, w, p.tp_ij, st))) return rc;
         if (minus) {
-            if ((rc = slice_into(S, true, wm, s.vv, w, p.wm_ij, st))) return rc;
+            if ((rc = slice_into(S, true, wm, p.Q2v, w, p.wm_ij, st))) return rc;
             if ((rc = slice_into(S, true, tm, p.Q2v, w, p.tm_ij, st))) return rc;
         }
         if ((rc = slice_into(S, true, L, n, w, p.L_bd, st))) return rc;
     }
     for (int64_t bi = p.b_lo; bi < p.b_hi; ++bi) {
-        const int64_t a0 = bi * p.nA;
-        const int64_t nA = std::min(p.nA, v - a0);
-        for (int sign = 0; sign < (minus ? 2 : 1); ++sign) {
-            const int64_t M = nA * v, N = sign ? p.Q2v : p.P2v, K = sign ? p.Q2o : p.P2o;
+        const int64_t b0 = bi * p.nA;
+        const int64_t nB = std::min(p.nA, v - b0), A = b0 + nB;
+        const int64_t rowsP = pm_P2(A) - pm_P2(b0), rowsQ = pm_Q2(A) - pm_Q2(b0);
+        for (int sign = 0; sign < 2; ++sign) {
+            const int64_t M = sign ? rowsQ : rowsP, N = sign ? p.Q2v : p.P2v, K = sign ? p.Q2o : p.P2o;
+            if (M == 0 || N == 0) continue;
+            if (sign && !minus) {  // o = 1: no antisymmetric part, D- = 0
+                hipLaunchKernelGGL(fill_zero_kernel, dim3(grid_for(M * N)), dim3(256), 0, st, dm, M * N);
+                if ((rc = hip_check(hipGetLastError(), "fill launch"))) return rc;
+                continue;
+            }
             StageTimer tm_(LADDER_STAGE_GEMM_E, gemm_flops(M, N, K), gemm_bytes(M, N, K), st);
             EpiStrided ed{sign ? dm : dp, N, 1.0, 0.0, nullptr, nullptr};
             hipError_t e;
+            const int64_t r0 = sign ? pm_Q2(b0) : pm_P2(b0);
             if (!S) {
-                e = launch_gemm<false, false, LADDER_STAGE_GEMM_E>((sign ? wm : wp) + a0 * v, s.vv, sign ? tm : tp, N, M, N, K, ed, st);
+                e = launch_gemm<false, false, LADDER_STAGE_GEMM_E>((sign ? wm : wp) + r0, N, sign ? tm : tp, N, M, N, K, ed, st);
             } else {
-                SplitShape sh{view(w, sign ? p.wm_ij : p.wp_ij, a0 * v), view(w, sign ? p.tm_ij : p.tp_ij, 0), M, N, K};
+                SplitShape sh{view(w, sign ? p.wm_ij : p.wp_ij, r0), view(w, sign ? p.tm_ij : p.tp_ij, 0), M, N, K};
                 e = launch_split<LADDER_STAGE_GEMM_E>(S, sh, ed, st);
             }
             if ((rc = hip_check(e, "GEMM-E launch"))) return rc;
         }
-        if (!minus && p.Q2v > 0) {  // o = 1: no antisymmetric part, D- = 0
-            hipLaunchKernelGGL(fill_zero_kernel, dim3(grid_for(nA * v * p.Q2v)), dim3(256), 0, st, dm, nA * v * p.Q2v);
-            if ((rc = hip_check(hipGetLastError(), "fill launch"))) return rc;
+        if (S) {  // L rows (b, w) of this batch, the K of tile (beta)
+            SlicedBuf lb = p.L_b;
+            lb.K = nB * v;
+            if ((rc = slice_into(S, true, L + b0 * v * n, n, w, lb, st))) return rc;
         }
-        {
-            StageTimer tm_(LADDER_STAGE_UNPACK, 0.0, 24.0 * (double)(nA * s.vvv), st);
-            hipLaunchKernelGGL(pm_unpack_D_tiled_kernel, pm_grid(v, nA * v), dim3(256), 0, st, dp, dm, v, nA * v, D);
-            if ((rc = hip_check(hipGetLastError(), "unpack launch"))) return rc;
-        }
-        if (S) {
+        for (int pass = 0; pass < 2; ++pass) {  // 0: tile (alpha), 1: tile (beta)
+            const int64_t M = pass ? A * v : nB * v, K = pass ? nB * v : A * v;
+            {
+                StageTimer tm_(LADDER_STAGE_UNPACK, 0.0, 8.0 * (double)(M * K) + 8.0 * (double)(rowsP * p.P2v + rowsQ * p.Q2v), st);
+                hipLaunchKernelGGL(pm_tile_ab_kernel, pm_grid(v, nB * A), dim3(256), 0, st, dp, dm, v, b0, nB,
+                                   pass ? 0 : 1, D);
+                if ((rc = hip_check(hipGetLastError(), "tile launch"))) return rc;
+            }
             SlicedBuf tl = p.tile_sl;
-            tl.R = nA * v;
-            if ((rc = slice_into(S, false, D, s.vv, w, tl, st))) return rc;
-        }
-        {
-            StageTimer tm_(LADDER_STAGE_GEMM_F, gemm_flops(nA * v, n, s.vv), gemm_bytes(nA * v, n, s.vv), st);
-            EpiStrided ex{X + a0 * v * n, n, 2.0 * alpha, beta, nullptr, nullptr};
+            tl.R = M;
+            tl.K = K;
+            if (S && (rc = slice_into(S, false, D, K, w, tl, st))) return rc;
+            StageTimer tm_(LADDER_STAGE_GEMM_F, gemm_flops(M, n, K), gemm_bytes(M, n, K), st);
+            // alpha: X rows (b, y), B = L rows (a, w) for a < A;  beta: X rows (a, y), B = L rows (b, w) of the batch
+            EpiStrided ex{X + (pass ? 0 : b0 * v * n), n, 2.0 * alpha, 1.0, nullptr, nullptr};
             hipError_t e;
             if (!S) {
-                e = launch_gemm<true, false, LADDER_STAGE_GEMM_F>(D, s.vv, L, n, nA * v, n, s.vv, ex, st);
+                e = launch_gemm<true, false, LADDER_STAGE_GEMM_F>(D, K, pass ? L + b0 * v * n : L, n, M, n, K, ex, st);
             } else {
-                SlicedBuf tl = p.tile_sl;
-                tl.R = nA * v;
-                SplitShape sh{view(w, tl, 0), view(w, p.L_bd, 0), nA * v, n, s.vv};
-                sh.ksplit = choose_ksplit(nA * v, n, s.vv, p.a_skp_elems);
+                SlicedBuf lb = p.L_b;
+                lb.K = nB * v;
+                SplitShape sh{view(w, tl, 0), pass ? view(w, lb, 0) : view(w, p.L_bd, 0), M, n, K};
+                sh.ksplit = choose_ksplit(M, n, K, p.a_skp_elems);
                 sh.part = (double*)(w + p.a_skp);
                 e = launch_split<LADDER_STAGE_GEMM_F>(S, sh, ex, st);
             }

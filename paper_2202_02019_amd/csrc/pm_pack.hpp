@@ -81,7 +81,8 @@ __host__ __device__ inline void pm_pack_amp_elem(int64_t t, const double* x, int
     }
 }
 
-// tbar -> wp[P(i,j)][(a,b)] = (2 - delta_ij) (t_ij^ab + t_ij^ba)/2, wm[Q(i,j)][(a,b)] = t_ij^ab - t_ij^ba.
+// tbar -> wp[P(i,j)][(a,b)] = (2 - delta_ij) (t_ij^ab + t_ij^ba)/2, wm[Q(i,j)][(a,b)] = t_ij^ab - t_ij^ba
+// over all (a, b): the reference the packed-row weights Wp, Wm are checked against.
 __host__ __device__ inline void pm_pack_w_elem(int64_t t, const double* x, int64_t o, int64_t v, double* wp, double* wm) {
     const int64_t vv = v * v, np = pm_P2(o) * vv;
     const bool plus = t < np;
@@ -154,18 +155,40 @@ __host__ __device__ inline bool pm_unpack_R_elem(int64_t t, const double* rp, co
     return true;
 }
 
-// D tile [(a',c)][(b,d)] of a batch from dp[(a',b)][P(c,d)] and dm[(a',b)][Q(c,d)]:
-//   D_{ab,cd} = dp[(a,b)][P(min,max)] + s_cd dm[(a,b)][Q(min,max)].
-// Slot t enumerates (a', b, c, d) with d fastest: one (a', b) at a time, so the
-// packed rows being gathered stay in L2 while whole d-runs of D are written.
-__host__ __device__ inline void pm_unpack_D_elem(int64_t t, const double* dp, const double* dm, int64_t v, double* D) {
-    const int64_t cp = pm_P2(v), cm = pm_Q2(v);
-    const int64_t d = t % v, c = (t / v) % v, row = t / (v * v);  // row = a' v + b
-    const int64_t b = row % v, ap = row / v;
+// ---- adjoint with packed density rows (a <= b) ----
+// The density is symmetric under the pair exchange, D_{ab,cd} = D_{ba,dc}, so the
+// adjoint forms only the rows a <= b: D+ = Wp^T Tp on rows P(a,b) and D- = Wm^T Tm
+// on rows Q(a,b), for the b of a batch [b0, b0+nB), with
+//   Wp[P(i,j)][P(a,b)] = (2 - delta_ij)(t_ij^ab + t_ij^ba)/2,  Wm[Q(i,j)][Q(a,b)] = t_ij^ab - t_ij^ba,
+// and X^J_xy = sum_zw D_{xz,yw} L^J_zw is assembled from the two uses of each row:
+//   (alpha) X_{b y} += sum_{a<b, w} D_{ab,wy} L_{a w}       rows (b, y), K = (a, w), a < b0 + nB
+//   (beta)  X_{a y} += sum_{b, w}   D_{ab,yw} L_{b w}       rows (a, y), K = (b, w), a <= b
+// (the z > x terms of X_x come from (beta) with (a, b) = (x, z), the z < x terms from
+// (alpha) with (a, b) = (z, x)).
+
+// D_{ab,cd} for a <= b, b in [b0, b0+nB), from the batch's packed rows.
+__host__ __device__ inline double pm_density(const double* dp, const double* dm, int64_t v, int64_t b0, int64_t a, int64_t b,
+                                             int64_t c, int64_t d) {
     const int64_t lo = c < d ? c : d, hi = c < d ? d : c;
-    double x = dp[row * cp + pm_P(lo, hi)];
-    if (c != d) x += (c < d ? 1.0 : -1.0) * dm[row * cm + pm_Q(lo, hi)];
-    D[((ap * v + c) * v + b) * v + d] = x;
+    double x = dp[(pm_P(a, b) - pm_P2(b0)) * pm_P2(v) + pm_P(lo, hi)];
+    if (a < b && c != d) x += (c < d ? 1.0 : -1.0) * dm[(pm_Q(a, b) - pm_Q2(b0)) * pm_Q2(v) + pm_Q(lo, hi)];
+    return x;
+}
+// Tile (alpha), [(b - b0) v + y][a v + w] with a < b0 + nB: D_{ab,wy} for a < b, else 0.
+__host__ __device__ inline void pm_tile_alpha_elem(int64_t t, const double* dp, const double* dm, int64_t v, int64_t b0,
+                                                   int64_t nB, double* T) {
+    const int64_t K = (b0 + nB) * v;
+    const int64_t row = t / K, col = t % K;
+    const int64_t b = b0 + row / v, y = row % v, a = col / v, w = col % v;
+    T[t] = a < b ? pm_density(dp, dm, v, b0, a, b, w, y) : 0.0;
+}
+// Tile (beta), [a v + y][(b - b0) v + w] with a < b0 + nB: D_{ab,yw} for a <= b, else 0.
+__host__ __device__ inline void pm_tile_beta_elem(int64_t t, const double* dp, const double* dm, int64_t v, int64_t b0,
+                                                  int64_t nB, double* T) {
+    const int64_t K = nB * v;
+    const int64_t row = t / K, col = t % K;
+    const int64_t a = row / v, y = row % v, b = b0 + col / v, w = col % v;
+    T[t] = a <= b ? pm_density(dp, dm, v, b0, a, b, y, w) : 0.0;
 }
 
 #define PM_GRID_STRIDE(total) \
@@ -224,9 +247,9 @@ __host__ __device__ inline void pm_stage_pair(const double* M, int64_t v, int64_
     }
 }
 
-// Source matrix of packed row r.  mode 0 (amplitudes): r = P(i,j) / Q(i,j) of an
-// o x o pair index, source i o + j.  mode 1 (g tile of batch [a0, a0+nA)):
-// r = rowp / rowm(a', b), source a'(v - a0) + b - a0.
+// Source matrix of packed row r.  mode 0 (amplitudes) and mode 2 (adjoint weights):
+// r = P(i,j) / Q(i,j) of an o x o pair index, source i o + j.  mode 1 (g tile of
+// batch [a0, a0+nA)): r = rowp / rowm(a', b), source a'(v - a0) + b - a0.
 struct PmRows {
     int mode;
     int64_t o;       // mode 0
@@ -234,7 +257,7 @@ struct PmRows {
 };
 __host__ __device__ inline int64_t pm_src_row(const PmRows& rw, int64_t v, int64_t r, bool plus) {
     int64_t i, j;
-    if (rw.mode == 0) {
+    if (rw.mode != 1) {
         if (plus) pm_unP(r, i, j); else pm_unQ(r, i, j);
         return i * rw.o + j;
     }
@@ -250,59 +273,19 @@ __host__ __device__ inline int64_t pm_src_row(const PmRows& rw, int64_t v, int64
 }
 
 // Packed row r, tile pair (c0, d0), from the staged A, B:
-//   plus:  out[P(c,d)] = off (M_cd + M_dc) for c < d, M_cc for c = d,
-//   minus: out[Q(c,d)] = off (M_cd - M_dc),
-// off = 1/2 for amplitudes (mode 0), 1 for g (mode 1, the w_cc = 1/2 folded in).
+//   plus:  out[P(c,d)] = off (M_cd + M_dc) for c < d, dg M_cc for c = d,
+//   minus: out[Q(c,d)] = off (M_cd - M_dc).
+// Amplitudes (mode 0): off = 1/2, dg = 1.  g (mode 1): off = 1, dg = 1 (the w_cc = 1/2
+// folded in).  Adjoint weights (mode 2): plus off = 1/2 (i = j) or 1, dg = 2 off; minus off = 1.
 __host__ __device__ inline void pm_pack_sym_tile(const PmTile& A, const PmTile& B, int64_t v, int64_t c0, int64_t d0,
-                                                 bool plus, double off, double* o, int tid, int nth) {
+                                                 bool plus, double off, double dg, double* o, int tid, int nth) {
     for (int e = tid; e < PM_T * PM_T; e += nth) {
         const int q = e / PM_T, rr = e % PM_T;  // d offset, c offset (c is contiguous in the packed index)
         const int64_t c = c0 + rr, d = d0 + q;
         if (c >= v || d >= v || (plus ? c > d : c >= d)) continue;
         const double mcd = A[rr][q], mdc = B[q][rr];
-        if (plus) o[pm_P(c, d)] = c == d ? mcd : off * (mcd + mdc);
+        if (plus) o[pm_P(c, d)] = c == d ? dg * mcd : off * (mcd + mdc);
         else o[pm_Q(c, d)] = off * (mcd - mdc);
-    }
-}
-
-// w row (i,j), full (a,b): wp = (2 - delta_ij)(M + M^T)/2, wm = M - M^T.
-__host__ __device__ inline void pm_pack_w_tile(const PmTile& A, const PmTile& B, int64_t v, int64_t c0, int64_t d0,
-                                               bool plus, bool diag_ij, double* ow, int tid, int nth) {
-    const double f = plus && diag_ij ? 0.5 : 1.0, sg = plus ? 1.0 : -1.0;
-    const bool same = c0 == d0;
-    for (int e = tid; e < PM_T * PM_T; e += nth) {
-        const int rr = e / PM_T, q = e % PM_T;  // row offset, contiguous column offset
-        if (c0 + rr < v && d0 + q < v) ow[(c0 + rr) * v + d0 + q] = f * (A[rr][q] + sg * B[q][rr]);
-        if (!same && d0 + rr < v && c0 + q < v) ow[(d0 + rr) * v + c0 + q] = f * (B[rr][q] + sg * A[q][rr]);
-    }
-}
-
-// D tile: stage packed row (a', b): Pp[q][rr] = dp[P(c,d)], Pm[q][rr] = dm[Q(c,d)]
-// for (c, d) = (c0 + rr, d0 + q), c <= d (zero elsewhere).
-__host__ __device__ inline void pm_stage_D(const double* prow, const double* mrow, int64_t v, int64_t c0, int64_t d0,
-                                           PmTile& Pp, PmTile& Pm, int tid, int nth) {
-    for (int e = tid; e < PM_T * PM_T; e += nth) {
-        const int q = e / PM_T, rr = e % PM_T;
-        const int64_t c = c0 + rr, d = d0 + q;
-        const bool in = c < v && d < v && c <= d;
-        Pp[q][rr] = in ? prow[pm_P(c, d)] : 0.0;
-        Pm[q][rr] = (in && c < d) ? mrow[pm_Q(c, d)] : 0.0;
-    }
-}
-// D_{ab,cd} = dp + s_cd dm written at D[((a' v + c) v + b) v + d] for the tile pair.
-__host__ __device__ inline void pm_unpack_D_tile(const PmTile& Pp, const PmTile& Pm, int64_t v, int64_t ap, int64_t b,
-                                                 int64_t c0, int64_t d0, double* D, int tid, int nth) {
-    const bool same = c0 == d0;
-    for (int e = tid; e < PM_T * PM_T; e += nth) {
-        const int rr = e / PM_T, q = e % PM_T;  // output row offset, contiguous column offset
-        {   // (c, d) = (c0 + rr, d0 + q), c <= d
-            const int64_t c = c0 + rr, d = d0 + q;
-            if (c < v && d < v && (!same || rr <= q)) D[((ap * v + c) * v + b) * v + d] = Pp[q][rr] + Pm[q][rr];
-        }
-        {   // (d, c) = (d0 + rr, c0 + q), d > c: D_{ab,dc} = dp - dm
-            const int64_t d = d0 + rr, c = c0 + q;
-            if (c < v && d < v && (!same || q < rr)) D[((ap * v + d) * v + b) * v + c] = Pp[rr][q] - Pm[rr][q];
-        }
     }
 }
 
@@ -324,30 +307,73 @@ __host__ __device__ inline void pm_pack_sym_block(const double* src, int64_t v, 
     const int64_t c0 = cb * PM_T, d0 = db * PM_T;
     pm_stage_pair(src + pm_src_row(rw, v, r, plus) * v * v, v, c0, d0, A, B, tid, nth);
     sync();
-    pm_pack_sym_tile(A, B, v, c0, d0, plus, rw.mode == 0 ? 0.5 : 1.0, out + r * (plus ? pm_P2(v) : pm_Q2(v)), tid, nth);
+    double off = rw.mode == 0 ? 0.5 : 1.0, dg = 1.0;
+    if (rw.mode == 2) {
+        int64_t i = 0, j = 0;
+        if (plus) pm_unP(r, i, j);
+        off = (plus && i == j) ? 0.5 : 1.0;
+        dg = 2.0 * off;
+    }
+    pm_pack_sym_tile(A, B, v, c0, d0, plus, off, dg, out + r * (plus ? pm_P2(v) : pm_Q2(v)), tid, nth);
 }
-// w row r = P(i,j) (plus) or Q(i,j) (minus), tile pair tpair.
+
+// Tiles (alpha) and (beta) of a batch [b0, b0+nB): block row `row` = (b - b0)(b0 + nB) + a
+// for a < b0 + nB, tile pair tpair of (c, d).  The packed row (a, b) is staged when the
+// pair contributes (alpha: a < b, beta: a <= b); otherwise zeros are written.
 template <class Sync>
-__host__ __device__ inline void pm_pack_w_block(const double* src, int64_t o, int64_t v, int64_t r, int64_t tpair, bool plus,
-                                                double* out, PmTile& A, PmTile& B, int tid, int nth, Sync sync) {
-    int64_t cb, db, i, j;
-    pm_unP(tpair, cb, db);
-    if (plus) pm_unP(r, i, j); else pm_unQ(r, i, j);
-    const int64_t c0 = cb * PM_T, d0 = db * PM_T;
-    pm_stage_pair(src + (i * o + j) * v * v, v, c0, d0, A, B, tid, nth);
-    sync();
-    pm_pack_w_tile(A, B, v, c0, d0, plus, i == j, out + r * v * v, tid, nth);
-}
-// D rows of packed row (a', b) = row, tile pair tpair.
-template <class Sync>
-__host__ __device__ inline void pm_unpack_D_block(const double* dp, const double* dm, int64_t v, int64_t row, int64_t tpair,
-                                                  double* D, PmTile& Pp, PmTile& Pm, int tid, int nth, Sync sync) {
+__host__ __device__ inline void pm_tile_ab_block(const double* dp, const double* dm, int64_t v, int64_t b0, int64_t nB,
+                                                 int64_t row, int64_t tpair, bool alpha, double* T, PmTile& Pp,
+                                                 PmTile& Pm, int tid, int nth, Sync sync) {
     int64_t cb, db;
     pm_unP(tpair, cb, db);
-    const int64_t c0 = cb * PM_T, d0 = db * PM_T;
-    pm_stage_D(dp + row * pm_P2(v), dm + row * pm_Q2(v), v, c0, d0, Pp, Pm, tid, nth);
+    const int64_t c0 = cb * PM_T, d0 = db * PM_T, A = b0 + nB;
+    const int64_t bl = row / A, a = row % A, b = b0 + bl;
+    const bool live = alpha ? a < b : a <= b;
+    if (live) {
+        const double* prow = dp + (pm_P(a, b) - pm_P2(b0)) * pm_P2(v);
+        const double* mrow = a < b ? dm + (pm_Q(a, b) - pm_Q2(b0)) * pm_Q2(v) : nullptr;
+        for (int e = tid; e < PM_T * PM_T; e += nth) {  // Pp[q][rr] = dp[P(x, y')], x = c0 + rr <= y' = d0 + q
+            const int q = e / PM_T, rr = e % PM_T;
+            const int64_t x = c0 + rr, yy = d0 + q;
+            const bool in = x < v && yy < v && x <= yy;
+            Pp[q][rr] = in ? prow[pm_P(x, yy)] : 0.0;
+            Pm[q][rr] = (in && x < yy && mrow) ? mrow[pm_Q(x, yy)] : 0.0;
+        }
+    }
     sync();
-    pm_unpack_D_tile(Pp, Pm, v, row / v, row % v, c0, d0, D, tid, nth);
+    const bool same = c0 == d0;
+    // D_{ab, x y'} = Pp + Pm and D_{ab, y' x} = Pp - Pm for x = c0 + rr <= y' = d0 + q
+    if (alpha) {  // T[(bl v + y)][a v + w] = D_{ab, w y}; K = (b0 + nB) v
+        const int64_t K = A * v;
+        double* base = T + bl * v * K + a * v;
+        for (int e = tid; e < PM_T * PM_T; e += nth) {
+            {   // (w, y) = (x, y'): row y', column x (x contiguous)
+                const int q = e / PM_T, rr = e % PM_T;
+                const int64_t x = c0 + rr, yy = d0 + q;
+                if (x < v && yy < v && (!same || rr <= q)) base[yy * K + x] = live ? Pp[q][rr] + Pm[q][rr] : 0.0;
+            }
+            {   // (w, y) = (y', x), y' > x: row x, column y' (y' contiguous)
+                const int rr = e / PM_T, q = e % PM_T;
+                const int64_t x = c0 + rr, yy = d0 + q;
+                if (x < v && yy < v && (!same || q > rr)) base[x * K + yy] = live ? Pp[q][rr] - Pm[q][rr] : 0.0;
+            }
+        }
+    } else {  // T[(a v + y)][bl v + w] = D_{ab, y w}; K = nB v
+        const int64_t K = nB * v;
+        double* base = T + a * v * K + bl * v;
+        for (int e = tid; e < PM_T * PM_T; e += nth) {
+            {   // (y, w) = (x, y'): row x, column y' (y' contiguous)
+                const int rr = e / PM_T, q = e % PM_T;
+                const int64_t x = c0 + rr, yy = d0 + q;
+                if (x < v && yy < v && (!same || rr <= q)) base[x * K + yy] = live ? Pp[q][rr] + Pm[q][rr] : 0.0;
+            }
+            {   // (y, w) = (y', x), y' > x: row y', column x (x contiguous)
+                const int q = e / PM_T, rr = e % PM_T;
+                const int64_t x = c0 + rr, yy = d0 + q;
+                if (x < v && yy < v && (!same || q > rr)) base[yy * K + x] = live ? Pp[q][rr] - Pm[q][rr] : 0.0;
+            }
+        }
+    }
 }
 
 // Launch shape of the tiled kernels: grid.x = tile pairs, rows over (y, z); the
@@ -362,20 +388,13 @@ __global__ __launch_bounds__(256) void pm_pack_sym_tiled_kernel(const double* __
     pm_pack_sym_block(src, v, rw, r, blockIdx.x, plus != 0, out, A, B, threadIdx.x, blockDim.x, PmBarrier{});
 }
 
-__global__ __launch_bounds__(256) void pm_pack_w_tiled_kernel(const double* __restrict__ src, int64_t o, int64_t v,
-                                                               int64_t nrows, int plus, double* __restrict__ out) {
-    __shared__ PmTile A, B;
-    const int64_t r = pm_block_row();
-    if (r >= nrows) return;
-    pm_pack_w_block(src, o, v, r, blockIdx.x, plus != 0, out, A, B, threadIdx.x, blockDim.x, PmBarrier{});
-}
-
-__global__ __launch_bounds__(256) void pm_unpack_D_tiled_kernel(const double* __restrict__ dp, const double* __restrict__ dm,
-                                                                 int64_t v, int64_t nrows, double* __restrict__ D) {
+__global__ __launch_bounds__(256) void pm_tile_ab_kernel(const double* __restrict__ dp, const double* __restrict__ dm,
+                                                          int64_t v, int64_t b0, int64_t nB, int alpha,
+                                                          double* __restrict__ T) {
     __shared__ PmTile Pp, Pm;
     const int64_t row = pm_block_row();
-    if (row >= nrows) return;
-    pm_unpack_D_block(dp, dm, v, row, blockIdx.x, D, Pp, Pm, threadIdx.x, blockDim.x, PmBarrier{});
+    if (row >= nB * (b0 + nB)) return;
+    pm_tile_ab_block(dp, dm, v, b0, nB, row, blockIdx.x, alpha != 0, T, Pp, Pm, threadIdx.x, blockDim.x, PmBarrier{});
 }
 
 }  // namespace ladder

@@ -69,18 +69,15 @@ int check(int64_t o, int64_t v, int64_t n, int64_t nA, unsigned long long seed) 
     for (int64_t t = 0; t < pm_w_count(o, v); ++t) pm_pack_w_elem(t, tb.data(), o, v, wp.data(), wm.data());
     int bad = 0;
     {
-        std::vector<double> tp2(tp.size(), NAN), tm2(tm.size(), NAN), wp2(wp.size(), NAN), wm2(wm.size(), NAN);
+        std::vector<double> tp2(tp.size(), NAN), tm2(tm.size(), NAN);
         const PmRows rw{0, o, 0, 0};
         run_tiled(v, pm_P2(o), [&](int64_t r, int64_t t, PmTile& A, PmTile& B) {
             pm_pack_sym_block(tau.data(), v, rw, r, t, true, tp2.data(), A, B, 0, 1, PmNoBarrier{});
-            pm_pack_w_block(tb.data(), o, v, r, t, true, wp2.data(), A, B, 0, 1, PmNoBarrier{});
         });
         run_tiled(v, pm_Q2(o), [&](int64_t r, int64_t t, PmTile& A, PmTile& B) {
             pm_pack_sym_block(tau.data(), v, rw, r, t, false, tm2.data(), A, B, 0, 1, PmNoBarrier{});
-            pm_pack_w_block(tb.data(), o, v, r, t, false, wm2.data(), A, B, 0, 1, PmNoBarrier{});
         });
         bad |= same(tp2, tp, pm_P2(o) * pm_P2(v), "tau+") | same(tm2, tm, pm_Q2(o) * pm_Q2(v), "tau-");
-        bad |= same(wp2, wp, pm_P2(o) * v * v, "w+") | same(wm2, wm, pm_Q2(o) * v * v, "w-");
     }
     std::vector<double> R(o * o * v * v, NAN);
     double worstR = 0, worstD = 0, E = 0, Eref = 0;
@@ -124,46 +121,92 @@ int check(int64_t o, int64_t v, int64_t n, int64_t nA, unsigned long long seed) 
                 double e;
                 if (pm_unpack_R_elem(t, rp.data(), rm.data(), o, v, a0, nb, 0.0, tb.data(), R.data(), pass, &e)) E += e;
             }
-        // density tiles
-        std::vector<double> dp(nb * v * pm_P2(v)), dm(nb * v * pm_Q2(v) + 1), D(nb * v * v * v);
-        for (int64_t row = 0; row < nb * v; ++row) {
-            for (int64_t k = 0; k < pm_P2(v); ++k) {
-                double s = 0;
-                for (int64_t p = 0; p < pm_P2(o); ++p) s += wp[p * v * v + a0 * v + row] * tp[p * pm_P2(v) + k];
-                dp[row * pm_P2(v) + k] = s;
-            }
-            for (int64_t k = 0; k < pm_Q2(v); ++k) {
-                double s = 0;
-                for (int64_t q = 0; q < pm_Q2(o); ++q) s += wm[q * v * v + a0 * v + row] * tm[q * pm_Q2(v) + k];
-                dm[row * pm_Q2(v) + k] = s;
-            }
-        }
-        for (int64_t t = 0; t < nb * v * v * v; ++t) pm_unpack_D_elem(t, dp.data(), dm.data(), v, D.data());
-        {
-            std::vector<double> D2(D.size(), NAN);
-            run_tiled(v, nb * v, [&](int64_t r, int64_t t, PmTile& A, PmTile& B) {
-                pm_unpack_D_block(dp.data(), dm.data(), v, r, t, D2.data(), A, B, 0, 1, PmNoBarrier{});
-            });
-            bad |= same(D2, D, nb * v * v * v, "D");
-        }
-        for (int64_t ap = 0; ap < nb; ++ap)
-            for (int64_t c = 0; c < v; ++c)
-                for (int64_t b = 0; b < v; ++b)
-                    for (int64_t d = 0; d < v; ++d) {
-                        double s = 0;
-                        for (int64_t ij = 0; ij < o * o; ++ij)
-                            s += tb[ij * v * v + (a0 + ap) * v + b] * tau[ij * v * v + c * v + d];
-                        worstD = fmax(worstD, fabs(D[((ap * v + c) * v + b) * v + d] - s));
-                    }
     }
     for (int64_t k = 0; k < o * o * v * v; ++k) {
         if (isnan(R[k])) { printf("R element %lld never written\n", (long long)k); return 1; }
         worstR = fmax(worstR, fabs(R[k] - Rref[k]));
         Eref += tb[k] * Rref[k];
     }
-    printf("o=%lld v=%lld n=%lld nA=%lld  max|dR| %.3e  max|dD| %.3e  |dE| %.3e\n", (long long)o, (long long)v, (long long)n,
-           (long long)nA, worstR, worstD, fabs(E - Eref));
-    return (!bad && worstR < 1e-12 && worstD < 1e-12 && fabs(E - Eref) < 1e-11) ? 0 : 1;
+    // adjoint with packed density rows: Wp/Wm packed on (a<=b) by the mode-2 tiles, D+/D- per
+    // batch of b, tiles (alpha) and (beta), and X assembled from both against the dense X
+    double worstX = 0;
+    {
+        std::vector<double> wpp(pm_P2(o) * pm_P2(v), NAN), wmm(pm_Q2(o) * pm_Q2(v) + 1, NAN);
+        const PmRows rw{2, o, 0, 0};
+        run_tiled(v, pm_P2(o), [&](int64_t r, int64_t t, PmTile& A, PmTile& B) {
+            pm_pack_sym_block(tb.data(), v, rw, r, t, true, wpp.data(), A, B, 0, 1, PmNoBarrier{});
+        });
+        run_tiled(v, pm_Q2(o), [&](int64_t r, int64_t t, PmTile& A, PmTile& B) {
+            pm_pack_sym_block(tb.data(), v, rw, r, t, false, wmm.data(), A, B, 0, 1, PmNoBarrier{});
+        });
+        for (int64_t p = 0; p < pm_P2(o); ++p)  // Wp[P(i,j)][P(a,b)] = wp[P(i,j)][(a,b)]
+            for (int64_t b = 0; b < v; ++b)
+                for (int64_t a = 0; a <= b; ++a)
+                    if (!(wpp[p * pm_P2(v) + pm_P(a, b)] == wp[p * v * v + a * v + b])) { printf("Wp differs\n"); bad = 1; }
+        for (int64_t q = 0; q < pm_Q2(o); ++q)
+            for (int64_t b = 0; b < v; ++b)
+                for (int64_t a = 0; a < b; ++a)
+                    if (!(wmm[q * pm_Q2(v) + pm_Q(a, b)] == wm[q * v * v + a * v + b])) { printf("Wm differs\n"); bad = 1; }
+        std::vector<double> X(v * v * n, 0.0), Xref(v * v * n, 0.0);
+        for (int64_t a = 0; a < v; ++a)
+            for (int64_t c = 0; c < v; ++c)
+                for (int64_t b = 0; b < v; ++b)
+                    for (int64_t d = 0; d < v; ++d) {
+                        double s = 0;
+                        for (int64_t ij = 0; ij < o * o; ++ij) s += tb[ij * v * v + a * v + b] * tau[ij * v * v + c * v + d];
+                        for (int64_t J = 0; J < n; ++J) Xref[(a * v + c) * n + J] += 2.0 * s * L[(b * v + d) * n + J];
+                    }
+        for (int64_t b0 = 0; b0 < v; b0 += nA) {
+            const int64_t nB = nA < v - b0 ? nA : v - b0, A = b0 + nB;
+            const int64_t rp = pm_P2(A) - pm_P2(b0), rm = pm_Q2(A) - pm_Q2(b0);
+            std::vector<double> dp(rp * pm_P2(v)), dm(rm * pm_Q2(v) + 1);
+            for (int64_t r = 0; r < rp; ++r)
+                for (int64_t k = 0; k < pm_P2(v); ++k) {
+                    double s = 0;
+                    for (int64_t p = 0; p < pm_P2(o); ++p) s += wpp[p * pm_P2(v) + pm_P2(b0) + r] * tp[p * pm_P2(v) + k];
+                    dp[r * pm_P2(v) + k] = s;
+                }
+            for (int64_t r = 0; r < rm; ++r)
+                for (int64_t k = 0; k < pm_Q2(v); ++k) {
+                    double s = 0;
+                    for (int64_t q = 0; q < pm_Q2(o); ++q) s += wmm[q * pm_Q2(v) + pm_Q2(b0) + r] * tm[q * pm_Q2(v) + k];
+                    dm[r * pm_Q2(v) + k] = s;
+                }
+            for (int64_t b = b0; b < A; ++b)  // the packed rows against the dense density
+                for (int64_t a = 0; a <= b; ++a)
+                    for (int64_t c = 0; c < v; ++c)
+                        for (int64_t d = 0; d < v; ++d) {
+                            double sd = 0;
+                            for (int64_t ij = 0; ij < o * o; ++ij) sd += tb[ij * v * v + a * v + b] * tau[ij * v * v + c * v + d];
+                            worstD = fmax(worstD, fabs(pm_density(dp.data(), dm.data(), v, b0, a, b, c, d) - sd));
+                        }
+            for (int pass = 0; pass < 2; ++pass) {  // 0: alpha, 1: beta
+                const bool alpha = pass == 0;
+                const int64_t rows = alpha ? nB * v : A * v, K = alpha ? A * v : nB * v;
+                std::vector<double> T(rows * K, NAN), T2(rows * K, NAN);
+                for (int64_t t = 0; t < rows * K; ++t) {
+                    if (alpha) pm_tile_alpha_elem(t, dp.data(), dm.data(), v, b0, nB, T.data());
+                    else pm_tile_beta_elem(t, dp.data(), dm.data(), v, b0, nB, T.data());
+                }
+                run_tiled(v, nB * A, [&](int64_t r, int64_t t, PmTile& Pa, PmTile& Pb) {
+                    pm_tile_ab_block(dp.data(), dm.data(), v, b0, nB, r, t, alpha, T2.data(), Pa, Pb, 0, 1, PmNoBarrier{});
+                });
+                bad |= same(T2, T, rows * K, alpha ? "tile alpha" : "tile beta");
+                // X rows: alpha (b, y) += T[(b-b0, y)][(a, w)] L[(a, w)];  beta (a, y) += T[(a, y)][(b-b0, w)] L[(b, w)]
+                const int64_t row0 = alpha ? b0 * v : 0, k0 = alpha ? 0 : b0 * v;
+                for (int64_t r = 0; r < rows; ++r)
+                    for (int64_t k = 0; k < K; ++k) {
+                        const double tv = T[r * K + k];
+                        if (tv == 0.0) continue;
+                        for (int64_t J = 0; J < n; ++J) X[(row0 + r) * n + J] += 2.0 * tv * L[(k0 + k) * n + J];
+                    }
+            }
+        }
+        for (int64_t k = 0; k < v * v * n; ++k) worstX = fmax(worstX, fabs(X[k] - Xref[k]));
+    }
+    printf("o=%lld v=%lld n=%lld nA=%lld  max|dR| %.3e  max|dD| %.3e  |dE| %.3e  max|dX| %.3e\n", (long long)o, (long long)v,
+           (long long)n, (long long)nA, worstR, worstD, fabs(E - Eref), worstX);
+    return (!bad && worstR < 1e-12 && worstD < 1e-12 && fabs(E - Eref) < 1e-11 && worstX < 1e-11) ? 0 : 1;
 }
 
 int main() {

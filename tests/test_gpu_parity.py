@@ -615,3 +615,27 @@ def test_autotune_then_default_calls_use_it(dev, tmp_path, precision):
     P.autotune_reset()
     assert P.autotune_load(str(cache)) == 1
     P.autotune_reset()
+
+
+def test_batched_after_retune_uses_new_sizes_and_stays_correct(dev):
+    """A tuned batch size for one instance shape changes that instance's plan inside the
+    ragged batch (the graph is recaptured, not replayed) and the results stay right."""
+    shapes = [(3, 14, 20), (2, 21, 13), (4, 9, 30)]
+    insts, refs = _instances(dev, shapes, 420)
+    P.autotune_reset()
+    ws0 = P.batched_workspace_size(insts)
+    P.batched(insts, P.DO_FORWARD | P.DO_ADJOINT)
+    d = insts[1]
+    ws = torch.empty(P.workspace_size(d["o"], d["v"], d["n"], P.Options(n_abatch=6)), dtype=torch.uint8, device=dev)
+    nA = P.autotune(d["L"], d["tau"], d["tbar"], o=d["o"], v=d["v"], n=d["n"], ws=ws)
+    assert 1 <= nA <= 6
+    P.batched(insts, P.DO_FORWARD | P.DO_ADJOINT)
+    torch.cuda.synchronize()
+    for dd, (L, tau, w) in zip(insts, refs):
+        o, v, n = dd["o"], dd["v"], dd["n"]
+        Rr, Er = oracle.forward(o, v, n, L, tau, w)
+        Xr = oracle.adjoint(o, v, n, L, tau, w)
+        assert err_norm(dd["R"].cpu().numpy(), Rr) <= TOL and err_norm(dd["X"].cpu().numpy(), Xr) <= TOL
+        assert err_rel(float(dd["E"]), Er) <= TOL
+    P.autotune_reset()
+    assert P.batched_workspace_size(insts) == ws0
