@@ -56,11 +56,12 @@ def tuned_batch(path, o, v, n, precision, slices, flags):
 
 
 def gemm_source_hash():
-    """First 16 hex digits of the SHA-256 of the GEMM kernel sources (the code the
-    stored HBM-traffic counters were taken on)."""
+    """First 16 hex digits of the SHA-256 of the library sources (kernels and the host
+    code that shapes their launches: the code the stored HBM-traffic counters were
+    taken on)."""
     import hashlib
     h = hashlib.sha256()
-    for f in ("split_bf16.hpp", "gemm_f64.hpp"):
+    for f in ("split_bf16.hpp", "gemm_f64.hpp", "pm_pack.hpp", "ladder.hip"):
         with open(os.path.join(ROOT, "paper_2202_02019_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
