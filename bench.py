@@ -145,9 +145,10 @@ def main():
         args.n_abatch = 8 if args.precision == "split" else 16  # a few large virtual batches fit in 288 GB
         nA_source = "fixed fallback"
     big = nominal_flops(o, v, n) > 1e14
-    huge = nominal_flops(o, v, n) > 1e15  # a single step takes minutes: no warm-up by default
+    # a step at retinal scale takes about half a minute: one untimed warm-up step (code objects,
+    # clocks and the fresh workspace settle), then one timed step
     steps = args.steps if args.steps is not None else (1 if big else 10)
-    warmup = args.warmup if args.warmup is not None else (0 if huge else (1 if big else 2))
+    warmup = args.warmup if args.warmup is not None else (1 if big else 2)
 
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
