@@ -31,6 +31,10 @@
  *                                                 the transposed ladder: the A2-term part
  *                                                 of the multiplier equations tbar A = -eta
  *                                                 (Sec. II A), E being linear in tau.
+ *   Wab^K_ab = sum_ci d_abci Z^K_ci,  Wci^K_ci = sum_ab d_abci Z^K_ab,
+ *   d_abci   = sum_j L_ji^ac R_j^b              the excited-state OV^3 density block
+ *                                                 (Appendix A) and its contributions to W
+ *                                                 (Sec. II B)
  *
  * The adjoint is written in its general form: it does NOT assume the pair
  * symmetry tau_ij^ab = tau_ji^ba (Appendix A, d_pqrs = d_rspq), so a GPU path that
@@ -41,6 +45,8 @@
  *   tau  [o][o][v][v] tau[((i*o+j)*v+c)*v+d] = tau_ij^cd  (also tbar, w, R)
  *   X    [v][v][n]   like L
  *   Lov  [o][v][n]   Lov[(i*v+a)*n+J]      = L^J_ia   (occupied-virtual block)
+ *   Zvo  [v][o][n]   Zvo[(c*o+i)*n+K]      = Z^K_ci   (virtual-occupied block, also Wci)
+ *   R1   [o][v]      R1[j*v+b]             = R_j^b    (excited-state singles)
  *   eps  [o+v]       occupied orbital energies first, then virtual
  *
  * Every function returns 0 on success and -1 on a bad argument.
@@ -478,5 +484,82 @@ int oracle_amplitude_update(int64_t o, int64_t v, const double* eps, const doubl
                     const double den = (eps[i] + eps[j]) - (eps[o + a] + eps[o + b]);
                     t[k] = t[k] + R[k] / den;
                 }
+    return 0;
+}
+
+/*
+ * Excited-state OV^3 density block (Appendix A, excited-state densities):
+ *   d_abci = sum_j L_ji^ac R_j^b
+ * and its two contributions to the three-index intermediate
+ * W^K_pq = sum_rs d_pqrs Z^K_rs (Sec. II A), over the integrals (ab|ci) of this
+ * block (Sec. II B, contributions of the OV^3 densities):
+ *   Wab^K_ab = sum_ci d_abci Z^K_ci           (the ab side)
+ *   Wci^K_ci = sum_ab d_abci Z^K_ab           (the ci side)
+ * Each density element is formed on its own (o products) and then contracted;
+ * the factored route of Sec. II B through X_aj^K and P_aj^K is deliberately not
+ * taken, so that it can be checked against this one.
+ * Layouts: L2 [o][o][v][v] with L2[((j*o+i)*v+a)*v+c] = L_ji^ac; R1 [o][v] with
+ * R1[j*v+b] = R_j^b; Zvv and Wab [v][v][n]; Zvo and Wci [v][o][n] with
+ * Zvo[(c*o+i)*n+K] = Z^K_ci.  The functions fill out[k][n] for the k index pairs
+ * given (ab[2t], ab[2t+1]) = (a, b), or (ci[2t], ci[2t+1]) = (c, i).
+ */
+static double dens_abci(int64_t o, int64_t v, const double* L2, const double* R1, int64_t a, int64_t b,
+                        int64_t c, int64_t i) {
+    double d = 0.0;
+    for (int64_t j = 0; j < o; ++j) d += L2[((j * o + i) * v + a) * v + c] * R1[j * v + b];
+    return d;
+}
+
+int oracle_ov3_abci_wab(int64_t o, int64_t v, int64_t n, const double* L2, const double* R1, const double* Zvo,
+                        int64_t k, const int64_t* ab, double* out) {
+    if (bad_dims(o, v, n) || !L2 || !R1 || !Zvo || !out || k < 0 || (k > 0 && !ab)) return -1;
+    for (int64_t t = 0; t < k; ++t)
+        if (ab[2 * t] < 0 || ab[2 * t] >= v || ab[2 * t + 1] < 0 || ab[2 * t + 1] >= v) return -1;
+#pragma omp parallel for schedule(dynamic, 1)
+    for (int64_t t = 0; t < k; ++t) {
+        const int64_t a = ab[2 * t], b = ab[2 * t + 1];
+        double* w = out + t * n;
+        for (int64_t K = 0; K < n; ++K) w[K] = 0.0;
+        for (int64_t c = 0; c < v; ++c)
+            for (int64_t i = 0; i < o; ++i) {
+                const double d = dens_abci(o, v, L2, R1, a, b, c, i);
+                const double* z = Zvo + (c * o + i) * n;
+                for (int64_t K = 0; K < n; ++K) w[K] += d * z[K];
+            }
+    }
+    return 0;
+}
+
+int oracle_ov3_abci_wci(int64_t o, int64_t v, int64_t n, const double* L2, const double* R1, const double* Zvv,
+                        int64_t k, const int64_t* ci, double* out) {
+    if (bad_dims(o, v, n) || !L2 || !R1 || !Zvv || !out || k < 0 || (k > 0 && !ci)) return -1;
+    for (int64_t t = 0; t < k; ++t)
+        if (ci[2 * t] < 0 || ci[2 * t] >= v || ci[2 * t + 1] < 0 || ci[2 * t + 1] >= o) return -1;
+#pragma omp parallel for schedule(dynamic, 1)
+    for (int64_t t = 0; t < k; ++t) {
+        const int64_t c = ci[2 * t], i = ci[2 * t + 1];
+        double* w = out + t * n;
+        for (int64_t K = 0; K < n; ++K) w[K] = 0.0;
+        for (int64_t a = 0; a < v; ++a)
+            for (int64_t b = 0; b < v; ++b) {
+                const double d = dens_abci(o, v, L2, R1, a, b, c, i);
+                const double* z = Zvv + (a * v + b) * n;
+                for (int64_t K = 0; K < n; ++K) w[K] += d * z[K];
+            }
+    }
+    return 0;
+}
+
+/* V[M][N] = sum_p Z[p][M] W[p][N] over any number of index pairs p (for the
+ * occupied-virtual block of V_MN = Z^M_ab W^N_ab + Z^M_ci W^N_ci, Sec. II B). */
+int oracle_metric_contraction_pairs(int64_t pairs, int64_t n, const double* Z, const double* W, double* V) {
+    if (pairs < 1 || n < 1 || !Z || !W || !V) return -1;
+#pragma omp parallel for schedule(static)
+    for (int64_t M = 0; M < n; ++M)
+        for (int64_t N = 0; N < n; ++N) {
+            double s = 0.0;
+            for (int64_t p = 0; p < pairs; ++p) s += Z[p * n + M] * W[p * n + N];
+            V[M * n + N] = s;
+        }
     return 0;
 }

@@ -98,3 +98,21 @@ def back_transform(v, n, x, y, W, K_range=None):
     for K in range(K_lo, K_hi):
         out[:, :, K - K_lo] = x.T @ np.ascontiguousarray(W[:, :, K]) @ y
     return out
+
+
+def ov3_abci(o, v, n, L2, R1, Zvv, Zvo):
+    """Both W contributions of the excited-state OV^3 density d_abci = sum_j L_ji^ac R_j^b:
+    Wab^K_ab = sum_ci d_abci Z^K_ci and Wci^K_ci = sum_ab d_abci Z^K_ab, one density slice
+    d[a] = d_a[b, (c,i)] at a time (the density is formed, as in the C version)."""
+    L2 = np.ascontiguousarray(L2, dtype=np.float64).reshape(o, o, v, v)   # [j, i, a, c]
+    R1 = np.ascontiguousarray(R1, dtype=np.float64).reshape(o, v)         # [j, b]
+    Zvv = np.ascontiguousarray(Zvv, dtype=np.float64).reshape(v, v, n)    # [a, b, K]
+    Zvo = np.ascontiguousarray(Zvo, dtype=np.float64).reshape(v * o, n)   # [(c,i), K]
+    Wab = np.empty((v, v, n))
+    Wci = np.zeros((v * o, n))
+    for a in range(v):
+        M = np.ascontiguousarray(L2[:, :, a, :].transpose(0, 2, 1)).reshape(o, v * o)  # M[j, (c,i)] = L_ji^ac
+        d = R1.T @ M                                                                    # d[b, (c,i)] = d_abci
+        Wab[a] = d @ Zvo
+        Wci += d.T @ Zvv[a]
+    return Wab, Wci.reshape(v, o, n)

@@ -23,7 +23,8 @@ LIB = os.path.join(HERE, "liboracle.so")
 __all__ = [
     "build", "load", "forward", "adjoint", "forward_range", "adjoint_range", "R_sample",
     "X_sample", "tau_gradient", "tau_gradient_range", "w_intermediate", "w_intermediate_range",
-    "metric_contraction", "back_transform", "back_transform_range", "excited_amplitudes", "mp2_amplitudes", "amplitude_update", "make_inputs",
+    "metric_contraction", "metric_contraction_pairs", "back_transform", "back_transform_range",
+    "excited_amplitudes", "ov3_abci", "ov3_abci_wab", "ov3_abci_wci", "mp2_amplitudes", "amplitude_update", "make_inputs",
     "num_threads",
     "set_num_threads", "flops_forward", "flops_adjoint", "matrix",
 ]
@@ -58,6 +59,9 @@ def load():
         lib.oracle_metric_contraction.argtypes = [i64, i64, dp, dp, dp]
         lib.oracle_excited_amplitudes.argtypes = [i64, i64, ctypes.c_double, dp, dp, ctypes.c_int, dp]
         lib.oracle_back_transform_range.argtypes = [i64, i64, dp, dp, dp, i64, i64, dp]
+        lib.oracle_ov3_abci_wab.argtypes = [i64, i64, i64, dp, dp, dp, i64, vp, dp]
+        lib.oracle_ov3_abci_wci.argtypes = [i64, i64, i64, dp, dp, dp, i64, vp, dp]
+        lib.oracle_metric_contraction_pairs.argtypes = [i64, i64, dp, dp, dp]
         lib.oracle_mp2_amplitudes.argtypes = [i64, i64, i64, dp, dp, dp]
         lib.oracle_amplitude_update.argtypes = [i64, i64, dp, dp, dp]
         lib.oracle_num_threads.restype = ctypes.c_int
@@ -65,6 +69,7 @@ def load():
         for f in ("oracle_ladder_forward_range", "oracle_ladder_adjoint_range", "oracle_ladder_R_sample",
                   "oracle_ladder_X_sample", "oracle_ladder_tau_gradient_range", "oracle_w_intermediate_range",
                   "oracle_metric_contraction", "oracle_back_transform_range", "oracle_excited_amplitudes",
+                  "oracle_ov3_abci_wab", "oracle_ov3_abci_wci", "oracle_metric_contraction_pairs",
                   "oracle_mp2_amplitudes",
                   "oracle_amplitude_update"):
             getattr(lib, f).restype = ctypes.c_int
@@ -186,6 +191,48 @@ def excited_amplitudes(o, v, R0, T, R2, mode):
     if load().oracle_excited_amplitudes(o, v, float(R0), _p(T), _p(R2), int(mode), _p(U)) != 0:
         raise RuntimeError("oracle_excited_amplitudes failed")
     return U
+
+
+def metric_contraction_pairs(pairs, n, Z, W):
+    """V [n][n], V_MN = sum_p Z^M_p W^N_p over `pairs` index pairs (Z, W: [pairs][n])."""
+    Z = _f64(Z, (pairs, n)); W = _f64(W, (pairs, n))
+    V = np.zeros((n, n))
+    if load().oracle_metric_contraction_pairs(pairs, n, _p(Z), _p(W), _p(V)) != 0:
+        raise RuntimeError("oracle_metric_contraction_pairs failed")
+    return V
+
+
+def _pairs(idx):
+    idx = np.ascontiguousarray(idx, dtype=np.int64).reshape(-1, 2)
+    return idx, (idx.ctypes.data if idx.shape[0] else None)
+
+
+def ov3_abci_wab(o, v, n, L2, R1, Zvo, ab):
+    """Wab^K_ab = sum_ci d_abci Z^K_ci (d_abci = sum_j L_ji^ac R_j^b) for pairs ab (k x 2): [k][n]."""
+    L2 = _f64(L2, (o, o, v, v)); R1 = _f64(R1, (o, v)); Zvo = _f64(Zvo, (v, o, n))
+    ab, pab = _pairs(ab)
+    out = np.zeros((ab.shape[0], n))
+    if load().oracle_ov3_abci_wab(o, v, n, _p(L2), _p(R1), _p(Zvo), ab.shape[0], pab, _p(out)) != 0:
+        raise RuntimeError("oracle_ov3_abci_wab failed")
+    return out
+
+
+def ov3_abci_wci(o, v, n, L2, R1, Zvv, ci):
+    """Wci^K_ci = sum_ab d_abci Z^K_ab for pairs ci (k x 2, c virtual, i occupied): [k][n]."""
+    L2 = _f64(L2, (o, o, v, v)); R1 = _f64(R1, (o, v)); Zvv = _f64(Zvv, (v, v, n))
+    ci, pci = _pairs(ci)
+    out = np.zeros((ci.shape[0], n))
+    if load().oracle_ov3_abci_wci(o, v, n, _p(L2), _p(R1), _p(Zvv), ci.shape[0], pci, _p(out)) != 0:
+        raise RuntimeError("oracle_ov3_abci_wci failed")
+    return out
+
+
+def ov3_abci(o, v, n, L2, R1, Zvv, Zvo):
+    """(Wab [v][v][n], Wci [v][o][n]): both contributions of the OV^3 block d_abci, in full."""
+    ab = np.array([(a, b) for a in range(v) for b in range(v)], dtype=np.int64)
+    ci = np.array([(c, i) for c in range(v) for i in range(o)], dtype=np.int64)
+    return (ov3_abci_wab(o, v, n, L2, R1, Zvo, ab).reshape(v, v, n),
+            ov3_abci_wci(o, v, n, L2, R1, Zvv, ci).reshape(v, o, n))
 
 
 def R_sample(o, v, n, L, tau, ab):

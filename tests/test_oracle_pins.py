@@ -394,6 +394,104 @@ def test_excited_amplitudes(oracle_lib):
         np.testing.assert_allclose(U, U.transpose(1, 0, 3, 2), rtol=0, atol=1e-15)
 
 
+# ---------------------------------------------------------------- excited-state OV^3 density d_abci
+@pytest.fixture(params=["c", "matrix"])
+def ov3(request, oracle_lib):
+    """(Wab, Wci) of d_abci = sum_j L_ji^ac R_j^b from the C and the numpy oracle."""
+    import oracle
+    return oracle_lib.ov3_abci if request.param == "c" else oracle.matrix.ov3_abci
+
+
+def test_ov3_abci_unit_density(ov3):
+    """One multiplier element L_ji^ac = 1 and one singles element R_j'^b = 1: the density is
+    [j = j'] at (a, b, c, i) only, so Wab^K_ab = Z^K_ci and Wci^K_ci = Z^K_ab exactly,
+    and nothing else is touched; R_2 of another occupied index gives zero."""
+    o, v, n = 3, 4, 5
+    Zvv, Zvo = rnd(91, v, v, n), rnd(92, v, o, n)
+    for (j, i, a, c, b) in [(0, 2, 1, 3, 0), (2, 2, 0, 0, 3), (1, 0, 3, 2, 3)]:
+        L2 = np.zeros((o, o, v, v)); L2[j, i, a, c] = 1.0
+        R1 = np.zeros((o, v)); R1[j, b] = 1.0
+        Wab, Wci = ov3(o, v, n, L2, R1, Zvv, Zvo)
+        ref_ab = np.zeros((v, v, n)); ref_ab[a, b] = Zvo[c, i]
+        ref_ci = np.zeros((v, o, n)); ref_ci[c, i] = Zvv[a, b]
+        assert np.array_equal(Wab, ref_ab) and np.array_equal(Wci, ref_ci), (j, i, a, c, b)
+        R1 = np.zeros((o, v)); R1[(j + 1) % o, b] = 1.0
+        Wab, Wci = ov3(o, v, n, L2, R1, Zvv, Zvo)
+        assert not Wab.any() and not Wci.any()
+    # ground state: d^gs_abci = 0 (no singles excitation)
+    Wab, Wci = ov3(o, v, n, rnd(93, o, o, v, v), np.zeros((o, v)), Zvv, Zvo)
+    assert not Wab.any() and not Wci.any()
+
+
+def test_ov3_abci_table_chain(ov3):
+    """The factored route of Sec. II B and its table of intermediates,
+    X_aj^K = L_ji^ac Z_ci^K, Wab = R_j^b X_aj^K, P_aj^K = R_j^b Z_ab^K, Wci = L_ji^ac P_aj^K,
+    gives what the oracle gets by forming the density and contracting it."""
+    o, v, n = 4, 7, 6
+    L2, R1, Zvv, Zvo = rnd(94, o, o, v, v), rnd(95, o, v), rnd(96, v, v, n), rnd(97, v, o, n)
+    Wab, Wci = ov3(o, v, n, L2, R1, Zvv, Zvo)
+    X = np.einsum("jiac,ciK->ajK", L2, Zvo)
+    P = np.einsum("jb,abK->ajK", R1, Zvv)
+    np.testing.assert_allclose(Wab, np.einsum("jb,ajK->abK", R1, X), rtol=0, atol=1e-13 * np.abs(Wab).max())
+    np.testing.assert_allclose(Wci, np.einsum("jiac,ajK->ciK", L2, P), rtol=0, atol=1e-13 * np.abs(Wci).max())
+
+
+def test_ov3_abci_energy_and_gradient(ov3, oracle_lib):
+    """With Z = L (both blocks), sum L_ab W_ab and sum L_ci W_ci are the same number,
+    E' = sum_abci d_abci (ab|ci) (Sec. II A energy over this block); E' is bilinear in the two
+    Cholesky blocks, so central differences of E' computed from the ab side reproduce the ci
+    side W_ci = dE'/dL_ci to rounding; and V_MN = Z_ab^M W_ab^N + Z_ci^M W_ci^N has trace 2 E'."""
+    o, v, n = 3, 5, 4
+    L2, R1, Lvv, Lvo = rnd(98, o, o, v, v), rnd(99, o, v), rnd(100, v, v, n), rnd(101, v, o, n)
+    Wab, Wci = ov3(o, v, n, L2, R1, Lvv, Lvo)
+    Eab, Eci = np.sum(Lvv * Wab), np.sum(Lvo * Wci)
+    assert abs(Eab - Eci) <= 1e-13 * np.sum(np.abs(Lvv * Wab))
+
+    def energy(Lvo_):
+        W, _ = ov3(o, v, n, L2, R1, Lvv, Lvo_)
+        return np.sum(Lvv * W)
+
+    h = 0.5
+    for (c, i, K) in [(0, 0, 0), (4, 2, 3), (2, 1, 1)]:
+        e = np.zeros_like(Lvo); e[c, i, K] = h
+        fd = (energy(Lvo + e) - energy(Lvo - e)) / (2 * h)
+        assert abs(fd - Wci[c, i, K]) <= 1e-12 * np.abs(Wci).max(), (c, i, K)
+    V = (oracle_lib.metric_contraction(v, n, Lvv, Wab)
+         + oracle_lib.metric_contraction_pairs(v * o, n, Lvo.reshape(v * o, n), Wci.reshape(v * o, n)))
+    assert abs(np.trace(V) - 2 * Eab) <= 1e-13 * np.abs(V).sum()
+
+
+def test_ov3_abci_integer_exact(oracle_lib):
+    """Small integer inputs: every product and sum is exact in FP64, so the C and the
+    numpy oracle (different summation orders) agree bit for bit; both are bilinear."""
+    import oracle
+    o, v, n = 4, 9, 6
+    g = np.random.default_rng(102)
+    L2, R1 = g.integers(-3, 4, (o, o, v, v)).astype(float), g.integers(-3, 4, (o, v)).astype(float)
+    Zvv, Zvo = g.integers(-3, 4, (v, v, n)).astype(float), g.integers(-3, 4, (v, o, n)).astype(float)
+    a1, c1 = oracle_lib.ov3_abci(o, v, n, L2, R1, Zvv, Zvo)
+    a2, c2 = oracle.matrix.ov3_abci(o, v, n, L2, R1, Zvv, Zvo)
+    assert np.array_equal(a1, a2) and np.array_equal(c1, c2)
+    a3, c3 = oracle_lib.ov3_abci(o, v, n, 2 * L2, -R1, Zvv, Zvo)
+    assert np.array_equal(a3, -2 * a1) and np.array_equal(c3, -2 * c1)
+    ab = np.array([[8, 0], [3, 3]]); ci = np.array([[0, 3], [8, 1]])
+    assert np.array_equal(oracle_lib.ov3_abci_wab(o, v, n, L2, R1, Zvo, ab), a1[ab[:, 0], ab[:, 1]])
+    assert np.array_equal(oracle_lib.ov3_abci_wci(o, v, n, L2, R1, Zvv, ci), c1[ci[:, 0], ci[:, 1]])
+
+
+def test_metric_contraction_pairs(oracle_lib):
+    """Over v^2 pairs it is the virtual-virtual contraction; a rank-one Z, W gives one entry."""
+    v, n = 4, 3
+    Z, W = rnd(103, v, v, n), rnd(104, v, v, n)
+    assert np.array_equal(oracle_lib.metric_contraction_pairs(v * v, n, Z, W), oracle_lib.metric_contraction(v, n, Z, W))
+    P = 7
+    z, w = np.zeros((P, n)), np.zeros((P, n))
+    z[:, 1], w[:, 2] = rnd(105, P), rnd(106, P)
+    V = oracle_lib.metric_contraction_pairs(P, n, z, w)
+    ref = np.zeros((n, n)); ref[1, 2] = np.dot(z[:, 1], w[:, 2])
+    np.testing.assert_allclose(V, ref, rtol=0, atol=1e-15)
+
+
 # ---------------------------------------------------------------- ranges and samples
 def test_ranges_and_samples_agree_with_full(oracle_lib):
     o, v, n = 2, 7, 4
