@@ -109,8 +109,9 @@ def main():
     ap.add_argument("--dense", action="store_true",
                     help="dense contraction instead of the +/- packed one (LADDER_FLAG_DENSE)")
     ap.add_argument("--next-rows", action="store_true",
-                    help="also time the transposed ladder (dE/dtau), the metric contraction V and the MO "
-                         "back-transformation once on the same inputs, with sampled checks")
+                    help="also time the transposed ladder (dE/dtau), the metric contraction V, the MO "
+                         "back-transformation and the excited-state OV^3 block d_abci once on the same "
+                         "inputs, with sampled checks")
     ap.add_argument("--copy-probe", action="store_true",
                     help="run a 1 GiB device copy first (reference kernel for the HBM traffic counters)")
     args = ap.parse_args()
@@ -351,8 +352,34 @@ def main():
                                  "err_sample_K": float(np.abs(Wmo[:, :, K:K + 1].cpu().numpy() - Wr).max()
                                                        / np.abs(Wr).max())}
         del Wmo
-        print("bench: next rows: tau gradient %.1f s, V %.1f ms, back-transform %.1f ms"
-              % (mst / 1e3, msv, msb), file=sys.stderr, flush=True)
+        # excited-state OV^3 block d_abci = L_ji^ac R_j^b with L_2 := tbar, seeded singles R_1 and
+        # Z := (L, seeded Zvo); checks: sampled rows against the oracle and sum Zvv*Wab = sum Zvo*Wci
+        del ws
+        torch.cuda.empty_cache()
+        R1 = torch.randn((o, v), dtype=torch.float64, device=dev, generator=gen) * 0.1
+        Zvo = torch.randn((v, o, n), dtype=torch.float64, device=dev, generator=gen) / n ** 0.5
+        ws = torch.empty(P.ov3_abci_workspace_size(o, v, n), dtype=torch.uint8, device=dev)
+        Wab, Wci = torch.empty_like(X), torch.empty((v, o, n), dtype=torch.float64, device=dev)
+        torch.cuda.synchronize()
+        ev0.record(stream)
+        P.ov3_abci(tbar, R1, L, Zvo, o=o, v=v, n=n, Wab=Wab, Wci=Wci, ws=ws)
+        ev1.record(stream)
+        torch.cuda.synchronize()
+        mso = ev0.elapsed_time(ev1)
+        Fo = 4.0 * o * o * v * v * n + 4.0 * o * v * v * n
+        s_ab, s_ci = float((L * Wab).sum()), float((Zvo * Wci).sum())
+        th_, R1h, Zvoh = tbar.cpu().numpy(), R1.cpu().numpy(), Zvo.cpu().numpy()
+        ab, ci = np.array([[0, 0], [v - 1, v // 2]]), np.array([[v // 3, o - 1]])
+        ra = oracle.ov3_abci_wab(o, v, n, th_, R1h, Zvoh, ab)
+        rc = oracle.ov3_abci_wci(o, v, n, th_, R1h, L.cpu().numpy(), ci)
+        ea = float(np.abs(Wab[ab[:, 0], ab[:, 1]].cpu().numpy() - ra).max() / np.abs(ra).max())
+        ec = float(np.abs(Wci[ci[:, 0], ci[:, 1]].cpu().numpy() - rc).max() / np.abs(rc).max())
+        nxt["ov3_abci"] = {"ms": mso, "flops": Fo, "tflops": Fo / (mso * 1e-3) / 1e12,
+                           "err_sample_Wab": ea, "err_sample_Wci": ec,
+                           "identity_rel": abs(s_ab - s_ci) / float((L * Wab).abs().sum())}
+        del Wab, Wci, th_
+        print("bench: next rows: tau gradient %.1f s, V %.1f ms, back-transform %.1f ms, OV3 d_abci %.1f ms"
+              % (mst / 1e3, msv, msb, mso), file=sys.stderr, flush=True)
 
     cpu = None
     errs = {}

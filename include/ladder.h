@@ -214,6 +214,41 @@ int ladder_excited_amplitudes(int64_t o, int64_t v, double R0, const double* T, 
                               double* U, void* stream);
 
 /*
+ * Excited-state OV^3 density block d_abci = sum_j L_ji^ac R_j^b (Appendix A,
+ * excited-state densities; it vanishes in the ground state) and its two
+ * contributions to the three-index intermediate W^K_pq = sum_rs d_pqrs Z^K_rs
+ * (Sec. II B, contributions of the OV^3 densities), built through the
+ * intermediates of the table in Sec. II B without forming the density:
+ *   X_aj^K = sum_ci L_ji^ac Z^K_ci,   Wab^K_ab = beta Wab + alpha sum_j R_j^b X_aj^K
+ *   P_aj^K = sum_b R_j^b Z^K_ab,      Wci^K_ci = beta Wci + alpha sum_aj L_ji^ac P_aj^K
+ * Layouts (row-major FP64, device): L2 [o][o][v][v] (L2[((j*o+i)*v+a)*v+c] =
+ * L_ji^ac, like tau); R1 [o][v] (R1[j*v+b] = R_j^b); Zvv, Wab [v][v][n] (like L);
+ * Zvo, Wci [v][o][n] (Zvo[(c*o+i)*n+K] = Z^K_ci).  Either output may be NULL to
+ * skip that side (Wab needs Zvo, Wci needs Zvv; the other may then be NULL).
+ * With beta == 0 the outputs are not read.  Four FP64 MFMA GEMMs,
+ * 4 o^2 v^2 n + 4 o v^2 n flops for both sides, after a reordering of L2 (and of
+ * Zvv for Wci) into the workspace: ladder_ov3_abci_workspace_size bytes, 256-byte
+ * aligned, (o^2 v^2 + o v n + v^2 n) doubles.  No input may overlap an output or
+ * the workspace; the outputs may not overlap each other.  The V_MN partner is
+ * ladder_metric_contraction (ab side) plus ladder_metric_contraction_pairs over
+ * the v*o pairs of the ci side.
+ */
+int ladder_ov3_abci_workspace_size(int64_t o, int64_t v, int64_t n, size_t* bytes);
+int ladder_ov3_abci(int64_t o, int64_t v, int64_t n, const double* L2, const double* R1, const double* Zvv,
+                    const double* Zvo, double alpha, double beta, double* Wab, double* Wci, void* ws, size_t ws_bytes,
+                    void* stream);
+
+/*
+ * ladder_metric_contraction over any number of index pairs (the two-index
+ * intermediate V_MN = Z^M_ab W^N_ab + Z^M_ci W^N_ci of Sec. II B has a
+ * virtual-occupied part):  V = beta * V + alpha * sum_p Z[p][M] W[p][N], with
+ * Z and W [pairs][n] and V [n][n].  V must not overlap Z or W; with beta == 0
+ * it is not read.
+ */
+int ladder_metric_contraction_pairs(int64_t pairs, int64_t n, const double* Z, const double* W, double alpha,
+                                    double beta, double* V, void* stream);
+
+/*
  * First-order doubles amplitudes from the occupied-virtual Cholesky block (the
  * synthetic stand-in for converged T2; Cholesky expansion of Sec. II A):
  *   t_ij^ab = (sum_J L^J_ia L^J_jb) / ((eps_i + eps_j) - (eps_a + eps_b)).
@@ -280,7 +315,9 @@ int ladder_batched(int count, const ladder_instance* inst, uint32_t what, void* 
 #define LADDER_STAGE_UNPACK 10  /* R and D rebuilt from their packed parts */
 #define LADDER_STAGE_METRIC 11  /* V = Z^T W (three-index to two-index intermediate) */
 #define LADDER_STAGE_BACKTRANSFORM 12 /* MO back-transformation of W */
-#define LADDER_NUM_STAGES 13
+#define LADDER_STAGE_OV3_PERMUTE 13 /* OV^3 block: multiplier and Z reorderings */
+#define LADDER_STAGE_OV3 14     /* OV^3 block: the four GEMMs of W_ab and W_ci */
+#define LADDER_NUM_STAGES 15
 typedef struct {
     int32_t stage;
     int32_t launches;

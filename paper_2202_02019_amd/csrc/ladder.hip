@@ -560,6 +560,47 @@ __global__ void excited_amplitudes_kernel(double R0, const double* __restrict__ 
     }
 }
 
+// Multipliers L2[j][i][a][c] (= L_ji^ac) to Lp[j][a][c][i]: for every (j, a) the [i][c]
+// block (row stride v*v) is written transposed as [c][i] (row stride o) through a
+// 32 x 33 LDS tile, so both the reads (along c) and the writes (along i) are
+// contiguous.  Tiles are walked grid-stride; every index is checked against o and v.
+__global__ __launch_bounds__(256) void ov3_permute_l2_kernel(const double* __restrict__ L2, double* __restrict__ Lp,
+                                                             int64_t o, int64_t v) {
+    __shared__ double tile[32][33];
+    const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;
+    const int64_t ti_n = (o + 31) / 32, tc_n = (v + 31) / 32;
+    const int64_t total = o * v * ti_n * tc_n;
+    for (int64_t t = blockIdx.x; t < total; t += gridDim.x) {
+        const int64_t tc = t % tc_n, r1 = t / tc_n;
+        const int64_t ti = r1 % ti_n, ja = r1 / ti_n;
+        const int64_t j = ja / v, a = ja - j * v;
+        const int64_t i0 = ti * 32, c0 = tc * 32;
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            const int64_t i = i0 + ty + 8 * r, c = c0 + tx;
+            if (i < o && c < v) tile[ty + 8 * r][tx] = L2[((j * o + i) * v + a) * v + c];
+        }
+        __syncthreads();
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            const int64_t c = c0 + ty + 8 * r, i = i0 + tx;
+            if (i < o && c < v) Lp[((j * v + a) * v + c) * o + i] = tile[tx][ty + 8 * r];
+        }
+        __syncthreads();
+    }
+}
+
+// Zt[b][a][K] = Z[a][b][K]: whole n-long rows moved, one (a, b) row per block step.
+__global__ __launch_bounds__(256) void ov3_swap_vv_kernel(const double* __restrict__ Z, double* __restrict__ Zt,
+                                                          int64_t v, int64_t n) {
+    for (int64_t ab = blockIdx.x; ab < v * v; ab += gridDim.x) {
+        const int64_t a = ab / v, b = ab - a * v;
+        const double* src = Z + ab * n;
+        double* dst = Zt + (b * v + a) * n;
+        for (int64_t K = threadIdx.x; K < n; K += blockDim.x) dst[K] = src[K];
+    }
+}
+
 // Grid of the tiled packing kernels: tile pairs in x, rows over (y, z).
 dim3 pm_grid(int64_t v, int64_t rows) {
     const int64_t gy = std::min<int64_t>(std::max<int64_t>(rows, 1), 65535);
@@ -1343,6 +1384,129 @@ int ladder_back_transform(int64_t v, int64_t n, const double* x, const double* y
     EpiSwapMid e2{Wmo, v, v, n, alpha, beta};
     return hip_check(launch_gemm<false, false, LADDER_STAGE_BACKTRANSFORM>(y, v, U, v * n, v, v * n, v, e2, st),
                      "back-transform GEMM launch");
+}
+
+int ladder_metric_contraction_pairs(int64_t pairs, int64_t n, const double* Z, const double* W, double alpha,
+                                    double beta, double* V, void* stream) {
+    g_last_error.clear();
+    if (pairs < 1 || n < 1 || pairs > (int64_t)1 << 40 || n > 1000000)
+        return fail(LADDER_EINVAL, "bad dimensions pairs=%lld n=%lld", (long long)pairs, (long long)n);
+    if (!Z || !W || !V) return fail(LADDER_EINVAL, "Z, W and V must be non-NULL");
+    if (!aligned8(Z) || !aligned8(W) || !aligned8(V)) return fail(LADDER_EINVAL, "misaligned pointer (8-byte alignment)");
+    int64_t zb;
+    if (!mul_ok(pairs, n * 8, zb)) return fail(LADDER_EINVAL, "size overflow");
+    const int64_t vb = n * n * 8;
+    if (overlap(V, vb, Z, zb) || overlap(V, vb, W, zb)) return fail(LADDER_EINVAL, "V overlaps Z or W");
+    hipStream_t st = (hipStream_t)stream;
+    StageTimer tm(LADDER_STAGE_METRIC, gemm_flops(n, n, pairs), gemm_bytes(n, n, pairs), st);
+    EpiStrided ev{V, n, alpha, beta, nullptr, nullptr};
+    return hip_check(launch_gemm<false, false, LADDER_STAGE_METRIC>(Z, n, W, n, n, n, pairs, ev, st), "metric GEMM launch");
+}
+
+namespace {
+// Workspace of ladder_ov3_abci: Lp [o][v][v][o], one [o][v][n] buffer (X, then P) and
+// Zt [v][v][n], each 256-byte aligned.
+struct Ov3Layout {
+    size_t lp, xp, zt, total;
+};
+int ov3_layout(int64_t o, int64_t v, int64_t n, Ov3Layout& l) {
+    Sizes s;
+    int rc;
+    if ((rc = check_dims(o, v, n, s))) return rc;
+    int64_t ovn;
+    if (!mul_ok(o * v, n, ovn) || ovn > INT64_MAX / 16) return fail(LADDER_EINVAL, "array sizes overflow 64-bit byte counts");
+    // every GEMM grid (one workgroup per 128 x 128 tile) must fit a 32-bit launch
+    const int64_t grid_max = (int64_t)1 << 31;
+    if (tiles(o * v, n) >= grid_max || tiles(v, v * n) >= grid_max || tiles(o, v * n) >= grid_max)
+        return fail(LADDER_EINVAL, "problem too large for one launch per GEMM");
+    l.lp = 0;
+    l.xp = align_up((size_t)s.ovv_elems * 8);
+    l.zt = l.xp + align_up((size_t)ovn * 8);
+    l.total = l.zt + align_up((size_t)s.vvn * 8);
+    return LADDER_OK;
+}
+}  // namespace
+
+int ladder_ov3_abci_workspace_size(int64_t o, int64_t v, int64_t n, size_t* bytes) {
+    g_last_error.clear();
+    if (!bytes) return fail(LADDER_EINVAL, "bytes is NULL");
+    Ov3Layout l;
+    int rc;
+    if ((rc = ov3_layout(o, v, n, l))) return rc;
+    *bytes = l.total;
+    return LADDER_OK;
+}
+
+int ladder_ov3_abci(int64_t o, int64_t v, int64_t n, const double* L2, const double* R1, const double* Zvv,
+                    const double* Zvo, double alpha, double beta, double* Wab, double* Wci, void* ws, size_t ws_bytes,
+                    void* stream) {
+    g_last_error.clear();
+    Ov3Layout l;
+    int rc;
+    if ((rc = ov3_layout(o, v, n, l))) return rc;
+    if (!L2 || !R1 || !ws) return fail(LADDER_EINVAL, "L2, R1 and ws must be non-NULL");
+    if (!Wab && !Wci) return fail(LADDER_EINVAL, "Wab and Wci are both NULL: nothing to compute");
+    if (Wab && !Zvo) return fail(LADDER_EINVAL, "Wab needs Zvo");
+    if (Wci && !Zvv) return fail(LADDER_EINVAL, "Wci needs Zvv");
+    if (!aligned8(L2) || !aligned8(R1) || !aligned8(Zvv) || !aligned8(Zvo) || !aligned8(Wab) || !aligned8(Wci) ||
+        ((uintptr_t)ws % ALIGN))
+        return fail(LADDER_EINVAL, "misaligned pointer (arrays need 8-byte, ws 256-byte alignment)");
+    if (ws_bytes < l.total) return fail(LADDER_EWORKSPACE, "workspace of %zu bytes, %zu needed", ws_bytes, l.total);
+    const int64_t l2b = o * o * v * v * 8, r1b = o * v * 8, vvb = v * v * n * 8, vob = v * o * n * 8;
+    const int64_t wsb = (int64_t)ws_bytes;
+    const void* ins[4] = {L2, R1, Zvv, Zvo};
+    const int64_t inb[4] = {l2b, r1b, vvb, vob};
+    for (int k = 0; k < 4; ++k)
+        if (overlap(ins[k], inb[k], ws, wsb) || overlap(Wab, vvb, ins[k], inb[k]) || overlap(Wci, vob, ins[k], inb[k]))
+            return fail(LADDER_EINVAL, "an input overlaps an output or the workspace");
+    if (overlap(Wab, vvb, ws, wsb) || overlap(Wci, vob, ws, wsb) || overlap(Wab, vvb, Wci, vob))
+        return fail(LADDER_EINVAL, "Wab or Wci overlaps the workspace or the other output");
+    hipStream_t st = (hipStream_t)stream;
+    char* w = (char*)ws;
+    double* Lp = (double*)(w + l.lp);
+    double* XP = (double*)(w + l.xp);
+    double* Zt = (double*)(w + l.zt);
+    const int64_t ov = o * v, vn = v * n;
+    {
+        StageTimer tm(LADDER_STAGE_OV3_PERMUTE, 0.0, 2.0 * (double)(l2b + (Wci ? vvb : 0)), st);
+        const int64_t tiles = ov * ((o + 31) / 32) * ((v + 31) / 32);
+        hipLaunchKernelGGL(ov3_permute_l2_kernel, dim3((unsigned)std::min<int64_t>(tiles, (int64_t)1 << 20)), dim3(256),
+                           0, st, L2, Lp, o, v);
+        if ((rc = hip_check(hipGetLastError(), "OV3 permutation launch"))) return rc;
+        if (Wci) {
+            hipLaunchKernelGGL(ov3_swap_vv_kernel, dim3((unsigned)std::min<int64_t>(v * v, (int64_t)1 << 20)), dim3(256),
+                               0, st, Zvv, Zt, v, n);
+            if ((rc = hip_check(hipGetLastError(), "OV3 permutation launch"))) return rc;
+        }
+    }
+    const double fl = (Wab ? gemm_flops(ov, n, ov) + gemm_flops(v, vn, o) : 0.0) +
+                      (Wci ? gemm_flops(o, vn, v) + gemm_flops(ov, n, ov) : 0.0);
+    const double by = (Wab ? gemm_bytes(ov, n, ov) + gemm_bytes(v, vn, o) : 0.0) +
+                      (Wci ? gemm_bytes(o, vn, v) + gemm_bytes(ov, n, ov) : 0.0);
+    StageTimer tm(LADDER_STAGE_OV3, fl, by, st);
+    if (Wab) {
+        // X[j][a][K] = sum_(c,i) Lp[j][a][c][i] Zvo[c][i][K]  (X_aj^K of the table of intermediates)
+        EpiStrided ex{XP, n, 1.0, 0.0, nullptr, nullptr};
+        if ((rc = hip_check(launch_gemm<true, false, LADDER_STAGE_OV3>(Lp, ov, Zvo, n, ov, n, ov, ex, st), "OV3 GEMM launch")))
+            return rc;
+        // Wab[a][b][K] = beta Wab + alpha sum_j R1[j][b] X[j][a][K]: A(b, j) = R1[j*v + b],
+        // B(j, (a,K)) = X[j*v*n + a*n + K]; the epilogue puts (b, (a,K)) at [a][b][K]
+        EpiSwapMid ew{Wab, v, v, n, alpha, beta};
+        if ((rc = hip_check(launch_gemm<false, false, LADDER_STAGE_OV3>(R1, v, XP, vn, v, vn, o, ew, st), "OV3 GEMM launch")))
+            return rc;
+    }
+    if (Wci) {
+        // P[j][a][K] = sum_b R1[j][b] Zt[b][a][K]  (P_aj^K of the table of intermediates)
+        EpiStrided ep{XP, vn, 1.0, 0.0, nullptr, nullptr};
+        if ((rc = hip_check(launch_gemm<true, false, LADDER_STAGE_OV3>(R1, v, Zt, vn, o, vn, v, ep, st), "OV3 GEMM launch")))
+            return rc;
+        // Wci[c][i][K] = beta Wci + alpha sum_(j,a) Lp[j][a][c][i] P[j][a][K]: A((c,i), (j,a)) is
+        // (c,i)-contiguous with stride v*o between (j,a) rows
+        EpiStrided ew{Wci, n, alpha, beta, nullptr, nullptr};
+        if ((rc = hip_check(launch_gemm<false, false, LADDER_STAGE_OV3>(Lp, ov, XP, n, ov, n, ov, ew, st), "OV3 GEMM launch")))
+            return rc;
+    }
+    return LADDER_OK;
 }
 
 int ladder_mp2_amplitudes(int64_t o, int64_t v, int64_t n, const double* Lov, const double* eps, double* t,

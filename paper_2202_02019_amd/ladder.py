@@ -30,13 +30,14 @@ EXPORTS = (
     "ladder_tau_gradient_workspace_size", "ladder_tau_gradient", "ladder_autotune", "ladder_autotune_load",
     "ladder_autotune_reset", "ladder_metric_contraction",
     "ladder_back_transform_workspace_size", "ladder_back_transform", "ladder_excited_amplitudes",
+    "ladder_ov3_abci_workspace_size", "ladder_ov3_abci", "ladder_metric_contraction_pairs",
     "ladder_mp2_amplitudes", "ladder_amplitude_update", "ladder_batched_workspace_size",
     "ladder_batched", "ladder_strerror", "ladder_last_error", "ladder_shutdown",
     "ladder_profile_start", "ladder_profile_stop",
 )
 
 STAGE_NAMES = ("gemm_b", "gemm_c", "energy", "gemm_e", "gemm_f", "swap", "mp2", "update", "slice", "pack", "unpack",
-               "metric", "back_transform")
+               "metric", "back_transform", "ov3_permute", "ov3")
 
 
 class LadderError(RuntimeError):
@@ -105,6 +106,9 @@ def _load():
     lib.ladder_back_transform_workspace_size.argtypes = [i64, i64, ctypes.POINTER(sz)]
     lib.ladder_back_transform.argtypes = [i64, i64, vp, vp, vp, dbl, dbl, vp, vp, sz, vp]
     lib.ladder_excited_amplitudes.argtypes = [i64, i64, dbl, vp, vp, ctypes.c_int, vp, vp]
+    lib.ladder_ov3_abci_workspace_size.argtypes = [i64, i64, i64, ctypes.POINTER(sz)]
+    lib.ladder_ov3_abci.argtypes = [i64, i64, i64, vp, vp, vp, vp, dbl, dbl, vp, vp, vp, sz, vp]
+    lib.ladder_metric_contraction_pairs.argtypes = [i64, i64, vp, vp, dbl, dbl, vp, vp]
     lib.ladder_mp2_amplitudes.argtypes = [i64, i64, i64, vp, vp, vp, vp]
     lib.ladder_amplitude_update.argtypes = [i64, i64, vp, vp, vp, vp]
     lib.ladder_batched_workspace_size.argtypes = [ctypes.c_int, ctypes.POINTER(_CInstance), ctypes.c_uint32, op,
@@ -113,7 +117,8 @@ def _load():
     for f in ("ladder_workspace_size", "ladder_forward", "ladder_adjoint", "ladder_tau_gradient_workspace_size",
               "ladder_tau_gradient", "ladder_autotune", "ladder_autotune_load", "ladder_metric_contraction",
               "ladder_back_transform_workspace_size",
-              "ladder_back_transform", "ladder_excited_amplitudes", "ladder_mp2_amplitudes",
+              "ladder_back_transform", "ladder_excited_amplitudes", "ladder_ov3_abci_workspace_size",
+              "ladder_ov3_abci", "ladder_metric_contraction_pairs", "ladder_mp2_amplitudes",
               "ladder_amplitude_update", "ladder_batched_workspace_size", "ladder_batched"):
         getattr(lib, f).restype = ctypes.c_int
     lib.ladder_strerror.argtypes = [ctypes.c_int]
@@ -315,6 +320,48 @@ def excited_amplitudes(T, R2, R0, *, o, v, mode=U_APPENDIX, U=None, stream=None)
     _need(U, "U", (o, o, v, v))
     _check(_load().ladder_excited_amplitudes(o, v, float(R0), _ptr(T), _ptr(R2), int(mode), _ptr(U), _stream(stream)))
     return U
+
+
+def ov3_abci_workspace_size(o: int, v: int, n: int) -> int:
+    b = ctypes.c_size_t(0)
+    _check(_load().ladder_ov3_abci_workspace_size(o, v, n, ctypes.byref(b)))
+    return b.value
+
+
+def ov3_abci(L2, R1, Zvv, Zvo, *, o, v, n, Wab=None, Wci=None, alpha=1.0, beta=0.0, want=(True, True), ws=None,
+             stream=None):
+    """Both W contributions of the excited-state OV^3 density d_abci = sum_j L_ji^ac R_j^b:
+    Wab [v][v][n] (from Zvo [v][o][n]) and Wci [v][o][n] (from Zvv [v][v][n]), each
+    beta*W + alpha*W'.  `want` = (ab side, ci side); a side not wanted is returned as None."""
+    want_ab, want_ci = bool(want[0]), bool(want[1])
+    _need(L2, "L2", (o, o, v, v)); _need(R1, "R1", (o, v))
+    if want_ab:
+        _need(Zvo, "Zvo", (v, o, n))
+        if Wab is None:
+            Wab = torch.empty((v, v, n), dtype=torch.float64, device=L2.device)
+        _need(Wab, "Wab", (v, v, n))
+    if want_ci:
+        _need(Zvv, "Zvv", (v, v, n))
+        if Wci is None:
+            Wci = torch.empty((v, o, n), dtype=torch.float64, device=L2.device)
+        _need(Wci, "Wci", (v, o, n))
+    wsb = _workspace(ov3_abci_workspace_size(o, v, n), L2.device, ws)
+    _check(_load().ladder_ov3_abci(o, v, n, _ptr(L2), _ptr(R1), _ptr(Zvv) if want_ci else None,
+                                   _ptr(Zvo) if want_ab else None, float(alpha), float(beta),
+                                   _ptr(Wab) if want_ab else None, _ptr(Wci) if want_ci else None, _ptr(wsb),
+                                   wsb.numel() * wsb.element_size(), _stream(stream)))
+    return (Wab if want_ab else None), (Wci if want_ci else None)
+
+
+def metric_contraction_pairs(Z, W, *, pairs, n, V=None, alpha=1.0, beta=0.0, stream=None):
+    """V_MN = beta*V + alpha * sum_p Z[p][M] W[p][N] over `pairs` index pairs  (Z, W: [pairs][n])."""
+    _need(Z, "Z", (pairs, n)); _need(W, "W", (pairs, n))
+    if V is None:
+        V = torch.empty((n, n), dtype=torch.float64, device=Z.device)
+    _need(V, "V", (n, n))
+    _check(_load().ladder_metric_contraction_pairs(pairs, n, _ptr(Z), _ptr(W), float(alpha), float(beta), _ptr(V),
+                                                   _stream(stream)))
+    return V
 
 
 def mp2_amplitudes(Lov, eps, *, o, v, n, t=None, stream=None):

@@ -129,6 +129,40 @@ def test_intermediate_entry_validation():
     assert bt(ws=3 * FAKE) == EINVAL                             # workspace overlaps W
 
 
+def test_ov3_abci_validation():
+    """The OV^3 entry points reject bad dimensions, missing operands, overlaps, misalignment
+    and a short workspace before any HIP call; the workspace holds the reordered multipliers,
+    one [o][v][n] intermediate and the reordered Zvv."""
+    lib = _lib()
+    o, v, n = 2, 3, 4
+    b = ctypes.c_size_t(0)
+    assert lib.ladder_ov3_abci_workspace_size(o, v, n, ctypes.byref(b)) == 0
+    assert b.value >= 8 * (o * o * v * v + o * v * n + v * v * n) and b.value % 256 == 0
+    assert lib.ladder_ov3_abci_workspace_size(o, 0, n, ctypes.byref(b)) == EINVAL
+    assert lib.ladder_ov3_abci_workspace_size(o, v, n, None) == EINVAL
+    M = 1 << 24  # 16 MiB apart: no two arrays below overlap
+
+    def call(L2=FAKE, R1=FAKE + M, Zvv=FAKE + 2 * M, Zvo=FAKE + 3 * M, Wab=FAKE + 4 * M, Wci=FAKE + 5 * M,
+             ws=FAKE + 6 * M, wsb=1 << 20, oo=o):
+        return lib.ladder_ov3_abci(oo, v, n, L2, R1, Zvv, Zvo, 1.0, 0.0, Wab, Wci, ws, wsb, None)
+
+    assert call(oo=0) == EINVAL
+    assert call(L2=None) == EINVAL
+    assert call(R1=None) == EINVAL
+    assert call(Wab=None, Wci=None) == EINVAL                   # nothing to compute
+    assert call(Zvo=None) == EINVAL                             # Wab needs Zvo
+    assert call(Zvv=None) == EINVAL                             # Wci needs Zvv
+    assert call(Wab=FAKE + 8) == EINVAL                         # Wab overlaps L2
+    assert call(Wci=FAKE + 4 * M + 8) == EINVAL                 # the outputs overlap
+    assert call(ws=FAKE + 6 * M + 8) == EINVAL                  # misaligned workspace
+    assert call(Wab=FAKE + 4 * M + 4) == EINVAL                 # misaligned output
+    assert call(ws=FAKE + 3 * M) == EINVAL                      # workspace overlaps Zvo
+    assert call(wsb=64) == EWORKSPACE
+    assert lib.ladder_metric_contraction_pairs(0, n, FAKE, 2 * FAKE, 1.0, 0.0, 3 * FAKE, None) == EINVAL
+    assert lib.ladder_metric_contraction_pairs(6, n, FAKE, None, 1.0, 0.0, 3 * FAKE, None) == EINVAL
+    assert lib.ladder_metric_contraction_pairs(6, n, FAKE, 2 * FAKE, 1.0, 0.0, FAKE + 8, None) == EINVAL  # V overlaps Z
+
+
 def test_autotune_validation_and_cache(tmp_path):
     """Argument checks run before any HIP call; the cache file is parsed line by line (other
     devices' lines and junk are skipped) and a tuned batch size changes the ragged-batch plan."""

@@ -584,6 +584,81 @@ def test_excited_amplitudes_and_density(dev, mode):
     assert np.array_equal(Tg.cpu().numpy(), Ur)
 
 
+# ------------------------------------------------------------------ excited-state OV^3 density d_abci
+def ov3_inputs(seed, o, v, n, integer=False):
+    rng = np.random.default_rng(seed)
+    if integer:
+        return (rng.integers(-3, 4, (o, o, v, v)).astype(float), rng.integers(-3, 4, (o, v)).astype(float),
+                rng.integers(-3, 4, (v, v, n)).astype(float), rng.integers(-3, 4, (v, o, n)).astype(float))
+    return (rng.standard_normal((o, o, v, v)), rng.standard_normal((o, v)), rng.standard_normal((v, v, n)),
+            rng.standard_normal((v, o, n)))
+
+
+@pytest.mark.parametrize("o,v,n,seed", [(1, 1, 1, 110), (2, 3, 2, 111), (3, 7, 5, 112), (5, 33, 17, 113),
+                                        (4, 130, 9, 114), (9, 20, 131, 115)])
+def test_ov3_abci_integer_bitwise(dev, o, v, n, seed):
+    """Integer inputs: every sum is exact on both sides, so Wab and Wci equal the oracle's
+    (density formed element by element) bit for bit; shapes span several 128 tiles and ragged tails."""
+    L2, R1, Zvv, Zvo = ov3_inputs(seed, o, v, n, integer=True)
+    Wab, Wci = P.ov3_abci(g(L2, dev), g(R1, dev), g(Zvv, dev), g(Zvo, dev), o=o, v=v, n=n)
+    Wab_r, Wci_r = oracle.ov3_abci(o, v, n, L2, R1, Zvv, Zvo)
+    assert np.array_equal(Wab.cpu().numpy(), Wab_r)
+    assert np.array_equal(Wci.cpu().numpy(), Wci_r)
+
+
+@pytest.mark.parametrize("o,v,n,seed", [(4, 20, 60, 116), (6, 45, 70, 117), (3, 129, 130, 118)])
+def test_ov3_abci_matches_oracle(dev, o, v, n, seed):
+    """Gaussian inputs with alpha, beta; each side alone (the other output and its Z NULL)
+    gives the same result as both together."""
+    L2, R1, Zvv, Zvo = ov3_inputs(seed, o, v, n)
+    rng = np.random.default_rng(seed + 1)
+    A0, C0 = rng.standard_normal((v, v, n)), rng.standard_normal((v, o, n))
+    Wab_r, Wci_r = oracle.matrix.ov3_abci(o, v, n, L2, R1, Zvv, Zvo)
+    Wab, Wci = P.ov3_abci(g(L2, dev), g(R1, dev), g(Zvv, dev), g(Zvo, dev), o=o, v=v, n=n, Wab=g(A0, dev),
+                          Wci=g(C0, dev), alpha=-0.5, beta=2.0)
+    ea, ec = err_norm(Wab.cpu().numpy(), 2.0 * A0 - 0.5 * Wab_r), err_norm(Wci.cpu().numpy(), 2.0 * C0 - 0.5 * Wci_r)
+    print("OV3 o=%d v=%d n=%d: err Wab %.3e err Wci %.3e" % (o, v, n, ea, ec))
+    assert ea <= TOL and ec <= TOL
+    a_only, none = P.ov3_abci(g(L2, dev), g(R1, dev), None, g(Zvo, dev), o=o, v=v, n=n, want=(True, False))
+    assert none is None and err_norm(a_only.cpu().numpy(), Wab_r) <= TOL
+    none, c_only = P.ov3_abci(g(L2, dev), g(R1, dev), g(Zvv, dev), None, o=o, v=v, n=n, want=(False, True))
+    assert none is None and err_norm(c_only.cpu().numpy(), Wci_r) <= TOL
+
+
+@pytest.mark.parametrize("pairs,n,seed", [(1, 1, 119), (35, 17, 120), (300, 129, 121)])
+def test_metric_contraction_pairs_bitwise(dev, pairs, n, seed):
+    rng = np.random.default_rng(seed)
+    Z, W, V0 = (rng.integers(-5, 6, s).astype(float) for s in ((pairs, n), (pairs, n), (n, n)))
+    V = P.metric_contraction_pairs(g(Z, dev), g(W, dev), pairs=pairs, n=n, V=g(V0, dev), alpha=2.0, beta=-1.0)
+    assert np.array_equal(V.cpu().numpy(), 2.0 * oracle.metric_contraction_pairs(pairs, n, Z, W) - V0)
+
+
+def test_ov3_abci_retinal_sampled(dev):
+    """o=78, v=657, n=2200 (the retinal shape, the launch the benchmark times): sampled rows of
+    Wab and Wci against the oracle one by one, and the identity sum Zvv*Wab = sum Zvo*Wci
+    (both are sum_abci d_abci (ab|ci) with (ab|ci) = sum_K Zvv^K_ab Zvo^K_ci)."""
+    o, v, n = 78, 657, 2200
+    gen = torch.Generator(device=dev)
+    gen.manual_seed(122)
+    L2 = torch.randn((o, o, v, v), dtype=torch.float64, device=dev, generator=gen)
+    R1 = torch.randn((o, v), dtype=torch.float64, device=dev, generator=gen)
+    Zvv = torch.randn((v, v, n), dtype=torch.float64, device=dev, generator=gen)
+    Zvo = torch.randn((v, o, n), dtype=torch.float64, device=dev, generator=gen)
+    Wab, Wci = P.ov3_abci(L2, R1, Zvv, Zvo, o=o, v=v, n=n)
+    torch.cuda.synchronize()
+    s_ab, s_ci = float((Zvv * Wab).sum()), float((Zvo * Wci).sum())
+    L2h, R1h, Zvvh, Zvoh = L2.cpu().numpy(), R1.cpu().numpy(), Zvv.cpu().numpy(), Zvo.cpu().numpy()
+    ab = np.array([[0, 0], [656, 1], [300, 656], [77, 78]])
+    ci = np.array([[0, 0], [656, 77], [123, 40]])
+    ra = oracle.ov3_abci_wab(o, v, n, L2h, R1h, Zvoh, ab)
+    rc = oracle.ov3_abci_wci(o, v, n, L2h, R1h, Zvvh, ci)
+    ea = err_norm(Wab[ab[:, 0], ab[:, 1]].cpu().numpy(), ra)
+    ec = err_norm(Wci[ci[:, 0], ci[:, 1]].cpu().numpy(), rc)
+    ident = abs(s_ab - s_ci) / (float((Zvv * Wab).abs().sum()))
+    print("OV3 retinal shape: err Wab %.3e err Wci %.3e identity %.3e" % (ea, ec, ident))
+    assert ea <= TOL and ec <= TOL and ident <= 1e-12
+
+
 # ------------------------------------------------------------------ autotuned batch size
 @pytest.mark.parametrize("precision", [P.FP64, P.SPLIT_BF16])
 def test_autotune_then_default_calls_use_it(dev, tmp_path, precision):
