@@ -203,7 +203,9 @@ int ladder_back_transform(int64_t v, int64_t n, const double* x, const double* y
  * d^es_abcd = O^(2)_abcd(L_2, U) (Appendix A), from the ground-state T_2, the
  * excited-state R_2 and the reference weight R_0.  The paper defines U twice:
  *   LADDER_U_TABLE    (0): U = T_2 R_0 + R_2                  (table of intermediates, Sec. II B)
- *   LADDER_U_APPENDIX (1): U = T_2 R_0 / 2 + Rt_2, Rt_ij^ab = 2 R_ij^ab - R_ji^ab   (Appendix A)
+ *   LADDER_U_APPENDIX (1): U = T_2 R_0 / 2 + Rt_2, Rt_ij^ab = R_ij^ab (1 + [i = j][a = b])
+ *                          (Appendix A; Rt_2 is its R~_2, the doubles expanded over all
+ *                          (ai, bj) with the diagonal ones counted twice)
  * The excited-state V^4 contribution to the three-index intermediate is then
  * ladder_adjoint(Z or L, U, L_2).  U may equal T (in place) but must not overlap
  * R2.  Pair-symmetric T and R2 give pair-symmetric U in both modes.  FP64.

@@ -276,7 +276,10 @@ int oracle_back_transform_range(int64_t v, int64_t n, const double* x, const dou
  * Excited-state amplitudes entering the excited-state V^4 density
  * d^es_abcd = O^(2)_abcd(L_2, U) (Appendix A); the paper gives two definitions:
  *   mode 0 (table of intermediates): U_ij^ab = R0 T_ij^ab + R_ij^ab
- *   mode 1 (Appendix A):             U_ij^ab = (R0/2) T_ij^ab + (2 R_ij^ab - R_ji^ab)
+ *   mode 1 (Appendix A):             U_ij^ab = (R0/2) T_ij^ab + Rt_ij^ab,
+ *                                    Rt_ij^ab = R_ij^ab (1 + [i = j][a = b])
+ * where Rt is the Appendix's R~_2: the doubles written over all (ai, bj) with the
+ * coefficient R_aibj (1 + delta_{ai,bj}), i.e. the diagonal doubles counted twice.
  */
 int oracle_excited_amplitudes(int64_t o, int64_t v, double R0, const double* T, const double* R2, int mode,
                               double* U) {
@@ -285,11 +288,11 @@ int oracle_excited_amplitudes(int64_t o, int64_t v, double R0, const double* T, 
         for (int64_t j = 0; j < o; ++j)
             for (int64_t a = 0; a < v; ++a)
                 for (int64_t b = 0; b < v; ++b) {
-                    const int64_t x = ((i * o + j) * v + a) * v + b, xs = ((j * o + i) * v + a) * v + b;
+                    const int64_t x = ((i * o + j) * v + a) * v + b;
                     if (mode == 0)
                         U[x] = R0 * T[x] + R2[x];
                     else
-                        U[x] = 0.5 * R0 * T[x] + (2.0 * R2[x] - R2[xs]);
+                        U[x] = 0.5 * R0 * T[x] + (i == j && a == b ? 2.0 * R2[x] : R2[x]);
                 }
     return 0;
 }

@@ -185,7 +185,7 @@ def back_transform(v, n, x, y, W):
 
 
 def excited_amplitudes(o, v, R0, T, R2, mode):
-    """U for the excited-state V^4 density (mode 0: R0 T + R2; mode 1: R0 T/2 + 2 R2 - R2(i<->j))."""
+    """U for the excited-state V^4 density (mode 0: R0 T + R2; mode 1: R0 T/2 + R~2, R~2 = R2 with its i=j, a=b elements doubled)."""
     T = _f64(T, (o, o, v, v)); R2 = _f64(R2, (o, o, v, v))
     U = np.zeros((o, o, v, v))
     if load().oracle_excited_amplitudes(o, v, float(R0), _p(T), _p(R2), int(mode), _p(U)) != 0:

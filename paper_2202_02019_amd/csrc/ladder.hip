@@ -546,7 +546,8 @@ __global__ void amplitude_update_kernel(const double* __restrict__ eps, const do
     }
 }
 
-// Excited-state amplitudes: mode 0: U = R0 T + R2; mode 1: U = (R0/2) T + 2 R2 - R2(i<->j).
+// Excited-state amplitudes: mode 0: U = R0 T + R2; mode 1: U = (R0/2) T + R~2 with
+// R~_ij^ab = R_ij^ab (1 + [i = j][a = b]) (the diagonal doubles counted twice).
 __global__ void excited_amplitudes_kernel(double R0, const double* __restrict__ T, const double* __restrict__ R2,
                                           int mode, double* __restrict__ U, int64_t o, int64_t v) {
     const int64_t total = o * o * v * v, vv = v * v;
@@ -554,8 +555,8 @@ __global__ void excited_amplitudes_kernel(double R0, const double* __restrict__ 
         if (mode == 0) {
             U[x] = R0 * T[x] + R2[x];
         } else {
-            const int64_t ab = x % vv, ij = x / vv, i = ij / o, j = ij % o;
-            U[x] = 0.5 * R0 * T[x] + (2.0 * R2[x] - R2[(j * o + i) * vv + ab]);
+            const int64_t ab = x % vv, ij = x / vv, i = ij / o, j = ij % o, a = ab / v, b = ab % v;
+            U[x] = 0.5 * R0 * T[x] + (i == j && a == b ? 2.0 * R2[x] : R2[x]);
         }
     }
 }

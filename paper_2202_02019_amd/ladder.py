@@ -313,7 +313,8 @@ def back_transform(x, y, W, *, v, n, Wmo=None, alpha=1.0, beta=0.0, ws=None, str
 
 
 def excited_amplitudes(T, R2, R0, *, o, v, mode=U_APPENDIX, U=None, stream=None):
-    """U for the excited-state V^4 density: U_TABLE: R0 T + R2; U_APPENDIX: R0 T / 2 + 2 R2 - R2(i<->j)."""
+    """U for the excited-state V^4 density: U_TABLE: R0 T + R2; U_APPENDIX: R0 T / 2 + R~2, where
+    R~2 is R2 with its diagonal elements (i = j, a = b) doubled."""
     _need(T, "T", (o, o, v, v)); _need(R2, "R2", (o, o, v, v))
     if U is None:
         U = torch.empty((o, o, v, v), dtype=torch.float64, device=T.device)

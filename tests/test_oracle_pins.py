@@ -376,18 +376,20 @@ def test_back_transform(gi):
 
 # ---------------------------------------------------------------- excited-state amplitudes
 def test_excited_amplitudes(oracle_lib):
-    """Special cases of both readings: R0 = 0 or R2 = 0 isolate one term; a unit R2 at
-    (i, j, a, b), i != j, gives 2 there and -1 at (j, i, a, b) in the Appendix reading;
-    pair-symmetric T and R2 give a pair-symmetric U."""
+    """Special cases of both readings: R0 = 0 or R2 = 0 isolate one term; in the Appendix
+    reading (R~_aibj = R_aibj (1 + delta_{ai,bj}), Appendix A) a unit R2 off the diagonal is
+    carried over unchanged and a unit R2 at i = j, a = b counts twice; pair-symmetric T and
+    R2 give a pair-symmetric U."""
     o, v = 3, 4
     T, R2 = rnd(81, o, o, v, v), rnd(82, o, o, v, v)
     assert np.array_equal(oracle_lib.excited_amplitudes(o, v, 0.0, T, R2, 0), R2)
     assert np.array_equal(oracle_lib.excited_amplitudes(o, v, 0.75, T, np.zeros_like(R2), 0), 0.75 * T)
     assert np.array_equal(oracle_lib.excited_amplitudes(o, v, 0.75, T, np.zeros_like(R2), 1), 0.375 * T)
-    E1 = np.zeros((o, o, v, v)); E1[0, 2, 1, 3] = 1.0
-    U = oracle_lib.excited_amplitudes(o, v, 0.3, np.zeros_like(T), E1, 1)
-    ref = np.zeros_like(U); ref[0, 2, 1, 3] = 2.0; ref[2, 0, 1, 3] = -1.0
-    assert np.array_equal(U, ref)
+    for (i, j, a, b, f) in [(0, 2, 1, 3, 1.0), (1, 1, 2, 0, 1.0), (0, 2, 3, 3, 1.0), (2, 2, 1, 1, 2.0)]:
+        E1 = np.zeros((o, o, v, v)); E1[i, j, a, b] = 1.0
+        U = oracle_lib.excited_amplitudes(o, v, 0.3, np.zeros_like(T), E1, 1)
+        ref = np.zeros_like(U); ref[i, j, a, b] = f
+        assert np.array_equal(U, ref), (i, j, a, b)
     Ts, Rs = pair_sym(T), pair_sym(R2)
     for mode in (0, 1):
         U = oracle_lib.excited_amplitudes(o, v, 0.9, Ts, Rs, mode)
