@@ -566,3 +566,161 @@ int oracle_metric_contraction_pairs(int64_t pairs, int64_t n, const double* Z, c
         }
     return 0;
 }
+
+/*
+ * Excited-state OV^3 density block d_abic (Appendix A, excited-state densities)
+ * and its two contributions to the three-index intermediate (Sec. II B):
+ *   Wab^K_ab = sum_ic d_abic Z^K_ic,   Wic^K_ic = sum_ab d_abic Z^K_ab.
+ * With L^a_m the singles and L_ij^ab the doubles multipliers, t the ground-state
+ * doubles, R_0, R^a_i, R_ij^ab the excited-state right vector, and the tilde
+ * conventions  t~_ij^ab = 2 t_ij^ab - t_ji^ab,  R~_ij^ab = R_ij^ab (1 + [i=j][a=b]):
+ *   d_abic = R_0 L^a_m t~_im^cb                               (1)
+ *          + L^a_m (2 R~_mi^bc - R~_mi^cb)                     (2)
+ *          + 2 X_ab R^c_i                                      (3)
+ *          - (V_akbi + Y_akbi) R^c_k                           (4)
+ *          + L_mk^ad t~_mi^bc R^d_k                            (5)
+ *          - L_mn^ad t_mn^bc R^d_i                             (6)
+ *          + Yt_akci R^b_k                                     (7)
+ *          - X_ac R^b_i                                        (8)
+ * with the intermediates of Sec. II B and Appendix A (all with C_2 = t):
+ *   X_ab    = L_kl^ad t_kl^bd
+ *   V_akbi  = L_lk^ae t_li^be          (V_ajbi = L_kj^ac C_ki^bc)
+ *   Y_akbi  = L_kl^ad t_il^bd          (Y_ajbi = L_jl^ad C_il^bd)
+ *   Yt_akci = L_mk^ea t~_mi^ec         (Yt_djak = L_mj^ed t~_mk^ea)
+ *   W_am    = L_mk^ad R^d_k            (W_ai = L_il^ad R_dl; term (5) is W_am t~_mi^bc)
+ *   B_iamn  = L_mn^ad R^d_i            (term (6) is -B_iamn t_mn^bc)
+ * Each intermediate is formed from its definition, then every density element
+ * d_abic is assembled from the eight terms and contracted.  Layouts: L1, R1
+ * [o][v] (L1[m*v+a] = L^a_m); L2, T, R2 [o][o][v][v] (L2[((i*o+j)*v+a)*v+b] =
+ * L_ij^ab); Zvv, Wab [v][v][n]; Zov, Wic [o][v][n] (Zov[(i*v+c)*n+K] = Z^K_ic).
+ */
+typedef struct {
+    int64_t o, v;
+    double R0;
+    const double *L1, *L2, *T, *R1, *R2;
+    double *X, *V, *Y, *Yt, *W, *B;
+} abic_ctx;
+
+static double a2(const abic_ctx* q, const double* A, int64_t i, int64_t j, int64_t a, int64_t b) {
+    return A[((i * q->o + j) * q->v + a) * q->v + b];
+}
+static double t_tilde(const abic_ctx* q, int64_t i, int64_t j, int64_t a, int64_t b) {
+    return 2.0 * a2(q, q->T, i, j, a, b) - a2(q, q->T, j, i, a, b);
+}
+static double r_tilde(const abic_ctx* q, int64_t i, int64_t j, int64_t a, int64_t b) {
+    const double r = a2(q, q->R2, i, j, a, b);
+    return (i == j && a == b) ? 2.0 * r : r;
+}
+
+static double abic_density(const abic_ctx* q, int64_t a, int64_t b, int64_t i, int64_t c) {
+    const int64_t o = q->o, v = q->v;
+    double d = 0.0;
+    for (int64_t m = 0; m < o; ++m) {
+        const double La = q->L1[m * v + a];
+        d += q->R0 * La * t_tilde(q, i, m, c, b);                                       /* (1) */
+        d += La * (2.0 * r_tilde(q, m, i, b, c) - r_tilde(q, m, i, c, b));              /* (2) */
+        d += q->W[a * o + m] * t_tilde(q, m, i, b, c);                                   /* (5) */
+    }
+    d += 2.0 * q->X[a * v + b] * q->R1[i * v + c];                                      /* (3) */
+    for (int64_t k = 0; k < o; ++k) {
+        const int64_t akbi = ((a * o + k) * v + b) * o + i;
+        d -= (q->V[akbi] + q->Y[akbi]) * q->R1[k * v + c];                               /* (4) */
+        d += q->Yt[((a * o + k) * v + c) * o + i] * q->R1[k * v + b];                    /* (7) */
+    }
+    for (int64_t m = 0; m < o; ++m)
+        for (int64_t nn = 0; nn < o; ++nn)
+            d -= q->B[((i * v + a) * o + m) * o + nn] * a2(q, q->T, m, nn, b, c);       /* (6) */
+    d -= q->X[a * v + c] * q->R1[i * v + b];                                            /* (8) */
+    return d;
+}
+
+int oracle_ov3_abic(int64_t o, int64_t v, int64_t n, double R0, const double* L1, const double* L2, const double* T,
+                    const double* R1, const double* R2, const double* Zvv, const double* Zov, double* Wab,
+                    double* Wic) {
+    if (bad_dims(o, v, n) || !L1 || !L2 || !T || !R1 || !R2 || !Zvv || !Zov || !Wab || !Wic) return -1;
+    abic_ctx q = {o, v, R0, L1, L2, T, R1, R2, NULL, NULL, NULL, NULL, NULL, NULL};
+    const int64_t ovov = o * v * o * v;
+    q.X = (double*)calloc((size_t)(v * v), sizeof(double));
+    q.V = (double*)calloc((size_t)ovov, sizeof(double));
+    q.Y = (double*)calloc((size_t)ovov, sizeof(double));
+    q.Yt = (double*)calloc((size_t)ovov, sizeof(double));
+    q.W = (double*)calloc((size_t)(v * o), sizeof(double));
+    q.B = (double*)calloc((size_t)(o * v * o * o), sizeof(double));
+    int rc = 0;
+    if (!q.X || !q.V || !q.Y || !q.Yt || !q.W || !q.B) {
+        rc = -1;
+        goto done;
+    }
+#pragma omp parallel for schedule(static)
+    for (int64_t a = 0; a < v; ++a) {
+        for (int64_t b = 0; b < v; ++b) {  /* X_ab = L_kl^ad t_kl^bd */
+            double s = 0.0;
+            for (int64_t k = 0; k < o; ++k)
+                for (int64_t l = 0; l < o; ++l)
+                    for (int64_t d = 0; d < v; ++d) s += a2(&q, L2, k, l, a, d) * a2(&q, T, k, l, b, d);
+            q.X[a * v + b] = s;
+        }
+        for (int64_t m = 0; m < o; ++m) {  /* W_am = L_mk^ad R^d_k */
+            double s = 0.0;
+            for (int64_t k = 0; k < o; ++k)
+                for (int64_t d = 0; d < v; ++d) s += a2(&q, L2, m, k, a, d) * R1[k * v + d];
+            q.W[a * o + m] = s;
+        }
+        for (int64_t k = 0; k < o; ++k)
+            for (int64_t b = 0; b < v; ++b)
+                for (int64_t i = 0; i < o; ++i) {
+                    double sv = 0.0, sy = 0.0, st = 0.0;
+                    for (int64_t l = 0; l < o; ++l)
+                        for (int64_t e = 0; e < v; ++e) {
+                            sv += a2(&q, L2, l, k, a, e) * a2(&q, T, l, i, b, e);   /* V_akbi */
+                            sy += a2(&q, L2, k, l, a, e) * a2(&q, T, i, l, b, e);   /* Y_akbi */
+                            st += a2(&q, L2, l, k, e, a) * t_tilde(&q, l, i, e, b); /* Yt_akbi (b as c) */
+                        }
+                    const int64_t x = ((a * o + k) * v + b) * o + i;
+                    q.V[x] = sv;
+                    q.Y[x] = sy;
+                    q.Yt[x] = st;
+                }
+    }
+#pragma omp parallel for collapse(2) schedule(static)
+    for (int64_t i = 0; i < o; ++i)
+        for (int64_t a = 0; a < v; ++a)
+            for (int64_t m = 0; m < o; ++m)
+                for (int64_t nn = 0; nn < o; ++nn) {  /* B_iamn = L_mn^ad R^d_i */
+                    double s = 0.0;
+                    for (int64_t d = 0; d < v; ++d) s += a2(&q, L2, m, nn, a, d) * R1[i * v + d];
+                    q.B[((i * v + a) * o + m) * o + nn] = s;
+                }
+#pragma omp parallel for schedule(dynamic, 1)
+    for (int64_t a = 0; a < v; ++a)
+        for (int64_t b = 0; b < v; ++b) {
+            double* w = Wab + (a * v + b) * n;
+            for (int64_t K = 0; K < n; ++K) w[K] = 0.0;
+            for (int64_t i = 0; i < o; ++i)
+                for (int64_t c = 0; c < v; ++c) {
+                    const double d = abic_density(&q, a, b, i, c);
+                    const double* z = Zov + (i * v + c) * n;
+                    for (int64_t K = 0; K < n; ++K) w[K] += d * z[K];
+                }
+        }
+#pragma omp parallel for collapse(2) schedule(dynamic, 1)
+    for (int64_t i = 0; i < o; ++i)
+        for (int64_t c = 0; c < v; ++c) {
+            double* w = Wic + (i * v + c) * n;
+            for (int64_t K = 0; K < n; ++K) w[K] = 0.0;
+            for (int64_t a = 0; a < v; ++a)
+                for (int64_t b = 0; b < v; ++b) {
+                    const double d = abic_density(&q, a, b, i, c);
+                    const double* z = Zvv + (a * v + b) * n;
+                    for (int64_t K = 0; K < n; ++K) w[K] += d * z[K];
+                }
+        }
+done:
+    free(q.X);
+    free(q.V);
+    free(q.Y);
+    free(q.Yt);
+    free(q.W);
+    free(q.B);
+    return rc;
+}

@@ -24,7 +24,7 @@ __all__ = [
     "build", "load", "forward", "adjoint", "forward_range", "adjoint_range", "R_sample",
     "X_sample", "tau_gradient", "tau_gradient_range", "w_intermediate", "w_intermediate_range",
     "metric_contraction", "metric_contraction_pairs", "back_transform", "back_transform_range",
-    "excited_amplitudes", "ov3_abci", "ov3_abci_wab", "ov3_abci_wci", "mp2_amplitudes", "amplitude_update", "make_inputs",
+    "excited_amplitudes", "ov3_abci", "ov3_abci_wab", "ov3_abci_wci", "ov3_abic", "mp2_amplitudes", "amplitude_update", "make_inputs",
     "num_threads",
     "set_num_threads", "flops_forward", "flops_adjoint", "matrix",
 ]
@@ -62,6 +62,7 @@ def load():
         lib.oracle_ov3_abci_wab.argtypes = [i64, i64, i64, dp, dp, dp, i64, vp, dp]
         lib.oracle_ov3_abci_wci.argtypes = [i64, i64, i64, dp, dp, dp, i64, vp, dp]
         lib.oracle_metric_contraction_pairs.argtypes = [i64, i64, dp, dp, dp]
+        lib.oracle_ov3_abic.argtypes = [i64, i64, i64, ctypes.c_double, dp, dp, dp, dp, dp, dp, dp, dp, dp]
         lib.oracle_mp2_amplitudes.argtypes = [i64, i64, i64, dp, dp, dp]
         lib.oracle_amplitude_update.argtypes = [i64, i64, dp, dp, dp]
         lib.oracle_num_threads.restype = ctypes.c_int
@@ -69,7 +70,7 @@ def load():
         for f in ("oracle_ladder_forward_range", "oracle_ladder_adjoint_range", "oracle_ladder_R_sample",
                   "oracle_ladder_X_sample", "oracle_ladder_tau_gradient_range", "oracle_w_intermediate_range",
                   "oracle_metric_contraction", "oracle_back_transform_range", "oracle_excited_amplitudes",
-                  "oracle_ov3_abci_wab", "oracle_ov3_abci_wci", "oracle_metric_contraction_pairs",
+                  "oracle_ov3_abci_wab", "oracle_ov3_abci_wci", "oracle_metric_contraction_pairs", "oracle_ov3_abic",
                   "oracle_mp2_amplitudes",
                   "oracle_amplitude_update"):
             getattr(lib, f).restype = ctypes.c_int
@@ -233,6 +234,18 @@ def ov3_abci(o, v, n, L2, R1, Zvv, Zvo):
     ci = np.array([(c, i) for c in range(v) for i in range(o)], dtype=np.int64)
     return (ov3_abci_wab(o, v, n, L2, R1, Zvo, ab).reshape(v, v, n),
             ov3_abci_wci(o, v, n, L2, R1, Zvv, ci).reshape(v, o, n))
+
+
+def ov3_abic(o, v, n, R0, L1, L2, T, R1, R2, Zvv, Zov):
+    """(Wab [v][v][n], Wic [o][v][n]): both contributions of the excited-state OV^3 block d_abic."""
+    L1 = _f64(L1, (o, v)); R1 = _f64(R1, (o, v))
+    L2 = _f64(L2, (o, o, v, v)); T = _f64(T, (o, o, v, v)); R2 = _f64(R2, (o, o, v, v))
+    Zvv = _f64(Zvv, (v, v, n)); Zov = _f64(Zov, (o, v, n))
+    Wab, Wic = np.zeros((v, v, n)), np.zeros((o, v, n))
+    if load().oracle_ov3_abic(o, v, n, float(R0), _p(L1), _p(L2), _p(T), _p(R1), _p(R2), _p(Zvv), _p(Zov),
+                              _p(Wab), _p(Wic)) != 0:
+        raise RuntimeError("oracle_ov3_abic failed")
+    return Wab, Wic
 
 
 def R_sample(o, v, n, L, tau, ab):

@@ -481,6 +481,152 @@ def test_ov3_abci_integer_exact(oracle_lib):
     assert np.array_equal(oracle_lib.ov3_abci_wci(o, v, n, L2, R1, Zvv, ci), c1[ci[:, 0], ci[:, 1]])
 
 
+# ---------------------------------------------------------------- excited-state OV^3 density d_abic
+@pytest.fixture(params=["c", "matrix"])
+def abic(request, oracle_lib):
+    """(Wab, Wic) of d_abic from the C and the numpy oracle."""
+    import oracle
+    return oracle_lib.ov3_abic if request.param == "c" else oracle.matrix.ov3_abic
+
+
+def abic_inputs(seed, o, v, n):
+    g = np.random.default_rng(seed)
+    return dict(R0=0.625, L1=g.standard_normal((o, v)), L2=g.standard_normal((o, o, v, v)),
+                T=g.standard_normal((o, o, v, v)), R1=g.standard_normal((o, v)), R2=g.standard_normal((o, o, v, v)),
+                Zvv=g.standard_normal((v, v, n)), Zov=g.standard_normal((o, v, n)))
+
+
+def _abic(f, o, v, n, x):
+    return f(o, v, n, x["R0"], x["L1"], x["L2"], x["T"], x["R1"], x["R2"], x["Zvv"], x["Zov"])
+
+
+def test_ov3_abic_ground_state_block(abic):
+    """R^a_i = R_ij^ab = 0 leaves the ground-state block d_abic = L^a_m t~_im^cb R_0 (Appendix A):
+    a unit L^a0_m0 with a unit t_i0m0^c0b0 gives d = 2 R_0 at (a0, b0, i0, c0) only, and a unit
+    t_m0i0^c0b0 gives -R_0 there; the W's are then that number times one Z row."""
+    o, v, n = 3, 4, 5
+    x = abic_inputs(130, o, v, n)
+    x["R1"], x["R2"], x["L2"] = np.zeros((o, v)), np.zeros((o, o, v, v)), np.zeros((o, o, v, v))
+    m0, a0, i0, b0, c0 = 1, 2, 0, 3, 1
+    x["L1"] = np.zeros((o, v)); x["L1"][m0, a0] = 1.0
+    for (pos, dval) in [((i0, m0, c0, b0), 2.0), ((m0, i0, c0, b0), -1.0)]:
+        x["T"] = np.zeros((o, o, v, v)); x["T"][pos] = 1.0
+        Wab, Wic = _abic(abic, o, v, n, x)
+        ref_ab = np.zeros((v, v, n)); ref_ab[a0, b0] = dval * x["R0"] * x["Zov"][i0, c0]
+        ref_ic = np.zeros((o, v, n)); ref_ic[i0, c0] = dval * x["R0"] * x["Zvv"][a0, b0]
+        assert np.array_equal(Wab, ref_ab) and np.array_equal(Wic, ref_ic), pos
+
+
+def test_ov3_abic_doubles_term(abic):
+    """R_0 = 0, t = 0, R^a_i = 0 leaves L^a_m (2 R~_mi^bc - R~_mi^cb): a unit R_m0i0^b0c0 (b0 != c0)
+    gives 2 at (a0, b0, i0, c0) and -1 at (a0, c0, i0, b0); a unit diagonal R_m0m0^bb counts
+    twice in R~ and gives 2*2 - 2 = 2 at (a0, b, m0, b)."""
+    o, v, n = 3, 4, 2
+    x = abic_inputs(131, o, v, n)
+    x["R0"], x["T"], x["R1"] = 0.0, np.zeros((o, o, v, v)), np.zeros((o, v))
+    m0, a0 = 2, 1
+    x["L1"] = np.zeros((o, v)); x["L1"][m0, a0] = 1.0
+    cases = [((m0, 0, 3, 1), [((a0, 3, 0, 1), 2.0), ((a0, 1, 0, 3), -1.0)]),
+             ((m0, m0, 2, 2), [((a0, 2, m0, 2), 2.0)])]
+    for pos, dens in cases:
+        x["R2"] = np.zeros((o, o, v, v)); x["R2"][pos] = 1.0
+        Wab, Wic = _abic(abic, o, v, n, x)
+        ref_ab, ref_ic = np.zeros((v, v, n)), np.zeros((o, v, n))
+        for (a, b, i, c), dv in dens:
+            ref_ab[a, b] += dv * x["Zov"][i, c]
+            ref_ic[i, c] += dv * x["Zvv"][a, b]
+        assert np.array_equal(Wab, ref_ab) and np.array_equal(Wic, ref_ic), pos
+
+
+def test_ov3_abic_table_route(abic):
+    """The W_ab and W_ic expressions of Sec. II B, built here from its table of intermediates
+    (X_ab, V, Y, W_am, B_iamn, and P^K, P_ik^K, P_ai^K, O^J_ai, Q^K, K_ik^K, U_bm^K, S_iacb), give
+    what the oracle gets from the Appendix A density.  Readings: the printed 2 Q_ak^K R^b_k
+    (and 2 Y_akci P_ak^K) is taken with Yt_akci, the intermediate of term (7) of d_abic; C^K
+    is the table's Q^K = X_ab Z_ab^K; O_bm^K is L^a_m Z_ab^K; the R_2 in Yt_bm^K(U) is R~_2."""
+    o, v, n = 3, 5, 4
+    x = abic_inputs(132, o, v, n)
+    Wab, Wic = _abic(abic, o, v, n, x)
+    L1, L2, T, R1, R2, R0, Zvv, Zov = (x[k] for k in ("L1", "L2", "T", "R1", "R2", "R0", "Zvv", "Zov"))
+    e = np.einsum
+    tt = 2.0 * T - T.transpose(1, 0, 2, 3)
+    Rt = R2 * (1.0 + e("ij,ab->ijab", np.eye(o), np.eye(v)))
+    X = e("klad,klbd->ab", L2, T)
+    VY = e("lkae,libe->akbi", L2, T) + e("klad,ilbd->akbi", L2, T)
+    Yt = e("lkea,liec->akci", L2, tt)
+    Wam = e("mkad,kd->am", L2, R1)
+    B = e("mnad,id->iamn", L2, R1)
+    S = e("iamn,mnbc->iacb", B, T)                       # S_iacb = B_iamn t_mn^bc = K_icab
+    A = R0 * tt.transpose(1, 0, 2, 3) + 2.0 * Rt.transpose(0, 1, 3, 2) - Rt   # A[m,i,c,b] for L^a_m
+    Ytb_U = e("micb,icK->bmK", A, Zov)                   # Yt_bm^K(U): sum_ic (...)_im^cb Z_ic^K
+    Ytb_T = e("mibc,icK->bmK", tt, Zov)                  # sum_ic t~_mi^bc Z_ic^K
+    PK = e("ic,icK->K", R1, Zov)
+    Oai = e("ac,icK->aiK", X, Zov)
+    Pik = e("kc,icK->ikK", R1, Zov)
+    Qak = e("akci,icK->akK", Yt, Zov)
+    ref_ab = (e("ma,bmK->abK", L1, Ytb_U) + 2.0 * e("ab,K->abK", X, PK) - e("aiK,ib->abK", Oai, R1)
+              - e("akbi,ikK->abK", VY, Pik) + e("akK,kb->abK", Qak, R1) + e("am,bmK->abK", Wam, Ytb_T)
+              - e("iacb,icK->abK", S, Zov))
+    Obm = e("ma,abK->bmK", L1, Zvv)
+    QK = e("ab,abK->K", X, Zvv)
+    Pai = e("ib,abK->aiK", R1, Zvv)
+    Kik = e("akbi,abK->ikK", VY, Zvv)
+    Ubm = e("am,abK->bmK", Wam, Zvv)
+    ref_ic = (e("micb,bmK->icK", A, Obm) + 2.0 * e("K,ic->icK", QK, R1) - e("ac,aiK->icK", X, Pai)
+              - e("kc,ikK->icK", R1, Kik) + e("akci,akK->icK", Yt, e("kb,abK->akK", R1, Zvv))
+              + e("mibc,bmK->icK", tt, Ubm) - e("iacb,abK->icK", S, Zvv))
+    np.testing.assert_allclose(Wab, ref_ab, rtol=0, atol=1e-12 * np.abs(ref_ab).max())
+    np.testing.assert_allclose(Wic, ref_ic, rtol=0, atol=1e-12 * np.abs(ref_ic).max())
+
+
+def test_ov3_abic_identity_gradient_linearity(abic):
+    """sum Zvv*Wab = sum Zov*Wic (both are sum_abic d_abic (ab|ic) with (ab|ic) = sum_K Zvv^K_ab
+    Zov^K_ic); central differences of that number in Zov give Wic; d is linear in the right vector
+    (R_0, R^a_i, R_ij^ab) and in the left one (L^a_m, L_ij^ab): the three parts of R add up, and
+    doubling either vector doubles W exactly."""
+    o, v, n = 3, 4, 3
+    x = abic_inputs(133, o, v, n)
+    Wab, Wic = _abic(abic, o, v, n, x)
+    s_ab, s_ic = np.sum(x["Zvv"] * Wab), np.sum(x["Zov"] * Wic)
+    assert abs(s_ab - s_ic) <= 1e-13 * np.sum(np.abs(x["Zvv"] * Wab))
+
+    def energy(Zov):
+        y = dict(x); y["Zov"] = Zov
+        return np.sum(x["Zvv"] * _abic(abic, o, v, n, y)[0])
+
+    for (i, c, K) in [(0, 0, 0), (2, 3, 2), (1, 2, 1)]:
+        h = np.zeros_like(x["Zov"]); h[i, c, K] = 0.5
+        fd = (energy(x["Zov"] + h) - energy(x["Zov"] - h)) / 1.0
+        assert abs(fd - Wic[i, c, K]) <= 1e-12 * np.abs(Wic).max(), (i, c, K)
+    parts = []
+    for keep in ("R0", "R1", "R2"):
+        y = dict(x)
+        for k in ("R0", "R1", "R2"):
+            if k != keep:
+                y[k] = 0.0 if k == "R0" else np.zeros_like(x[k])
+        parts.append(_abic(abic, o, v, n, y))
+    np.testing.assert_allclose(sum(p[0] for p in parts), Wab, rtol=0, atol=1e-13 * np.abs(Wab).max())
+    np.testing.assert_allclose(sum(p[1] for p in parts), Wic, rtol=0, atol=1e-13 * np.abs(Wic).max())
+    y = dict(x); y["R0"], y["R1"], y["R2"] = 2 * x["R0"], 2 * x["R1"], 2 * x["R2"]
+    a2, c2 = _abic(abic, o, v, n, y)
+    assert np.array_equal(a2, 2 * Wab) and np.array_equal(c2, 2 * Wic)
+    y = dict(x); y["L1"], y["L2"] = 2 * x["L1"], 2 * x["L2"]
+    a2, c2 = _abic(abic, o, v, n, y)
+    assert np.array_equal(a2, 2 * Wab) and np.array_equal(c2, 2 * Wic)
+
+
+def test_ov3_abic_integer_exact(oracle_lib):
+    """Small integer inputs: both oracles are exact and agree bit for bit."""
+    import oracle
+    o, v, n = 3, 6, 4
+    g = np.random.default_rng(134)
+    ints = lambda *s: g.integers(-2, 3, s).astype(float)
+    args = (2.0, ints(o, v), ints(o, o, v, v), ints(o, o, v, v), ints(o, v), ints(o, o, v, v), ints(v, v, n), ints(o, v, n))
+    a1, c1 = oracle_lib.ov3_abic(o, v, n, *args)
+    a2, c2 = oracle.matrix.ov3_abic(o, v, n, *args)
+    assert np.array_equal(a1, a2) and np.array_equal(c1, c2)
+
+
 def test_metric_contraction_pairs(oracle_lib):
     """Over v^2 pairs it is the virtual-virtual contraction; a rank-one Z, W gives one entry."""
     v, n = 4, 3
