@@ -378,8 +378,32 @@ def main():
                            "err_sample_Wab": ea, "err_sample_Wci": ec,
                            "identity_rel": abs(s_ab - s_ci) / float((L * Wab).abs().sum())}
         del Wab, Wci, th_
-        print("bench: next rows: tau gradient %.1f s, V %.1f ms, back-transform %.1f ms, OV3 d_abci %.1f ms"
-              % (mst / 1e3, msv, msb, mso), file=sys.stderr, flush=True)
+        # excited-state OV^3 block d_abic with L_2 := tbar, t := tau, R_2 := R (the ladder output), seeded
+        # singles L_1, R_1 and R_0; check: sum Zvv*Wab = sum Zov*Wic (Zvv := L, Zov := the seeded block)
+        del ws
+        torch.cuda.empty_cache()
+        L1 = torch.randn((o, v), dtype=torch.float64, device=dev, generator=gen) * 0.1
+        Zov = Zvo.view(v, o, n).permute(1, 0, 2).contiguous()
+        del Zvo
+        ws = torch.empty(P.ov3_abic_workspace_size(o, v, n), dtype=torch.uint8, device=dev)
+        Wab, Wic = torch.empty_like(X), torch.empty((o, v, n), dtype=torch.float64, device=dev)
+        torch.cuda.synchronize()
+        ev0.record(stream)
+        P.ov3_abic(0.25, L1, tbar, tau, R1, R, L, Zov, o=o, v=v, n=n, Wab=Wab, Wic=Wic, ws=ws)
+        ev1.record(stream)
+        torch.cuda.synchronize()
+        msi = ev0.elapsed_time(ev1)
+        # GEMM flops above o v^2 n: V+Y, Yt and S (8 o^3 v^3), X_ab, B_iamn, the S contractions of
+        # both sides (4 o v^3 n) and the eight (o v)^2 n contractions of terms (1), (2), (4), (5), (7)
+        Fi = (8.0 * o ** 3 * v ** 3 + 2.0 * o ** 2 * v ** 3 + 2.0 * o ** 3 * v ** 2 + 4.0 * o * v ** 3 * n
+              + 16.0 * o * o * v * v * n)
+        s_ab, s_ic = float((L * Wab).sum()), float((Zov * Wic).sum())
+        nxt["ov3_abic"] = {"ms": msi, "flops": Fi, "tflops": Fi / (msi * 1e-3) / 1e12,
+                           "identity_rel": abs(s_ab - s_ic) / float((L * Wab).abs().sum())}
+        del Wab, Wic, Zov, ws
+        torch.cuda.empty_cache()
+        print("bench: next rows: tau gradient %.1f s, V %.1f ms, back-transform %.1f ms, OV3 d_abci %.1f ms, "
+              "OV3 d_abic %.1f s" % (mst / 1e3, msv, msb, mso, msi / 1e3), file=sys.stderr, flush=True)
 
     cpu = None
     errs = {}

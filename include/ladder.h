@@ -241,6 +241,31 @@ int ladder_ov3_abci(int64_t o, int64_t v, int64_t n, const double* L2, const dou
                     void* stream);
 
 /*
+ * Excited-state OV^3 density block d_abic (Appendix A, excited-state densities)
+ * and its two contributions to the three-index intermediate (Sec. II B):
+ *   Wab^K_ab = beta Wab + alpha sum_ic d_abic Z^K_ic,  Wic^K_ic = beta Wic + alpha sum_ab d_abic Z^K_ab,
+ *   d_abic = R_0 L^a_m t~_im^cb + L^a_m (2 R~_mi^bc - R~_mi^cb) + 2 X_ab R^c_i
+ *          - (V_akbi + Y_akbi) R^c_k + L_mk^ad t~_mi^bc R^d_k - L_mn^ad t_mn^bc R^d_i
+ *          + Yt_akci R^b_k - X_ac R^b_i
+ * with t~_ij^ab = 2 t_ij^ab - t_ji^ab, R~_ij^ab = R_ij^ab (1 + [i=j][a=b]) and the
+ * intermediates X_ab = L_kl^ad t_kl^bd, V_akbi = L_lk^ae t_li^be, Y_akbi = L_kl^ad t_il^bd,
+ * Yt_akci = L_mk^ea t~_mi^ec of Sec. II B and Appendix A (C_2 = t).  The density is
+ * never formed: each term is contracted through its own intermediates (the o^3 v^3
+ * ones, V + Y, Yt and S_iacb = B_iamn t_mn^bc, are FP64 MFMA GEMMs; S is formed for
+ * eight occupied indices at a time).  Inputs (device, row-major FP64): L1, R1 [o][v]
+ * (L1[m*v+a] = L^a_m); L2, T, R2 [o][o][v][v] (L2[((i*o+j)*v+a)*v+b] = L_ij^ab);
+ * Zvv, Wab [v][v][n]; Zov, Wic [o][v][n] (Zov[(i*v+c)*n+K] = Z^K_ic).  Either output
+ * may be NULL to skip that side (Wab needs Zov, Wic needs Zvv).  With beta == 0 the
+ * outputs are not read.  Workspace: ladder_ov3_abic_workspace_size bytes, 256-byte
+ * aligned (three o^2 v^2 buffers, o^3 v, 8 v^3, v^2 n and a few [o][v][n] arrays).
+ * No input may overlap an output or the workspace; the outputs may not overlap.
+ */
+int ladder_ov3_abic_workspace_size(int64_t o, int64_t v, int64_t n, size_t* bytes);
+int ladder_ov3_abic(int64_t o, int64_t v, int64_t n, double R0, const double* L1, const double* L2, const double* T,
+                    const double* R1, const double* R2, const double* Zvv, const double* Zov, double alpha, double beta,
+                    double* Wab, double* Wic, void* ws, size_t ws_bytes, void* stream);
+
+/*
  * ladder_metric_contraction over any number of index pairs (the two-index
  * intermediate V_MN = Z^M_ab W^N_ab + Z^M_ci W^N_ci of Sec. II B has a
  * virtual-occupied part):  V = beta * V + alpha * sum_p Z[p][M] W[p][N], with

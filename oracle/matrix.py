@@ -122,27 +122,28 @@ def ov3_abic(o, v, n, R0, L1, L2, T, R1, R2, Zvv, Zov):
     """Both W contributions of the excited-state OV^3 density d_abic (same eight terms and
     intermediates as the C version), the density formed in full with einsum and contracted."""
     f = lambda x, s: np.ascontiguousarray(x, dtype=np.float64).reshape(s)
+    ein = lambda spec, *ops: np.einsum(spec, *ops, optimize=True)   # library contractions as steps
     L1, R1 = f(L1, (o, v)), f(R1, (o, v))
     L2, T, R2 = f(L2, (o, o, v, v)), f(T, (o, o, v, v)), f(R2, (o, o, v, v))
     Zvv, Zov = f(Zvv, (v, v, n)), f(Zov, (o, v, n))
     tt = 2.0 * T - T.transpose(1, 0, 2, 3)                      # t~_ij^ab
     eye_o, eye_v = np.eye(o), np.eye(v)
-    Rt = R2 * (1.0 + np.einsum("ij,ab->ijab", eye_o, eye_v))      # R~_ij^ab
-    X = np.einsum("klad,klbd->ab", L2, T)
-    V = np.einsum("lkae,libe->akbi", L2, T)
-    Y = np.einsum("klad,ilbd->akbi", L2, T)
-    Yt = np.einsum("lkea,liec->akci", L2, tt)
-    W = np.einsum("mkad,kd->am", L2, R1)
-    B = np.einsum("mnad,id->iamn", L2, R1)
-    d = (R0 * np.einsum("ma,imcb->abic", L1, tt)
-         + np.einsum("ma,mibc->abic", L1, 2.0 * Rt)
-         - np.einsum("ma,micb->abic", L1, Rt)
-         + 2.0 * np.einsum("ab,ic->abic", X, R1)
-         - np.einsum("akbi,kc->abic", V + Y, R1)
-         + np.einsum("am,mibc->abic", W, tt)
-         - np.einsum("iamn,mnbc->abic", B, T)
-         + np.einsum("akci,kb->abic", Yt, R1)
-         - np.einsum("ac,ib->abic", X, R1))
-    Wab = np.einsum("abic,icK->abK", d, Zov)
-    Wic = np.einsum("abic,abK->icK", d, Zvv)
+    Rt = R2 * (1.0 + ein("ij,ab->ijab", eye_o, eye_v))      # R~_ij^ab
+    X = ein("klad,klbd->ab", L2, T)
+    V = ein("lkae,libe->akbi", L2, T)
+    Y = ein("klad,ilbd->akbi", L2, T)
+    Yt = ein("lkea,liec->akci", L2, tt)
+    W = ein("mkad,kd->am", L2, R1)
+    B = ein("mnad,id->iamn", L2, R1)
+    d = (R0 * ein("ma,imcb->abic", L1, tt)
+         + ein("ma,mibc->abic", L1, 2.0 * Rt)
+         - ein("ma,micb->abic", L1, Rt)
+         + 2.0 * ein("ab,ic->abic", X, R1)
+         - ein("akbi,kc->abic", V + Y, R1)
+         + ein("am,mibc->abic", W, tt)
+         - ein("iamn,mnbc->abic", B, T)
+         + ein("akci,kb->abic", Yt, R1)
+         - ein("ac,ib->abic", X, R1))
+    Wab = ein("abic,icK->abK", d, Zov)
+    Wic = ein("abic,abK->icK", d, Zvv)
     return Wab, Wic

@@ -224,6 +224,25 @@ struct EpiStrided {
     }
 };
 
+// General placement: m = x1*X2 + x2, n = y1*Y2 + y2 and
+// out[x1*sx1 + x2*sx2 + y1*sy1 + y2*sy2] = alpha*C + beta*out, for results written into
+// a slab of a larger array (strides independent of the index decomposition).
+struct EpiPlace {
+    double* out;
+    int64_t X2, Y2;
+    int64_t sx1, sx2, sy1, sy2;
+    double alpha, beta;
+    struct Local {};
+    __device__ Local begin() const { return {}; }
+    __device__ void put(Local&, int64_t m, int64_t n, double c) const {
+        const int64_t x1 = m / X2, x2 = m - x1 * X2;
+        const int64_t y1 = n / Y2, y2 = n - y1 * Y2;
+        double* p = out + x1 * sx1 + x2 * sx2 + y1 * sy1 + y2 * sy2;
+        *p = beta == 0.0 ? alpha * c : alpha * c + beta * *p;
+    }
+    __device__ void finish(Local&, int64_t) const {}
+};
+
 // First-order amplitudes: m = i*v + a, n = j*v + b,
 // t[((i*o + j)*v + a)*v + b] = C / ((eps_i + eps_j) - (eps_a + eps_b)).
 struct EpiMP2 {

@@ -602,6 +602,65 @@ __global__ __launch_bounds__(256) void ov3_swap_vv_kernel(const double* __restri
     }
 }
 
+// Reordering with an optional second term: out is walked in its own order over the
+// extents D[0..3] (last index fastest, so the writes are contiguous) and
+//   out[x] = c1 * in[sum_k idx_k s[k]] + c2 * in[sum_k idx_k t[k]]   (second read only if c2 != 0).
+// The host checks that the largest offset of either stride set lies inside `in`.
+struct Perm4 {
+    int64_t D[4], s[4], t[4];
+    double c1, c2;
+};
+__global__ __launch_bounds__(256) void permute4_kernel(const double* __restrict__ in, double* __restrict__ out, Perm4 p) {
+    const int64_t total = p.D[0] * p.D[1] * p.D[2] * p.D[3];
+    for (int64_t x = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; x < total; x += (int64_t)gridDim.x * blockDim.x) {
+        int64_t r = x;
+        const int64_t i3 = r % p.D[3];
+        r /= p.D[3];
+        const int64_t i2 = r % p.D[2];
+        r /= p.D[2];
+        const int64_t i1 = r % p.D[1], i0 = r / p.D[1];
+        double val = p.c1 * in[i0 * p.s[0] + i1 * p.s[1] + i2 * p.s[2] + i3 * p.s[3]];
+        if (p.c2 != 0.0) val += p.c2 * in[i0 * p.t[0] + i1 * p.t[1] + i2 * p.t[2] + i3 * p.t[3]];
+        out[x] = val;
+    }
+}
+
+// Amplitude matrix of the singles-multiplier terms of d_abic, rows (m, b), columns (i, c):
+//   A[(m,b),(i,c)] = R0 (2 t_im^cb - t_mi^cb) + 2 R~_mi^bc - R~_mi^cb,
+//   R~_mi^pq = R_mi^pq (1 + [m = i][p = q]).
+__global__ __launch_bounds__(256) void abic_amp_kernel(double R0, const double* __restrict__ T,
+                                                       const double* __restrict__ R2, double* __restrict__ A,
+                                                       int64_t o, int64_t v) {
+    const int64_t total = o * o * v * v;
+    for (int64_t x = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; x < total; x += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t c = x % v, r1 = x / v;
+        const int64_t i = r1 % o, r2 = r1 / o;
+        const int64_t b = r2 % v, m = r2 / v;
+        const double dg = (m == i && b == c) ? 2.0 : 1.0;
+        const double tt = 2.0 * T[((i * o + m) * v + c) * v + b] - T[((m * o + i) * v + c) * v + b];
+        A[x] = R0 * tt + dg * (2.0 * R2[((m * o + i) * v + b) * v + c] - R2[((m * o + i) * v + c) * v + b]);
+    }
+}
+
+// W_am = sum_kd L_mk^ad R^d_k, stored Wma[m][a]: one 64-lane wave per (m, a).
+__global__ __launch_bounds__(256) void abic_wam_kernel(const double* __restrict__ L2, const double* __restrict__ R1,
+                                                       double* __restrict__ Wma, int64_t o, int64_t v) {
+    const int lane = threadIdx.x & 63;
+    const int64_t waves = (int64_t)gridDim.x * (blockDim.x >> 6);
+    for (int64_t w = (int64_t)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6); w < o * v; w += waves) {
+        const int64_t m = w / v, a = w - m * v;
+        double s = 0.0;
+        for (int64_t k = 0; k < o; ++k) {
+            const double* l = L2 + ((m * o + k) * v + a) * v;
+            const double* r = R1 + k * v;
+            for (int64_t d = lane; d < v; d += 64) s += l[d] * r[d];
+        }
+#pragma unroll
+        for (int off = 32; off > 0; off >>= 1) s += __shfl_xor(s, off);
+        if (lane == 0) Wma[m * v + a] = s;
+    }
+}
+
 // Grid of the tiled packing kernels: tile pairs in x, rows over (y, z).
 dim3 pm_grid(int64_t v, int64_t rows) {
     const int64_t gy = std::min<int64_t>(std::max<int64_t>(rows, 1), 65535);
@@ -1507,6 +1566,300 @@ int ladder_ov3_abci(int64_t o, int64_t v, int64_t n, const double* L2, const dou
         if ((rc = hip_check(launch_gemm<false, false, LADDER_STAGE_OV3>(Lp, ov, XP, n, ov, n, ov, ew, st), "OV3 GEMM launch")))
             return rc;
     }
+    return LADDER_OK;
+}
+
+namespace {
+// Workspace of ladder_ov3_abic (every slot 256-byte aligned):
+//   three o^2 v^2 buffers (reordered operands and the o^2 v^2 intermediates V+Y, Yt and the
+//   amplitude matrices), B_iamn (o^3 v), the S_iacb slab of `g` occupied indices (g v^3),
+//   Zt (v^2 n), eight [o][v][n] or [o][o][n] buffers, Xvv (v^2), W_am (o v), P^K and Q^K (n).
+struct AbicLayout {
+    int64_t g;
+    size_t bufA, bufB, bufC, Bm, S, Zt, Zvo, OX, Pp, Pk, PKI, KK, QY, YA, OA, Xvv, Wma, PK, QK, total;
+};
+int abic_layout(int64_t o, int64_t v, int64_t n, AbicLayout& l) {
+    Sizes s;
+    int rc;
+    if ((rc = check_dims(o, v, n, s))) return rc;
+    int64_t ovn, oon, ooov, vvv;
+    if (!mul_ok(o * v, n, ovn) || !mul_ok(o * o, n, oon) || !mul_ok(o * o, o * v, ooov) || !mul_ok(s.vv, v, vvv) ||
+        ovn > INT64_MAX / 16 || ooov > INT64_MAX / 16)
+        return fail(LADDER_EINVAL, "array sizes overflow 64-bit byte counts");
+    l.g = std::min<int64_t>(o, 8);
+    const int64_t grid_max = (int64_t)1 << 31;
+    const int64_t shapes[][2] = {{v, v}, {o * v, o * v}, {o * v, n}, {s.vv, n}, {o * o, n}, {v, v * n}, {o, v * n},
+                                 {v, o * n}, {o, o * o * v}, {v, s.vv}, {l.g * v, n}, {1, n}};
+    for (auto& sh : shapes)
+        if (tiles(sh[0], sh[1]) >= grid_max) return fail(LADDER_EINVAL, "problem too large for one launch per GEMM");
+    size_t off = 0;
+    auto take = [&](size_t elems) {
+        const size_t at = off;
+        off += align_up(elems * 8);
+        return at;
+    };
+    l.bufA = take((size_t)s.ovv_elems);
+    l.bufB = take((size_t)s.ovv_elems);
+    l.bufC = take((size_t)s.ovv_elems);
+    l.Bm = take((size_t)ooov);
+    l.S = take((size_t)(l.g * vvv));
+    l.Zt = take((size_t)s.vvn);
+    l.Zvo = take((size_t)ovn);
+    l.OX = take((size_t)ovn);
+    l.Pp = take((size_t)ovn);
+    l.Pk = take((size_t)ovn);
+    l.PKI = take((size_t)oon);
+    l.KK = take((size_t)oon);
+    l.QY = take((size_t)ovn);
+    l.YA = take((size_t)ovn);
+    l.OA = take((size_t)ovn);
+    l.Xvv = take((size_t)s.vv);
+    l.Wma = take((size_t)(o * v));
+    l.PK = take((size_t)n);
+    l.QK = take((size_t)n);
+    l.total = off;
+    return LADDER_OK;
+}
+
+// Launches permute4_kernel after checking that both stride sets stay inside `in_elems`.
+int permute4(const double* in, int64_t in_elems, double* out, const Perm4& p, hipStream_t st) {
+    int64_t hi1 = 0, hi2 = 0;
+    for (int k = 0; k < 4; ++k) {
+        if (p.D[k] < 1) return fail(LADDER_EINVAL, "empty reordering");
+        hi1 += (p.D[k] - 1) * p.s[k];
+        hi2 += (p.D[k] - 1) * p.t[k];
+    }
+    if (hi1 >= in_elems || (p.c2 != 0.0 && hi2 >= in_elems)) return fail(LADDER_EINVAL, "reordering out of range");
+    const int64_t total = p.D[0] * p.D[1] * p.D[2] * p.D[3];
+    hipLaunchKernelGGL(permute4_kernel, dim3(grid_for(total)), dim3(256), 0, st, in, out, p);
+    return hip_check(hipGetLastError(), "reordering launch");
+}
+}  // namespace
+
+int ladder_ov3_abic_workspace_size(int64_t o, int64_t v, int64_t n, size_t* bytes) {
+    g_last_error.clear();
+    if (!bytes) return fail(LADDER_EINVAL, "bytes is NULL");
+    AbicLayout l;
+    int rc;
+    if ((rc = abic_layout(o, v, n, l))) return rc;
+    *bytes = l.total;
+    return LADDER_OK;
+}
+
+int ladder_ov3_abic(int64_t o, int64_t v, int64_t n, double R0, const double* L1, const double* L2, const double* T,
+                    const double* R1, const double* R2, const double* Zvv, const double* Zov, double alpha, double beta,
+                    double* Wab, double* Wic, void* ws, size_t ws_bytes, void* stream) {
+    g_last_error.clear();
+    AbicLayout l;
+    int rc;
+    if ((rc = abic_layout(o, v, n, l))) return rc;
+    if (!L1 || !L2 || !T || !R1 || !R2 || !ws) return fail(LADDER_EINVAL, "L1, L2, T, R1, R2 and ws must be non-NULL");
+    if (!Wab && !Wic) return fail(LADDER_EINVAL, "Wab and Wic are both NULL: nothing to compute");
+    if (Wab && !Zov) return fail(LADDER_EINVAL, "Wab needs Zov");
+    if (Wic && !Zvv) return fail(LADDER_EINVAL, "Wic needs Zvv");
+    const void* ptrs[] = {L1, L2, T, R1, R2, Zvv, Zov, Wab, Wic};
+    for (const void* q : ptrs)
+        if (!aligned8(q)) return fail(LADDER_EINVAL, "misaligned pointer (8-byte alignment)");
+    if ((uintptr_t)ws % ALIGN) return fail(LADDER_EINVAL, "misaligned workspace (256-byte alignment)");
+    if (ws_bytes < l.total) return fail(LADDER_EWORKSPACE, "workspace of %zu bytes, %zu needed", ws_bytes, l.total);
+    const int64_t ov = o * v, vv = v * v, on = o * n, vn = v * n, oo = o * o;
+    const int64_t ovvb = oo * vv * 8, ovb = ov * 8, vvnb = vv * n * 8, ovnb = ov * n * 8, wsb = (int64_t)ws_bytes;
+    const void* ins[] = {L1, L2, T, R1, R2, Zvv, Zov};
+    const int64_t inb[] = {ovb, ovvb, ovvb, ovb, ovvb, vvnb, ovnb};
+    for (int k = 0; k < 7; ++k)
+        if (overlap(ins[k], inb[k], ws, wsb) || overlap(Wab, vvnb, ins[k], inb[k]) || overlap(Wic, ovnb, ins[k], inb[k]))
+            return fail(LADDER_EINVAL, "an input overlaps an output or the workspace");
+    if (overlap(Wab, vvnb, ws, wsb) || overlap(Wic, ovnb, ws, wsb) || overlap(Wab, vvnb, Wic, ovnb))
+        return fail(LADDER_EINVAL, "Wab or Wic overlaps the workspace or the other output");
+
+    hipStream_t st = (hipStream_t)stream;
+    char* w = (char*)ws;
+    auto at = [&](size_t off) { return (double*)(w + off); };
+    double *bA = at(l.bufA), *bB = at(l.bufB), *bC = at(l.bufC), *Bm = at(l.Bm), *S = at(l.S), *Zt = at(l.Zt);
+    double *Zvo = at(l.Zvo), *OX = at(l.OX), *Pp = at(l.Pp), *Pk = at(l.Pk), *PKI = at(l.PKI), *KK = at(l.KK);
+    double *QY = at(l.QY), *YA = at(l.YA), *OA = at(l.OA), *Xvv = at(l.Xvv), *Wma = at(l.Wma), *PK = at(l.PK);
+    double* QK = at(l.QK);
+    const int64_t L2n = oo * vv;
+    const bool ab = Wab != nullptr, ic = Wic != nullptr;
+#define ABIC_GEMM(AK, BK, A_, lda, B_, ldb, M, N, K, epi)                                                         \
+    do {                                                                                                           \
+        if ((rc = hip_check(launch_gemm<AK, BK, LADDER_STAGE_OV3>(A_, lda, B_, ldb, M, N, K, epi, st),           \
+                            "OV3 GEMM launch")))                                                                   \
+            return rc;                                                                                             \
+    } while (0)
+
+    // ---- reorderings and the beta scaling of the outputs
+    {
+        StageTimer tm(LADDER_STAGE_OV3_PERMUTE, 0.0, 16.0 * (double)(ov * n + vv * n), st);
+        if (ab) {
+            if (beta == 0.0) hipLaunchKernelGGL(fill_zero_kernel, dim3(grid_for(vv * n)), dim3(256), 0, st, Wab, vv * n);
+            else if (beta != 1.0) hipLaunchKernelGGL(scale_kernel, dim3(grid_for(vv * n)), dim3(256), 0, st, Wab, vv * n, beta);
+            if ((rc = hip_check(hipGetLastError(), "scale launch"))) return rc;
+            // Zvo[c][i][K] = Zov[i][c][K]
+            if ((rc = permute4(Zov, ov * n, Zvo, Perm4{{1, v, o, n}, {0, n, vn, 1}, {0, 0, 0, 0}, 1.0, 0.0}, st))) return rc;
+        }
+        if (ic) {
+            if (beta == 0.0) hipLaunchKernelGGL(fill_zero_kernel, dim3(grid_for(ov * n)), dim3(256), 0, st, Wic, ov * n);
+            else if (beta != 1.0) hipLaunchKernelGGL(scale_kernel, dim3(grid_for(ov * n)), dim3(256), 0, st, Wic, ov * n, beta);
+            if ((rc = hip_check(hipGetLastError(), "scale launch"))) return rc;
+            // Zt[b][a][K] = Zvv[a][b][K]
+            if ((rc = permute4(Zvv, vv * n, Zt, Perm4{{1, v, v, n}, {0, n, vn, 1}, {0, 0, 0, 0}, 1.0, 0.0}, st))) return rc;
+        }
+    }
+    double fl = 0.0, by = 0.0;
+    auto acct = [&](int64_t M, int64_t N, int64_t K) {
+        fl += gemm_flops(M, N, K);
+        by += gemm_bytes(M, N, K);
+    };
+    StageTimer tm(LADDER_STAGE_OV3, 0.0, 0.0, st);
+    // ---- terms (3) and (8): X_ab = L_kl^ad t_kl^bd over rows a, b and columns (kl, d)
+    if ((rc = permute4(L2, L2n, bA, Perm4{{1, v, oo, v}, {0, v, vv, 1}, {0, 0, 0, 0}, 1.0, 0.0}, st))) return rc;
+    if ((rc = permute4(T, L2n, bB, Perm4{{1, v, oo, v}, {0, v, vv, 1}, {0, 0, 0, 0}, 1.0, 0.0}, st))) return rc;
+    {
+        EpiStrided e{Xvv, v, 1.0, 0.0, nullptr, nullptr};
+        ABIC_GEMM(true, true, bA, oo * v, bB, oo * v, v, v, oo * v, e);
+        acct(v, v, oo * v);
+    }
+    if (ab) {
+        // (3): Wab += 2 alpha X_ab P^K, P^K = sum_ic R^c_i Z^K_ic
+        EpiStrided e1{PK, n, 1.0, 0.0, nullptr, nullptr};
+        ABIC_GEMM(true, false, R1, ov, Zov, n, 1, n, ov, e1);
+        EpiStrided e2{Wab, n, 2.0 * alpha, 1.0, nullptr, nullptr};
+        ABIC_GEMM(true, false, Xvv, 1, PK, n, vv, n, 1, e2);
+        // (8): Wab -= alpha R^b_i O_ai^K, O_ai^K = sum_c X_ac Z^K_ic stored OX[i][a][K]
+        EpiSwapMid e3{OX, v, o, n, 1.0, 0.0};
+        ABIC_GEMM(true, false, Xvv, v, Zvo, on, v, on, v, e3);
+        EpiSwapMid e4{Wab, v, v, n, -alpha, 1.0};
+        ABIC_GEMM(false, false, R1, v, OX, vn, v, vn, o, e4);
+        acct(1, n, ov); acct(vv, n, 1); acct(v, on, v); acct(v, vn, o);
+    }
+    if (ic) {
+        // (3): Wic += 2 alpha R^c_i Q^K, Q^K = sum_ab X_ab Z^K_ab
+        EpiStrided e1{QK, n, 1.0, 0.0, nullptr, nullptr};
+        ABIC_GEMM(true, false, Xvv, vv, Zvv, n, 1, n, vv, e1);
+        EpiStrided e2{Wic, n, 2.0 * alpha, 1.0, nullptr, nullptr};
+        ABIC_GEMM(true, false, R1, 1, QK, n, ov, n, 1, e2);
+        // (8): Wic -= alpha X_ac P_ai^K, P_ai^K = sum_b R^b_i Z^K_ab stored Pp[a][i][K]
+        EpiSwapMid e3{Pp, o, v, n, 1.0, 0.0};
+        ABIC_GEMM(true, false, R1, v, Zt, vn, o, vn, v, e3);
+        EpiSwapMid e4{Wic, v, o, n, -alpha, 1.0};
+        ABIC_GEMM(false, false, Xvv, v, Pp, on, v, on, v, e4);
+        // Pk[k][a][K] for term (7)
+        EpiStrided e5{Pk, vn, 1.0, 0.0, nullptr, nullptr};
+        ABIC_GEMM(true, false, R1, v, Zt, vn, o, vn, v, e5);
+        acct(1, n, vv); acct(ov, n, 1); acct(o, vn, v); acct(v, on, v); acct(o, vn, v);
+    }
+    // ---- term (4): VY[a][b][k][i] = V_akbi + Y_akbi
+    //   V: rows (a,k) of L_lk^ae, columns (b,i) of t_li^be, summed over (l,e)
+    if ((rc = permute4(L2, L2n, bA, Perm4{{v, o, o, v}, {v, vv, ov * v, 1}, {0, 0, 0, 0}, 1.0, 0.0}, st))) return rc;
+    if ((rc = permute4(T, L2n, bB, Perm4{{v, o, o, v}, {v, vv, ov * v, 1}, {0, 0, 0, 0}, 1.0, 0.0}, st))) return rc;
+    {
+        EpiSwapMid e{bC, o, v, o, 1.0, 0.0};
+        ABIC_GEMM(true, true, bA, ov, bB, ov, ov, ov, ov, e);
+    }
+    //   Y: rows (a,k) of L_kl^ad, columns (b,i) of t_il^bd, summed over (l,d)
+    if ((rc = permute4(L2, L2n, bA, Perm4{{v, o, o, v}, {v, ov * v, vv, 1}, {0, 0, 0, 0}, 1.0, 0.0}, st))) return rc;
+    if ((rc = permute4(T, L2n, bB, Perm4{{v, o, o, v}, {v, ov * v, vv, 1}, {0, 0, 0, 0}, 1.0, 0.0}, st))) return rc;
+    {
+        EpiSwapMid e{bC, o, v, o, 1.0, 1.0};
+        ABIC_GEMM(true, true, bA, ov, bB, ov, ov, ov, ov, e);
+    }
+    acct(ov, ov, ov); acct(ov, ov, ov);
+    if (ab) {
+        // Wab -= alpha sum_ik VY[(a,b),(k,i)] P_ik^K, P_ik^K = sum_c R^c_k Z^K_ic stored PKI[k][i][K]
+        EpiStrided e1{PKI, on, 1.0, 0.0, nullptr, nullptr};
+        ABIC_GEMM(true, false, R1, v, Zvo, on, o, on, v, e1);
+        EpiStrided e2{Wab, n, -alpha, 1.0, nullptr, nullptr};
+        ABIC_GEMM(true, false, bC, oo, PKI, n, vv, n, oo, e2);
+        acct(o, on, v); acct(vv, n, oo);
+    }
+    if (ic) {
+        // Wic -= alpha sum_k R^c_k K_ik^K, K_ik^K = sum_ab VY[(a,b),(k,i)] Z^K_ab stored KK[k][i][K]
+        EpiStrided e1{KK, n, 1.0, 0.0, nullptr, nullptr};
+        ABIC_GEMM(false, false, bC, oo, Zvv, n, oo, n, vv, e1);
+        EpiSwapMid e2{Wic, v, o, n, -alpha, 1.0};
+        ABIC_GEMM(false, false, R1, v, KK, on, v, on, o, e2);
+        acct(oo, n, vv); acct(v, on, o);
+    }
+    // ---- term (7): Yt[(k,a),(i,c)] = sum_me L_mk^ea (2 t_mi^ec - t_im^ec)
+    if ((rc = permute4(L2, L2n, bA, Perm4{{o, v, o, v}, {vv, 1, ov * v, v}, {0, 0, 0, 0}, 1.0, 0.0}, st))) return rc;
+    if ((rc = permute4(T, L2n, bB, Perm4{{o, v, o, v}, {vv, 1, ov * v, v}, {ov * v, 1, vv, v}, 2.0, -1.0}, st)))
+        return rc;
+    {
+        EpiStrided e{bC, ov, 1.0, 0.0, nullptr, nullptr};
+        ABIC_GEMM(true, true, bA, ov, bB, ov, ov, ov, ov, e);
+        acct(ov, ov, ov);
+    }
+    if (ab) {
+        // Wab += alpha sum_k R^b_k Q_ak^K, Q_ak^K = sum_ic Yt[(k,a),(i,c)] Z^K_ic stored QY[k][a][K]
+        EpiStrided e1{QY, n, 1.0, 0.0, nullptr, nullptr};
+        ABIC_GEMM(true, false, bC, ov, Zov, n, ov, n, ov, e1);
+        EpiSwapMid e2{Wab, v, v, n, alpha, 1.0};
+        ABIC_GEMM(false, false, R1, v, QY, vn, v, vn, o, e2);
+        acct(ov, n, ov); acct(v, vn, o);
+    }
+    if (ic) {
+        // Wic += alpha sum_(k,a) Yt[(k,a),(i,c)] P_ak^K
+        EpiStrided e1{Wic, n, alpha, 1.0, nullptr, nullptr};
+        ABIC_GEMM(false, false, bC, ov, Pk, n, ov, n, ov, e1);
+        acct(ov, n, ov);
+    }
+    // ---- terms (1), (2) and (5): sum_m c[m][a] Amp[(m,b),(i,c)] with (c, Amp) = (L^a_m, A) and (W_am, t~_mi^bc)
+    hipLaunchKernelGGL(abic_amp_kernel, dim3(grid_for(L2n)), dim3(256), 0, st, R0, T, R2, bA, o, v);
+    if ((rc = hip_check(hipGetLastError(), "amplitude launch"))) return rc;
+    if ((rc = permute4(T, L2n, bB, Perm4{{o, v, o, v}, {ov * v, v, vv, 1}, {vv, v, ov * v, 1}, 2.0, -1.0}, st)))
+        return rc;
+    hipLaunchKernelGGL(abic_wam_kernel, dim3((unsigned)std::min<int64_t>((ov + 3) / 4, 65536)), dim3(256), 0, st, L2, R1,
+                       Wma, o, v);
+    if ((rc = hip_check(hipGetLastError(), "W_am launch"))) return rc;
+    const double* amps[2] = {bA, bB};
+    const double* coef[2] = {L1, Wma};
+    for (int t = 0; t < 2; ++t) {
+        if (ab) {
+            // YA[(m,b)][K] = sum_ic Amp[(m,b),(i,c)] Z^K_ic;  Wab[a][(b,K)] += alpha sum_m coef[m][a] YA[m][(b,K)]
+            EpiStrided e1{YA, n, 1.0, 0.0, nullptr, nullptr};
+            ABIC_GEMM(true, false, amps[t], ov, Zov, n, ov, n, ov, e1);
+            EpiStrided e2{Wab, vn, alpha, 1.0, nullptr, nullptr};
+            ABIC_GEMM(false, false, coef[t], v, YA, vn, v, vn, o, e2);
+            acct(ov, n, ov); acct(v, vn, o);
+        }
+        if (ic) {
+            // OA[m][(b,K)] = sum_a coef[m][a] Z^K_ab;  Wic[(i,c)][K] += alpha sum_(m,b) Amp[(m,b),(i,c)] OA[(m,b)][K]
+            EpiStrided e1{OA, vn, 1.0, 0.0, nullptr, nullptr};
+            ABIC_GEMM(true, false, coef[t], v, Zvv, vn, o, vn, v, e1);
+            EpiStrided e2{Wic, n, alpha, 1.0, nullptr, nullptr};
+            ABIC_GEMM(false, false, amps[t], ov, OA, n, ov, n, ov, e2);
+            acct(o, vn, v); acct(ov, n, ov);
+        }
+    }
+    // ---- term (6): -B_iamn t_mn^bc, B_iamn = sum_d L_mn^ad R^d_i stored Bm[i][(m,n)][a]
+    {
+        EpiStrided e{Bm, oo * v, 1.0, 0.0, nullptr, nullptr};
+        ABIC_GEMM(true, true, R1, v, L2, v, o, oo * v, v, e);
+        acct(o, oo * v, v);
+    }
+    for (int64_t i0 = 0; i0 < o; i0 += l.g) {
+        const int64_t gl = std::min<int64_t>(l.g, o - i0);
+        for (int64_t il = 0; il < gl; ++il) {
+            // S[(a,b)][(il,c)] = sum_mn Bm[i][(m,n)][a] t_mn^bc
+            EpiPlace e{S + il * v, 1, v, l.g * vv, 0, l.g * v, 1, 1.0, 0.0};
+            ABIC_GEMM(false, false, Bm + (i0 + il) * oo * v, v, T, vv, v, vv, oo, e);
+            acct(v, vv, oo);
+        }
+        if (ab) {
+            EpiStrided e{Wab, n, -alpha, 1.0, nullptr, nullptr};
+            ABIC_GEMM(true, false, S, l.g * v, Zov + i0 * vn, n, vv, n, gl * v, e);
+            acct(vv, n, gl * v);
+        }
+        if (ic) {
+            EpiStrided e{Wic + i0 * vn, n, -alpha, 1.0, nullptr, nullptr};
+            ABIC_GEMM(false, false, S, l.g * v, Zvv, n, gl * v, n, vv, e);
+            acct(gl * v, n, vv);
+        }
+    }
+#undef ABIC_GEMM
+    tm.rec.flops = fl;
+    tm.rec.bytes = by;
     return LADDER_OK;
 }
 

@@ -30,7 +30,8 @@ EXPORTS = (
     "ladder_tau_gradient_workspace_size", "ladder_tau_gradient", "ladder_autotune", "ladder_autotune_load",
     "ladder_autotune_reset", "ladder_metric_contraction",
     "ladder_back_transform_workspace_size", "ladder_back_transform", "ladder_excited_amplitudes",
-    "ladder_ov3_abci_workspace_size", "ladder_ov3_abci", "ladder_metric_contraction_pairs",
+    "ladder_ov3_abci_workspace_size", "ladder_ov3_abci", "ladder_ov3_abic_workspace_size", "ladder_ov3_abic",
+    "ladder_metric_contraction_pairs",
     "ladder_mp2_amplitudes", "ladder_amplitude_update", "ladder_batched_workspace_size",
     "ladder_batched", "ladder_strerror", "ladder_last_error", "ladder_shutdown",
     "ladder_profile_start", "ladder_profile_stop",
@@ -109,6 +110,8 @@ def _load():
     lib.ladder_ov3_abci_workspace_size.argtypes = [i64, i64, i64, ctypes.POINTER(sz)]
     lib.ladder_ov3_abci.argtypes = [i64, i64, i64, vp, vp, vp, vp, dbl, dbl, vp, vp, vp, sz, vp]
     lib.ladder_metric_contraction_pairs.argtypes = [i64, i64, vp, vp, dbl, dbl, vp, vp]
+    lib.ladder_ov3_abic_workspace_size.argtypes = [i64, i64, i64, ctypes.POINTER(sz)]
+    lib.ladder_ov3_abic.argtypes = [i64, i64, i64, dbl, vp, vp, vp, vp, vp, vp, vp, dbl, dbl, vp, vp, vp, sz, vp]
     lib.ladder_mp2_amplitudes.argtypes = [i64, i64, i64, vp, vp, vp, vp]
     lib.ladder_amplitude_update.argtypes = [i64, i64, vp, vp, vp, vp]
     lib.ladder_batched_workspace_size.argtypes = [ctypes.c_int, ctypes.POINTER(_CInstance), ctypes.c_uint32, op,
@@ -118,7 +121,8 @@ def _load():
               "ladder_tau_gradient", "ladder_autotune", "ladder_autotune_load", "ladder_metric_contraction",
               "ladder_back_transform_workspace_size",
               "ladder_back_transform", "ladder_excited_amplitudes", "ladder_ov3_abci_workspace_size",
-              "ladder_ov3_abci", "ladder_metric_contraction_pairs", "ladder_mp2_amplitudes",
+              "ladder_ov3_abci", "ladder_ov3_abic_workspace_size", "ladder_ov3_abic", "ladder_metric_contraction_pairs",
+              "ladder_mp2_amplitudes",
               "ladder_amplitude_update", "ladder_batched_workspace_size", "ladder_batched"):
         getattr(lib, f).restype = ctypes.c_int
     lib.ladder_strerror.argtypes = [ctypes.c_int]
@@ -352,6 +356,39 @@ def ov3_abci(L2, R1, Zvv, Zvo, *, o, v, n, Wab=None, Wci=None, alpha=1.0, beta=0
                                    _ptr(Wab) if want_ab else None, _ptr(Wci) if want_ci else None, _ptr(wsb),
                                    wsb.numel() * wsb.element_size(), _stream(stream)))
     return (Wab if want_ab else None), (Wci if want_ci else None)
+
+
+def ov3_abic_workspace_size(o: int, v: int, n: int) -> int:
+    b = ctypes.c_size_t(0)
+    _check(_load().ladder_ov3_abic_workspace_size(o, v, n, ctypes.byref(b)))
+    return b.value
+
+
+def ov3_abic(R0, L1, L2, T, R1, R2, Zvv, Zov, *, o, v, n, Wab=None, Wic=None, alpha=1.0, beta=0.0, want=(True, True),
+             ws=None, stream=None):
+    """Both W contributions of the excited-state OV^3 density d_abic: Wab [v][v][n] (from
+    Zov [o][v][n]) and Wic [o][v][n] (from Zvv [v][v][n]), each beta*W + alpha*W'.
+    L1, R1: [o][v]; L2, T, R2: [o][o][v][v]; R0 a float.  `want` = (ab side, ic side)."""
+    want_ab, want_ic = bool(want[0]), bool(want[1])
+    _need(L1, "L1", (o, v)); _need(R1, "R1", (o, v))
+    for t, name in ((L2, "L2"), (T, "T"), (R2, "R2")):
+        _need(t, name, (o, o, v, v))
+    if want_ab:
+        _need(Zov, "Zov", (o, v, n))
+        if Wab is None:
+            Wab = torch.empty((v, v, n), dtype=torch.float64, device=L2.device)
+        _need(Wab, "Wab", (v, v, n))
+    if want_ic:
+        _need(Zvv, "Zvv", (v, v, n))
+        if Wic is None:
+            Wic = torch.empty((o, v, n), dtype=torch.float64, device=L2.device)
+        _need(Wic, "Wic", (o, v, n))
+    wsb = _workspace(ov3_abic_workspace_size(o, v, n), L2.device, ws)
+    _check(_load().ladder_ov3_abic(o, v, n, float(R0), _ptr(L1), _ptr(L2), _ptr(T), _ptr(R1), _ptr(R2),
+                                   _ptr(Zvv) if want_ic else None, _ptr(Zov) if want_ab else None, float(alpha),
+                                   float(beta), _ptr(Wab) if want_ab else None, _ptr(Wic) if want_ic else None,
+                                   _ptr(wsb), wsb.numel() * wsb.element_size(), _stream(stream)))
+    return (Wab if want_ab else None), (Wic if want_ic else None)
 
 
 def metric_contraction_pairs(Z, W, *, pairs, n, V=None, alpha=1.0, beta=0.0, stream=None):

@@ -163,6 +163,34 @@ def test_ov3_abci_validation():
     assert lib.ladder_metric_contraction_pairs(6, n, FAKE, 2 * FAKE, 1.0, 0.0, FAKE + 8, None) == EINVAL  # V overlaps Z
 
 
+def test_ov3_abic_validation():
+    """ladder_ov3_abic rejects bad calls before any HIP call."""
+    lib = _lib()
+    o, v, n = 2, 3, 4
+    b = ctypes.c_size_t(0)
+    assert lib.ladder_ov3_abic_workspace_size(o, v, n, ctypes.byref(b)) == 0
+    assert b.value >= 8 * (3 * o * o * v * v + o ** 3 * v + v ** 3 + v * v * n) and b.value % 256 == 0
+    assert lib.ladder_ov3_abic_workspace_size(0, v, n, ctypes.byref(b)) == EINVAL
+    M = 1 << 24
+
+    def call(L1=FAKE, L2=FAKE + M, T=FAKE + 2 * M, R1=FAKE + 3 * M, R2=FAKE + 4 * M, Zvv=FAKE + 5 * M,
+             Zov=FAKE + 6 * M, Wab=FAKE + 7 * M, Wic=FAKE + 8 * M, ws=FAKE + 9 * M, wsb=1 << 22, vv=v):
+        return lib.ladder_ov3_abic(o, vv, n, 0.5, L1, L2, T, R1, R2, Zvv, Zov, 1.0, 0.0, Wab, Wic, ws, wsb, None)
+
+    assert call(vv=0) == EINVAL
+    for k in ("L1", "L2", "T", "R1", "R2", "ws"):
+        assert call(**{k: None}) == EINVAL, k
+    assert call(Wab=None, Wic=None) == EINVAL
+    assert call(Zov=None) == EINVAL                             # Wab needs Zov
+    assert call(Zvv=None) == EINVAL                             # Wic needs Zvv
+    assert call(T=FAKE + 2 * M + 4) == EINVAL                   # misaligned input
+    assert call(ws=FAKE + 9 * M + 64) == EINVAL                 # misaligned workspace
+    assert call(Wab=FAKE + 4 * M + 8) == EINVAL                 # Wab overlaps R2
+    assert call(Wic=FAKE + 7 * M + 8) == EINVAL                 # the outputs overlap
+    assert call(ws=FAKE + 2 * M) == EINVAL                      # workspace overlaps T
+    assert call(wsb=256) == EWORKSPACE
+
+
 def test_autotune_validation_and_cache(tmp_path):
     """Argument checks run before any HIP call; the cache file is parsed line by line (other
     devices' lines and junk are skipped) and a tuned batch size changes the ragged-batch plan."""

@@ -659,6 +659,66 @@ def test_ov3_abci_retinal_sampled(dev):
     assert ea <= TOL and ec <= TOL and ident <= 1e-12
 
 
+# ------------------------------------------------------------------ excited-state OV^3 density d_abic
+def abic_inputs(seed, o, v, n, integer=False):
+    rng = np.random.default_rng(seed)
+    draw = (lambda *s: rng.integers(-2, 3, s).astype(float)) if integer else (lambda *s: rng.standard_normal(s))
+    return dict(R0=0.5 if integer else 0.625, L1=draw(o, v), L2=draw(o, o, v, v), T=draw(o, o, v, v), R1=draw(o, v),
+                R2=draw(o, o, v, v), Zvv=draw(v, v, n), Zov=draw(o, v, n))
+
+
+def gpu_abic(dev, o, v, n, x, **kw):
+    return P.ov3_abic(x["R0"], *(g(x[k], dev) if x.get(k) is not None else None
+                                 for k in ("L1", "L2", "T", "R1", "R2", "Zvv", "Zov")), o=o, v=v, n=n, **kw)
+
+
+@pytest.mark.parametrize("o,v,n,seed", [(1, 1, 1, 140), (2, 3, 2, 141), (3, 7, 5, 142), (9, 6, 4, 143),
+                                        (10, 13, 3, 144), (4, 33, 17, 145)])
+def test_ov3_abic_integer_bitwise(dev, o, v, n, seed):
+    """Integer inputs: every intermediate and sum is an exact integer on both sides, so Wab and Wic
+    equal the oracle's (Appendix A density formed element by element) bit for bit; o = 9, 10 run
+    the S_iacb slab over a full and a ragged group of occupied indices."""
+    x = abic_inputs(seed, o, v, n, integer=True)
+    Wab, Wic = gpu_abic(dev, o, v, n, x)
+    ra, rc = oracle.ov3_abic(o, v, n, x["R0"], x["L1"], x["L2"], x["T"], x["R1"], x["R2"], x["Zvv"], x["Zov"])
+    assert np.array_equal(Wab.cpu().numpy(), ra)
+    assert np.array_equal(Wic.cpu().numpy(), rc)
+
+
+@pytest.mark.parametrize("o,v,n,seed", [(4, 20, 30, 146), (11, 17, 40, 147), (3, 130, 9, 148)])
+def test_ov3_abic_matches_oracle(dev, o, v, n, seed):
+    """Gaussian inputs with alpha and beta; each side alone gives the same as both together."""
+    x = abic_inputs(seed, o, v, n)
+    rng = np.random.default_rng(seed + 1)
+    A0, C0 = rng.standard_normal((v, v, n)), rng.standard_normal((o, v, n))
+    ra, rc = oracle.matrix.ov3_abic(o, v, n, x["R0"], x["L1"], x["L2"], x["T"], x["R1"], x["R2"], x["Zvv"], x["Zov"])
+    Wab, Wic = gpu_abic(dev, o, v, n, x, Wab=g(A0, dev), Wic=g(C0, dev), alpha=1.5, beta=-1.0)
+    ea, ec = err_norm(Wab.cpu().numpy(), 1.5 * ra - A0), err_norm(Wic.cpu().numpy(), 1.5 * rc - C0)
+    print("d_abic o=%d v=%d n=%d: err Wab %.3e err Wic %.3e" % (o, v, n, ea, ec))
+    assert ea <= TOL and ec <= TOL
+    y = dict(x); y["Zvv"] = None
+    a_only, none = gpu_abic(dev, o, v, n, y, want=(True, False))
+    assert none is None and err_norm(a_only.cpu().numpy(), ra) <= TOL
+    y = dict(x); y["Zov"] = None
+    none, c_only = gpu_abic(dev, o, v, n, y, want=(False, True))
+    assert none is None and err_norm(c_only.cpu().numpy(), rc) <= TOL
+
+
+def test_ov3_abic_medium_and_identity(dev):
+    """o=20, v=150, n=600 (the medium workload) in full against the numpy oracle, and the
+    identity sum Zvv*Wab = sum Zov*Wic that holds at any size."""
+    o, v, n = 20, 150, 600
+    x = abic_inputs(149, o, v, n)
+    x["L2"] *= 0.1; x["T"] *= 0.1; x["R2"] *= 0.1
+    ra, rc = oracle.matrix.ov3_abic(o, v, n, x["R0"], x["L1"], x["L2"], x["T"], x["R1"], x["R2"], x["Zvv"], x["Zov"])
+    Wab, Wic = gpu_abic(dev, o, v, n, x)
+    Wab, Wic = Wab.cpu().numpy(), Wic.cpu().numpy()
+    ea, ec = err_norm(Wab, ra), err_norm(Wic, rc)
+    ident = abs(np.sum(x["Zvv"] * Wab) - np.sum(x["Zov"] * Wic)) / np.sum(np.abs(x["Zvv"] * Wab))
+    print("d_abic medium: err Wab %.3e err Wic %.3e identity %.3e" % (ea, ec, ident))
+    assert ea <= TOL and ec <= TOL and ident <= 1e-12
+
+
 # ------------------------------------------------------------------ autotuned batch size
 @pytest.mark.parametrize("precision", [P.FP64, P.SPLIT_BF16])
 def test_autotune_then_default_calls_use_it(dev, tmp_path, precision):
