@@ -385,11 +385,12 @@ def main():
         L1 = torch.randn((o, v), dtype=torch.float64, device=dev, generator=gen) * 0.1
         Zov = Zvo.view(v, o, n).permute(1, 0, 2).contiguous()
         del Zvo
-        ws = torch.empty(P.ov3_abic_workspace_size(o, v, n), dtype=torch.uint8, device=dev)
+        opts_o = P.Options(precision=prec, n_slices=args.slices)
+        ws = torch.empty(P.ov3_abic_workspace_size(o, v, n, opts_o), dtype=torch.uint8, device=dev)
         Wab, Wic = torch.empty_like(X), torch.empty((o, v, n), dtype=torch.float64, device=dev)
         torch.cuda.synchronize()
         ev0.record(stream)
-        P.ov3_abic(0.25, L1, tbar, tau, R1, R, L, Zov, o=o, v=v, n=n, Wab=Wab, Wic=Wic, ws=ws)
+        P.ov3_abic(0.25, L1, tbar, tau, R1, R, L, Zov, o=o, v=v, n=n, Wab=Wab, Wic=Wic, ws=ws, opts=opts_o)
         ev1.record(stream)
         torch.cuda.synchronize()
         msi = ev0.elapsed_time(ev1)
@@ -399,6 +400,7 @@ def main():
               + 16.0 * o * o * v * v * n)
         s_ab, s_ic = float((L * Wab).sum()), float((Zov * Wic).sum())
         nxt["ov3_abic"] = {"ms": msi, "flops": Fi, "tflops": Fi / (msi * 1e-3) / 1e12,
+                           "precision": "split" if prec == P.SPLIT_BF16 else "fp64",
                            "identity_rel": abs(s_ab - s_ic) / float((L * Wab).abs().sum())}
         del Wab, Wic, Zov, ws
         torch.cuda.empty_cache()

@@ -256,14 +256,18 @@ int ladder_ov3_abci(int64_t o, int64_t v, int64_t n, const double* L2, const dou
  * (L1[m*v+a] = L^a_m); L2, T, R2 [o][o][v][v] (L2[((i*o+j)*v+a)*v+b] = L_ij^ab);
  * Zvv, Wab [v][v][n]; Zov, Wic [o][v][n] (Zov[(i*v+c)*n+K] = Z^K_ic).  Either output
  * may be NULL to skip that side (Wab needs Zov, Wic needs Zvv).  With beta == 0 the
- * outputs are not read.  Workspace: ladder_ov3_abic_workspace_size bytes, 256-byte
- * aligned (three o^2 v^2 buffers, o^3 v, 8 v^3, v^2 n and a few [o][v][n] arrays).
+ * outputs are not read.  opts (may be NULL: FP64) selects the precision of the three
+ * o^3 v^3 products V+Y, Yt and S: LADDER_FP64 or LADDER_SPLIT_BF16 with n_slices
+ * slices (the split GEMM of the ladder, FP64 combine); everything else is FP64;
+ * n_abatch and flags are ignored.  Workspace: ladder_ov3_abic_workspace_size bytes
+ * for the same opts, 256-byte aligned (three o^2 v^2 buffers, o^3 v, 8 v^3, v^2 n and
+ * a few [o][v][n] arrays; split adds the slices of two o v x o v operands).
  * No input may overlap an output or the workspace; the outputs may not overlap.
  */
-int ladder_ov3_abic_workspace_size(int64_t o, int64_t v, int64_t n, size_t* bytes);
+int ladder_ov3_abic_workspace_size(int64_t o, int64_t v, int64_t n, const ladder_options* opts, size_t* bytes);
 int ladder_ov3_abic(int64_t o, int64_t v, int64_t n, double R0, const double* L1, const double* L2, const double* T,
                     const double* R1, const double* R2, const double* Zvv, const double* Zov, double alpha, double beta,
-                    double* Wab, double* Wic, void* ws, size_t ws_bytes, void* stream);
+                    double* Wab, double* Wic, void* ws, size_t ws_bytes, const ladder_options* opts, void* stream);
 
 /*
  * ladder_metric_contraction over any number of index pairs (the two-index

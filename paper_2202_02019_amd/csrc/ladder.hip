@@ -1574,14 +1574,21 @@ namespace {
 //   three o^2 v^2 buffers (reordered operands and the o^2 v^2 intermediates V+Y, Yt and the
 //   amplitude matrices), B_iamn (o^3 v), the S_iacb slab of `g` occupied indices (g v^3),
 //   Zt (v^2 n), eight [o][v][n] or [o][o][n] buffers, Xvv (v^2), W_am (o v), P^K and Q^K (n).
+// Split precision adds the BF16 slices of the two operands of the o^3 v^3 GEMMs (rows
+// o v, length o v; the slices of t along (mn) for S_iacb reuse the first one) and of one
+// B_i.. block (rows v, length o^2).
 struct AbicLayout {
     int64_t g;
     size_t bufA, bufB, bufC, Bm, S, Zt, Zvo, OX, Pp, Pk, PKI, KK, QY, YA, OA, Xvv, Wma, PK, QK, total;
+    int slices = 0;  // 0: FP64
+    SlicedBuf slA, slB, slT, slBm;
 };
-int abic_layout(int64_t o, int64_t v, int64_t n, AbicLayout& l) {
+int abic_layout(int64_t o, int64_t v, int64_t n, const ladder_options* opts, AbicLayout& l) {
     Sizes s;
+    ladder_options op;
     int rc;
-    if ((rc = check_dims(o, v, n, s))) return rc;
+    if ((rc = check_dims(o, v, n, s)) || (rc = get_opts(opts, op))) return rc;
+    l.slices = op.precision == LADDER_SPLIT_BF16 ? (int)op.n_slices : 0;
     int64_t ovn, oon, ooov, vvv;
     if (!mul_ok(o * v, n, ovn) || !mul_ok(o * o, n, oon) || !mul_ok(o * o, o * v, ooov) || !mul_ok(s.vv, v, vvv) ||
         ovn > INT64_MAX / 16 || ooov > INT64_MAX / 16)
@@ -1617,6 +1624,31 @@ int abic_layout(int64_t o, int64_t v, int64_t n, AbicLayout& l) {
     l.Wma = take((size_t)(o * v));
     l.PK = take((size_t)n);
     l.QK = take((size_t)n);
+    if (l.slices) {
+        const int64_t ov = o * v;
+        // slicer grids and 32-bit panel offsets of the split GEMM (as for the ladder)
+        if ((ov / 16 + 1) * split_nchunk(ov) >= (int64_t(1) << 31) || (s.vv / 32 + 1) * split_nchunk(o * o) >= (int64_t(1) << 31) ||
+            2 * (split_kpad(std::max(ov, o * o)) / 16) * SPLIT_PANEL * 16 * 2 + 4096 >= (int64_t(1) << 32))
+            return fail(LADDER_EUNSUPPORTED, "split precision: o v too large for the slicer grid or panel offsets");
+        auto sliced = [&](int64_t R, int64_t K, size_t at) {
+            SlicedBuf b;
+            b.R = R;
+            b.K = K;
+            b.s_off = at;
+            b.e_off = at + align_up(slice_bytes(l.slices, R, K));
+            return b;
+        };
+        const size_t a_b = align_up(slice_bytes(l.slices, ov, ov)) + align_up(exp_bytes(ov, ov));
+        const size_t t_b = align_up(slice_bytes(l.slices, s.vv, o * o)) + align_up(exp_bytes(s.vv, o * o));
+        const size_t r1 = off;
+        off += std::max(a_b, t_b);
+        l.slA = sliced(ov, ov, r1);
+        l.slT = sliced(s.vv, o * o, r1);
+        l.slB = sliced(ov, ov, off);
+        off += a_b;
+        l.slBm = sliced(v, o * o, off);
+        off += align_up(slice_bytes(l.slices, v, o * o)) + align_up(exp_bytes(v, o * o));
+    }
     l.total = off;
     return LADDER_OK;
 }
@@ -1636,23 +1668,23 @@ int permute4(const double* in, int64_t in_elems, double* out, const Perm4& p, hi
 }
 }  // namespace
 
-int ladder_ov3_abic_workspace_size(int64_t o, int64_t v, int64_t n, size_t* bytes) {
+int ladder_ov3_abic_workspace_size(int64_t o, int64_t v, int64_t n, const ladder_options* opts, size_t* bytes) {
     g_last_error.clear();
     if (!bytes) return fail(LADDER_EINVAL, "bytes is NULL");
     AbicLayout l;
     int rc;
-    if ((rc = abic_layout(o, v, n, l))) return rc;
+    if ((rc = abic_layout(o, v, n, opts, l))) return rc;
     *bytes = l.total;
     return LADDER_OK;
 }
 
 int ladder_ov3_abic(int64_t o, int64_t v, int64_t n, double R0, const double* L1, const double* L2, const double* T,
                     const double* R1, const double* R2, const double* Zvv, const double* Zov, double alpha, double beta,
-                    double* Wab, double* Wic, void* ws, size_t ws_bytes, void* stream) {
+                    double* Wab, double* Wic, void* ws, size_t ws_bytes, const ladder_options* opts, void* stream) {
     g_last_error.clear();
     AbicLayout l;
     int rc;
-    if ((rc = abic_layout(o, v, n, l))) return rc;
+    if ((rc = abic_layout(o, v, n, opts, l))) return rc;
     if (!L1 || !L2 || !T || !R1 || !R2 || !ws) return fail(LADDER_EINVAL, "L1, L2, T, R1, R2 and ws must be non-NULL");
     if (!Wab && !Wic) return fail(LADDER_EINVAL, "Wab and Wic are both NULL: nothing to compute");
     if (Wab && !Zov) return fail(LADDER_EINVAL, "Wab needs Zov");
@@ -1711,6 +1743,18 @@ int ladder_ov3_abic(int64_t o, int64_t v, int64_t n, double R0, const double* L1
         fl += gemm_flops(M, N, K);
         by += gemm_bytes(M, N, K);
     };
+    // C(m, n) = sum_k A[m*K + k] B[n*K + k] for the (o v)^3 products: FP64 MFMA, or both
+    // operands sliced into BF16 and the split GEMM (FP64 combine, same epilogue).
+    auto rows_gemm = [&](const double* A_, const double* B_, int64_t M, int64_t N, int64_t K, const auto& epi) -> int {
+        acct(M, N, K);
+        if (!l.slices) return hip_check(launch_gemm<true, true, LADDER_STAGE_OV3>(A_, K, B_, K, M, N, K, epi, st),
+                                        "OV3 GEMM launch");
+        int r;
+        if ((r = slice_into(l.slices, false, A_, K, w, l.slA, st)) || (r = slice_into(l.slices, false, B_, K, w, l.slB, st)))
+            return r;
+        SplitShape sh{view(w, l.slA, 0), view(w, l.slB, 0), M, N, K};
+        return hip_check(launch_split<LADDER_STAGE_OV3>(l.slices, sh, epi, st), "OV3 split GEMM launch");
+    };
     StageTimer tm(LADDER_STAGE_OV3, 0.0, 0.0, st);
     // ---- terms (3) and (8): X_ab = L_kl^ad t_kl^bd over rows a, b and columns (kl, d)
     if ((rc = permute4(L2, L2n, bA, Perm4{{1, v, oo, v}, {0, v, vv, 1}, {0, 0, 0, 0}, 1.0, 0.0}, st))) return rc;
@@ -1753,18 +1797,11 @@ int ladder_ov3_abic(int64_t o, int64_t v, int64_t n, double R0, const double* L1
     //   V: rows (a,k) of L_lk^ae, columns (b,i) of t_li^be, summed over (l,e)
     if ((rc = permute4(L2, L2n, bA, Perm4{{v, o, o, v}, {v, vv, ov * v, 1}, {0, 0, 0, 0}, 1.0, 0.0}, st))) return rc;
     if ((rc = permute4(T, L2n, bB, Perm4{{v, o, o, v}, {v, vv, ov * v, 1}, {0, 0, 0, 0}, 1.0, 0.0}, st))) return rc;
-    {
-        EpiSwapMid e{bC, o, v, o, 1.0, 0.0};
-        ABIC_GEMM(true, true, bA, ov, bB, ov, ov, ov, ov, e);
-    }
+    if ((rc = rows_gemm(bA, bB, ov, ov, ov, EpiSwapMid{bC, o, v, o, 1.0, 0.0}))) return rc;
     //   Y: rows (a,k) of L_kl^ad, columns (b,i) of t_il^bd, summed over (l,d)
     if ((rc = permute4(L2, L2n, bA, Perm4{{v, o, o, v}, {v, ov * v, vv, 1}, {0, 0, 0, 0}, 1.0, 0.0}, st))) return rc;
     if ((rc = permute4(T, L2n, bB, Perm4{{v, o, o, v}, {v, ov * v, vv, 1}, {0, 0, 0, 0}, 1.0, 0.0}, st))) return rc;
-    {
-        EpiSwapMid e{bC, o, v, o, 1.0, 1.0};
-        ABIC_GEMM(true, true, bA, ov, bB, ov, ov, ov, ov, e);
-    }
-    acct(ov, ov, ov); acct(ov, ov, ov);
+    if ((rc = rows_gemm(bA, bB, ov, ov, ov, EpiSwapMid{bC, o, v, o, 1.0, 1.0}))) return rc;
     if (ab) {
         // Wab -= alpha sum_ik VY[(a,b),(k,i)] P_ik^K, P_ik^K = sum_c R^c_k Z^K_ic stored PKI[k][i][K]
         EpiStrided e1{PKI, on, 1.0, 0.0, nullptr, nullptr};
@@ -1785,11 +1822,7 @@ int ladder_ov3_abic(int64_t o, int64_t v, int64_t n, double R0, const double* L1
     if ((rc = permute4(L2, L2n, bA, Perm4{{o, v, o, v}, {vv, 1, ov * v, v}, {0, 0, 0, 0}, 1.0, 0.0}, st))) return rc;
     if ((rc = permute4(T, L2n, bB, Perm4{{o, v, o, v}, {vv, 1, ov * v, v}, {ov * v, 1, vv, v}, 2.0, -1.0}, st)))
         return rc;
-    {
-        EpiStrided e{bC, ov, 1.0, 0.0, nullptr, nullptr};
-        ABIC_GEMM(true, true, bA, ov, bB, ov, ov, ov, ov, e);
-        acct(ov, ov, ov);
-    }
+    if ((rc = rows_gemm(bA, bB, ov, ov, ov, EpiStrided{bC, ov, 1.0, 0.0, nullptr, nullptr}))) return rc;
     if (ab) {
         // Wab += alpha sum_k R^b_k Q_ak^K, Q_ak^K = sum_ic Yt[(k,a),(i,c)] Z^K_ic stored QY[k][a][K]
         EpiStrided e1{QY, n, 1.0, 0.0, nullptr, nullptr};
@@ -1838,12 +1871,21 @@ int ladder_ov3_abic(int64_t o, int64_t v, int64_t n, double R0, const double* L1
         ABIC_GEMM(true, true, R1, v, L2, v, o, oo * v, v, e);
         acct(o, oo * v, v);
     }
+    if (l.slices && (rc = slice_into(l.slices, true, T, vv, w, l.slT, st))) return rc;  // rows (b,c), along (mn)
     for (int64_t i0 = 0; i0 < o; i0 += l.g) {
         const int64_t gl = std::min<int64_t>(l.g, o - i0);
         for (int64_t il = 0; il < gl; ++il) {
             // S[(a,b)][(il,c)] = sum_mn Bm[i][(m,n)][a] t_mn^bc
             EpiPlace e{S + il * v, 1, v, l.g * vv, 0, l.g * v, 1, 1.0, 0.0};
-            ABIC_GEMM(false, false, Bm + (i0 + il) * oo * v, v, T, vv, v, vv, oo, e);
+            const double* Bi = Bm + (i0 + il) * oo * v;
+            if (l.slices) {
+                if ((rc = slice_into(l.slices, true, Bi, v, w, l.slBm, st))) return rc;  // rows a, along (mn)
+                SplitShape sh{view(w, l.slBm, 0), view(w, l.slT, 0), v, vv, oo};
+                if ((rc = hip_check(launch_split<LADDER_STAGE_OV3>(l.slices, sh, e, st), "OV3 split GEMM launch")))
+                    return rc;
+            } else {
+                ABIC_GEMM(false, false, Bi, v, T, vv, v, vv, oo, e);
+            }
             acct(v, vv, oo);
         }
         if (ab) {

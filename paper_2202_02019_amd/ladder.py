@@ -110,8 +110,8 @@ def _load():
     lib.ladder_ov3_abci_workspace_size.argtypes = [i64, i64, i64, ctypes.POINTER(sz)]
     lib.ladder_ov3_abci.argtypes = [i64, i64, i64, vp, vp, vp, vp, dbl, dbl, vp, vp, vp, sz, vp]
     lib.ladder_metric_contraction_pairs.argtypes = [i64, i64, vp, vp, dbl, dbl, vp, vp]
-    lib.ladder_ov3_abic_workspace_size.argtypes = [i64, i64, i64, ctypes.POINTER(sz)]
-    lib.ladder_ov3_abic.argtypes = [i64, i64, i64, dbl, vp, vp, vp, vp, vp, vp, vp, dbl, dbl, vp, vp, vp, sz, vp]
+    lib.ladder_ov3_abic_workspace_size.argtypes = [i64, i64, i64, op, ctypes.POINTER(sz)]
+    lib.ladder_ov3_abic.argtypes = [i64, i64, i64, dbl, vp, vp, vp, vp, vp, vp, vp, dbl, dbl, vp, vp, vp, sz, op, vp]
     lib.ladder_mp2_amplitudes.argtypes = [i64, i64, i64, vp, vp, vp, vp]
     lib.ladder_amplitude_update.argtypes = [i64, i64, vp, vp, vp, vp]
     lib.ladder_batched_workspace_size.argtypes = [ctypes.c_int, ctypes.POINTER(_CInstance), ctypes.c_uint32, op,
@@ -358,17 +358,19 @@ def ov3_abci(L2, R1, Zvv, Zvo, *, o, v, n, Wab=None, Wci=None, alpha=1.0, beta=0
     return (Wab if want_ab else None), (Wci if want_ci else None)
 
 
-def ov3_abic_workspace_size(o: int, v: int, n: int) -> int:
+def ov3_abic_workspace_size(o: int, v: int, n: int, opts=None) -> int:
     b = ctypes.c_size_t(0)
-    _check(_load().ladder_ov3_abic_workspace_size(o, v, n, ctypes.byref(b)))
+    co = _opts(opts)
+    _check(_load().ladder_ov3_abic_workspace_size(o, v, n, ctypes.byref(co), ctypes.byref(b)))
     return b.value
 
 
 def ov3_abic(R0, L1, L2, T, R1, R2, Zvv, Zov, *, o, v, n, Wab=None, Wic=None, alpha=1.0, beta=0.0, want=(True, True),
-             ws=None, stream=None):
+             ws=None, opts=None, stream=None):
     """Both W contributions of the excited-state OV^3 density d_abic: Wab [v][v][n] (from
     Zov [o][v][n]) and Wic [o][v][n] (from Zvv [v][v][n]), each beta*W + alpha*W'.
-    L1, R1: [o][v]; L2, T, R2: [o][o][v][v]; R0 a float.  `want` = (ab side, ic side)."""
+    L1, R1: [o][v]; L2, T, R2: [o][o][v][v]; R0 a float.  `want` = (ab side, ic side);
+    opts.precision picks FP64 or split BF16 for the o^3 v^3 products."""
     want_ab, want_ic = bool(want[0]), bool(want[1])
     _need(L1, "L1", (o, v)); _need(R1, "R1", (o, v))
     for t, name in ((L2, "L2"), (T, "T"), (R2, "R2")):
@@ -383,11 +385,12 @@ def ov3_abic(R0, L1, L2, T, R1, R2, Zvv, Zov, *, o, v, n, Wab=None, Wic=None, al
         if Wic is None:
             Wic = torch.empty((o, v, n), dtype=torch.float64, device=L2.device)
         _need(Wic, "Wic", (o, v, n))
-    wsb = _workspace(ov3_abic_workspace_size(o, v, n), L2.device, ws)
+    co = _opts(opts)
+    wsb = _workspace(ov3_abic_workspace_size(o, v, n, co), L2.device, ws)
     _check(_load().ladder_ov3_abic(o, v, n, float(R0), _ptr(L1), _ptr(L2), _ptr(T), _ptr(R1), _ptr(R2),
                                    _ptr(Zvv) if want_ic else None, _ptr(Zov) if want_ab else None, float(alpha),
                                    float(beta), _ptr(Wab) if want_ab else None, _ptr(Wic) if want_ic else None,
-                                   _ptr(wsb), wsb.numel() * wsb.element_size(), _stream(stream)))
+                                   _ptr(wsb), wsb.numel() * wsb.element_size(), ctypes.byref(co), _stream(stream)))
     return (Wab if want_ab else None), (Wic if want_ic else None)
 
 

@@ -168,14 +168,18 @@ def test_ov3_abic_validation():
     lib = _lib()
     o, v, n = 2, 3, 4
     b = ctypes.c_size_t(0)
-    assert lib.ladder_ov3_abic_workspace_size(o, v, n, ctypes.byref(b)) == 0
+    assert lib.ladder_ov3_abic_workspace_size(o, v, n, None, ctypes.byref(b)) == 0
     assert b.value >= 8 * (3 * o * o * v * v + o ** 3 * v + v ** 3 + v * v * n) and b.value % 256 == 0
-    assert lib.ladder_ov3_abic_workspace_size(0, v, n, ctypes.byref(b)) == EINVAL
+    bs = ctypes.c_size_t(0)
+    assert lib.ladder_ov3_abic_workspace_size(o, v, n, _opts(precision=B.SPLIT_BF16), ctypes.byref(bs)) == 0
+    assert bs.value > b.value                                   # plus the BF16 slices
+    assert lib.ladder_ov3_abic_workspace_size(0, v, n, None, ctypes.byref(b)) == EINVAL
+    assert lib.ladder_ov3_abic_workspace_size(o, v, n, _opts(precision=7), ctypes.byref(b)) == EUNSUPPORTED
     M = 1 << 24
 
     def call(L1=FAKE, L2=FAKE + M, T=FAKE + 2 * M, R1=FAKE + 3 * M, R2=FAKE + 4 * M, Zvv=FAKE + 5 * M,
-             Zov=FAKE + 6 * M, Wab=FAKE + 7 * M, Wic=FAKE + 8 * M, ws=FAKE + 9 * M, wsb=1 << 22, vv=v):
-        return lib.ladder_ov3_abic(o, vv, n, 0.5, L1, L2, T, R1, R2, Zvv, Zov, 1.0, 0.0, Wab, Wic, ws, wsb, None)
+             Zov=FAKE + 6 * M, Wab=FAKE + 7 * M, Wic=FAKE + 8 * M, ws=FAKE + 9 * M, wsb=1 << 22, vv=v, opts=None):
+        return lib.ladder_ov3_abic(o, vv, n, 0.5, L1, L2, T, R1, R2, Zvv, Zov, 1.0, 0.0, Wab, Wic, ws, wsb, opts, None)
 
     assert call(vv=0) == EINVAL
     for k in ("L1", "L2", "T", "R1", "R2", "ws"):
@@ -189,6 +193,8 @@ def test_ov3_abic_validation():
     assert call(Wic=FAKE + 7 * M + 8) == EINVAL                 # the outputs overlap
     assert call(ws=FAKE + 2 * M) == EINVAL                      # workspace overlaps T
     assert call(wsb=256) == EWORKSPACE
+    assert call(wsb=b.value, opts=_opts(precision=B.SPLIT_BF16)) == EWORKSPACE   # FP64 size is short for split
+    assert call(opts=_opts(precision=B.SPLIT_BF16, n_slices=9)) == EUNSUPPORTED
 
 
 def test_autotune_validation_and_cache(tmp_path):

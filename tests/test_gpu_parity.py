@@ -719,6 +719,28 @@ def test_ov3_abic_medium_and_identity(dev):
     assert ea <= TOL and ec <= TOL and ident <= 1e-12
 
 
+@pytest.mark.parametrize("o,v,n,seed", [(2, 3, 2, 150), (9, 6, 4, 151), (4, 33, 17, 152)])
+def test_ov3_abic_split_integer_bitwise(dev, o, v, n, seed):
+    """Split BF16 for the o^3 v^3 products: small integers are exact in the slices and every
+    chunk sum is exact, so the result is still bitwise the oracle's."""
+    x = abic_inputs(seed, o, v, n, integer=True)
+    Wab, Wic = gpu_abic(dev, o, v, n, x, opts=P.Options(precision=P.SPLIT_BF16))
+    ra, rc = oracle.ov3_abic(o, v, n, x["R0"], x["L1"], x["L2"], x["T"], x["R1"], x["R2"], x["Zvv"], x["Zov"])
+    assert np.array_equal(Wab.cpu().numpy(), ra)
+    assert np.array_equal(Wic.cpu().numpy(), rc)
+
+
+def test_ov3_abic_split_medium(dev):
+    """Split BF16 (S = 5) on the medium workload against the numpy oracle, in full."""
+    o, v, n = 20, 150, 600
+    x = abic_inputs(153, o, v, n)
+    ra, rc = oracle.matrix.ov3_abic(o, v, n, x["R0"], x["L1"], x["L2"], x["T"], x["R1"], x["R2"], x["Zvv"], x["Zov"])
+    Wab, Wic = gpu_abic(dev, o, v, n, x, opts=P.Options(precision=P.SPLIT_BF16))
+    ea, ec = err_norm(Wab.cpu().numpy(), ra), err_norm(Wic.cpu().numpy(), rc)
+    print("d_abic split medium: err Wab %.3e err Wic %.3e" % (ea, ec))
+    assert ea <= SPLIT_TOL_RX and ec <= SPLIT_TOL_RX
+
+
 # ------------------------------------------------------------------ autotuned batch size
 @pytest.mark.parametrize("precision", [P.FP64, P.SPLIT_BF16])
 def test_autotune_then_default_calls_use_it(dev, tmp_path, precision):
