@@ -112,6 +112,9 @@ def main():
                     help="also time the transposed ladder (dE/dtau), the metric contraction V, the MO "
                          "back-transformation and the excited-state OV^3 block d_abci once on the same "
                          "inputs, with sampled checks")
+    ap.add_argument("--decay", type=float, default=0.0, metavar="ALPHA",
+                    help="stress variant of the inputs: Cholesky vectors scaled by exp(-ALPHA J / n) "
+                         "(0 = the plain recipe)")
     ap.add_argument("--copy-probe", action="store_true",
                     help="run a 1 GiB device copy first (reference kernel for the HBM traffic counters)")
     args = ap.parse_args()
@@ -162,6 +165,11 @@ def main():
     t0 = time.time()
     L = SG.draw_L_vv(seed, o, v, n)
     Lov = SG.draw_L_ov(seed, o, v, n)
+    if args.decay:
+        import synthetic
+        f = torch.from_numpy(synthetic.decay_factors(n, args.decay)).to(dev)
+        L.mul_(f)
+        Lov.mul_(f)
     eps = SG.draw_eps(seed, o, v)
     tau = P.mp2_amplitudes(Lov, eps, o=o, v=v, n=n)
     del Lov
@@ -438,7 +446,8 @@ def main():
         "config": {"workload": name, "o": o, "v": v, "n_chol": n, "seed": seed, "precision": args.precision,
                    "n_slices": args.slices, "n_abatch": nA_eff or 0, "n_abatch_source": nA_source,
                    "nominal_flops": F,
-                   "path": "dense" if args.dense else "+/- packed"},
+                   "path": "dense" if args.dense else "+/- packed",
+                   "decay": args.decay},
         "energy": float(E.cpu()),
         "roofline": roofline, "stages": stage_summary, "cpu_baseline": cpu,
         "frac_fp64_peak": value / PEAK["fp64"],

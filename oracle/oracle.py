@@ -284,14 +284,18 @@ def amplitude_update(o, v, eps, R, t):
     return t
 
 
-def make_inputs(o, v, n, seed):
+def make_inputs(o, v, n, seed, decay=0.0):
     """The oracle-side inputs of the synthetic recipe: (L_vv, tau, tbar, L_ov, eps).
 
     tau = t with t the first-order amplitudes built by the oracle from the draws,
-    tbar = t + 1e-2 * xi with the pair-symmetric noise xi.
+    tbar = t + 1e-2 * xi with the pair-symmetric noise xi; decay > 0 scales the
+    Cholesky vectors by exp(-decay * J / n) first (the stress variant).
     """
     Lvv = synthetic.draw_L_vv(seed, o, v, n)
     Lov = synthetic.draw_L_ov(seed, o, v, n)
+    if decay:
+        f = synthetic.decay_factors(n, decay)
+        Lvv, Lov = Lvv * f, Lov * f
     eps = synthetic.draw_eps(seed, o, v)
     t = mp2_amplitudes(o, v, n, Lov, eps)
     tbar = t + synthetic.NOISE_SCALE * synthetic.draw_noise_full(seed, o, v)

@@ -23,6 +23,9 @@ N = o + v orbitals, occupied first):
     P = min(i*v+a, j*v+b), Q = max(...), so that xi_ij^ab = xi_ji^ba.
 The amplitudes t_ij^ab = (ia|jb)/(eps_i+eps_j-eps_a-eps_b), tau = t and
 tbar = t + 1e-2 * xi are formed by the consumer.
+Stress variant (decaying Cholesky vectors, as pivoted Cholesky vectors of real
+molecules decay with J): every block of L is multiplied by exp(-alpha * J / n)
+along J before the amplitudes are formed (alpha = 0: the plain recipe).
 
 The same generator is implemented for the GPU in synth.hip from the definition
 above; the two agree bitwise on integers and uniforms and to a few ulps on
@@ -49,7 +52,7 @@ NOISE_SCALE = 1e-2
 
 __all__ = [
     "splitmix64", "uniform", "gaussian", "counter", "draw_L_block", "draw_L_vv", "draw_L_ov",
-    "draw_eps", "pair_noise", "draw_noise_full", "asym_noise_full", "batched_sizes",
+    "draw_eps", "pair_noise", "draw_noise_full", "asym_noise_full", "batched_sizes", "decay_factors",
     "CONFIGS", "STREAM_L", "STREAM_EPS_OCC", "STREAM_EPS_VIRT", "STREAM_NOISE", "STREAM_SIZES",
     "STREAM_ASYM", "L_SCALE", "NOISE_SCALE",
 ]
@@ -117,6 +120,11 @@ def draw_L_vv(seed: int, o: int, v: int, n: int) -> np.ndarray:
 def draw_L_ov(seed: int, o: int, v: int, n: int) -> np.ndarray:
     """Occupied-virtual block, layout [o][v][n]."""
     return draw_L_block(seed, o + v, n, 0, o, o, v)
+
+
+def decay_factors(n: int, alpha: float) -> np.ndarray:
+    """exp(-alpha * J / n) for J < n: the per-vector scale of the decaying stress variant."""
+    return np.exp(-float(alpha) * np.arange(n, dtype=np.float64) / n)
 
 
 def draw_eps(seed: int, o: int, v: int) -> np.ndarray:

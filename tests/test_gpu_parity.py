@@ -306,6 +306,21 @@ def test_split_medium_error_versus_slices(dev):
     assert errs[6][0] <= 2 * errs[5][0] and errs[5][0] <= errs[3][0]
 
 
+@pytest.mark.parametrize("alpha", [4.0, 8.0])
+def test_split_medium_decaying_vectors(dev, alpha):
+    """Stress variant of the recipe: Cholesky vectors decaying as exp(-alpha J / n) (real pivoted
+    vectors do), so the chunk exponents of the slices along J differ by up to alpha / ln 2 bits.
+    The default S = 5 still meets the targets on every element of the medium workload."""
+    o, v, n = 20, 150, 600
+    L, tau, tbar, _, _ = oracle.make_inputs(o, v, n, 2, decay=alpha)
+    Rr, Er = oracle.matrix.forward(o, v, n, L, tau, tbar)
+    Xr = oracle.matrix.adjoint(o, v, n, L, tau, tbar)
+    R, E, X = run(dev, o, v, n, L, tau, tbar, P.Options(precision=P.SPLIT_BF16))
+    eR, eE, eX = err_norm(R, Rr), err_rel(E, Er), err_norm(X, Xr)
+    print("split medium, decay %.0f: err_R %.3e err_E %.3e err_X %.3e" % (alpha, eR, eE, eX))
+    assert eR <= SPLIT_TOL_RX and eE <= SPLIT_TOL_E and eX <= SPLIT_TOL_RX
+
+
 def test_split_autograd(dev):
     o, v, n = 3, 21, 25
     L, tau, w = gaussian_inputs(19, o, v, n)
