@@ -30,6 +30,10 @@ WORKLOADS = {
     "retinal": (78, 657, 2200, 3),
     "autograd": (40, 350, 1200, 5),
     "batched": (None, None, None, 4),
+    # shapes derived from the paper's other molecules (electrons from the formulas,
+    # aug-cc-pVDZ functions, the Cholesky counts the paper quotes): thymine, azobenzene
+    "thymine": (33, 228, 967, 6),
+    "azobenzene": (48, 364, 1444, 7),
 }
 PEAK = {"fp64": 78.6, "bf16": 2516.6}  # dense MFMA TFLOP/s, MI355X
 

@@ -64,6 +64,8 @@ CONFIGS = {
     "retinal": dict(o=78, v=657, n=2200, seed=3),
     "batched": dict(count=64, seed=4),
     "autograd": dict(o=40, v=350, n=1200, seed=5),
+    "thymine": dict(o=33, v=228, n=967, seed=6),
+    "azobenzene": dict(o=48, v=364, n=1444, seed=7),
 }
 
 
