@@ -321,6 +321,19 @@ def test_split_medium_decaying_vectors(dev, alpha):
     assert eR <= SPLIT_TOL_RX and eE <= SPLIT_TOL_E and eX <= SPLIT_TOL_RX
 
 
+@pytest.mark.parametrize("o,v,n,seed", [(1, 2, 1, 160), (2, 3, 2, 161)])
+def test_autograd_gradcheck(dev, o, v, n, seed):
+    """torch.autograd.gradcheck on the FP64 path: central differences of E in every entry of
+    L, tau and tbar (E is quadratic in L and bilinear in (tau, tbar), so the differences are
+    exact up to rounding) against LadderEnergy's backward (adjoint, transposed ladder, R).
+    The perturbations break pair symmetry, so the general path is used."""
+    L, tau, w = gaussian_inputs(seed, o, v, n, symmetric=False)
+    args = [g(x, dev).requires_grad_(True) for x in (L, tau, w)]
+    opts = P.Options(flags=P.FLAG_GENERAL)
+    f = lambda L_, t_, w_: P.ladder_energy(L_, t_, w_, (o, v, n), opts)
+    assert torch.autograd.gradcheck(f, args, eps=1e-6, atol=1e-9, rtol=1e-7)
+
+
 def test_split_autograd(dev):
     o, v, n = 3, 21, 25
     L, tau, w = gaussian_inputs(19, o, v, n)
