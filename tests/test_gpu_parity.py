@@ -334,6 +334,41 @@ def test_autograd_gradcheck(dev, o, v, n, seed):
     assert torch.autograd.gradcheck(f, args, eps=1e-6, atol=1e-9, rtol=1e-7)
 
 
+def test_retinal_split_sampled(dev):
+    """o=78, v=657, n=2200, seed 3, in the configuration the benchmark times (split BF16, S = 5,
+    +/- packed, the batch size of the committed autotune cache): one forward and one adjoint on
+    the GPU-drawn recipe inputs, then sampled rows of R (all ij for chosen ab) and of X (all J for
+    chosen ac) against the oracle, computed one by one from host copies of the same arrays."""
+    import os
+    from synthetic import gpu as SG
+    torch.cuda.empty_cache()
+    o, v, n, seed = 78, 657, 2200, 3
+    cache = os.path.join(os.path.dirname(P.library_path()), "tuned_mi355x.jsonl")
+    P.autotune_load(cache)
+    L = SG.draw_L_vv(seed, o, v, n)
+    Lov = SG.draw_L_ov(seed, o, v, n)
+    tau = P.mp2_amplitudes(Lov, SG.draw_eps(seed, o, v), o=o, v=v, n=n)
+    del Lov
+    tbar = SG.add_noise(seed, o, v, tau)
+    opts = P.Options(precision=P.SPLIT_BF16)
+    ws = torch.empty(P.workspace_size(o, v, n, opts), dtype=torch.uint8, device=dev)
+    R, E = P.forward(L, tau, tbar, o=o, v=v, n=n, ws=ws, opts=opts)
+    X = P.adjoint(L, tau, tbar, o=o, v=v, n=n, ws=ws, opts=opts)
+    torch.cuda.synchronize()
+    del ws
+    print("retinal split: forward + adjoint done, E = %.15g" % float(E), flush=True)
+    Lh, th, wh = L.cpu().numpy(), tau.cpu().numpy(), tbar.cpu().numpy()
+    ab = np.array([[0, 0], [656, 656], [3, 600], [600, 3], [327, 328]])
+    pq = np.array([[0, 0], [656, 1], [100, 540]])
+    Rr = oracle.R_sample(o, v, n, Lh, th, ab)
+    Xr = oracle.X_sample(o, v, n, Lh, th, wh, pq)
+    Rg = np.stack([R[:, :, a, b].cpu().numpy().ravel() for a, b in ab])
+    Xg = np.stack([X[p, q].cpu().numpy() for p, q in pq])
+    eR, eX = err_norm(Rg, Rr), err_norm(Xg, Xr)
+    print("retinal split sampled: err_R %.3e err_X %.3e" % (eR, eX))
+    assert eR <= SPLIT_TOL_RX and eX <= SPLIT_TOL_RX
+
+
 def test_split_autograd(dev):
     o, v, n = 3, 21, 25
     L, tau, w = gaussian_inputs(19, o, v, n)
