@@ -65,10 +65,32 @@ def gemm_source_hash():
     taken on)."""
     import hashlib
     h = hashlib.sha256()
-    for f in ("split_bf16.hpp", "gemm_f64.hpp", "pm_pack.hpp", "ladder.hip"):
-        with open(os.path.join(ROOT, "paper_2202_02019_amd", "csrc", f), "rb") as fh:
+    for f in ("csrc/split_bf16.hpp", "csrc/gemm_f64.hpp", "csrc/pm_pack.hpp", "csrc/ladder.hip", "build.py"):
+        with open(os.path.join(ROOT, "paper_2202_02019_amd", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
+
+
+def mfma_ceiling(seconds=0.2):
+    """Rate of the register-only MFMA probe (ladder_mfma_probe) for BF16 and FP64, in TFLOP/s:
+    what the matrix cores sustain on this chip under its clock and power limits."""
+    import torch
+
+    import paper_2202_02019_amd as P
+    out = {}
+    blocks = 8 * torch.cuda.get_device_properties(0).multi_processor_count
+    for name, kind, rate in (("bf16", P.PROBE_BF16, 2.0e15), ("fp64", P.PROBE_FP64, 7.0e13)):
+        _, per_iter = P.mfma_probe(kind, 1, blocks)
+        iters = max(1, int(seconds * rate / per_iter))
+        buf, _ = P.mfma_probe(kind, iters, blocks)          # warm-up at full length
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        _, fl = P.mfma_probe(kind, iters, blocks, out=buf)
+        e1.record()
+        torch.cuda.synchronize()
+        out[name + "_tflops"] = fl / (e0.elapsed_time(e1) * 1e-3) / 1e12
+        out[name + "_frac_of_published"] = out[name + "_tflops"] / PEAK[name]
+    return out
 
 
 def measured_traffic(workload, precision, kernel, n_abatch):
@@ -253,6 +275,9 @@ def main():
                 "slice_products": prods if args.precision == "split" else None,
                 "fp64_equivalent_tflops": fp64_equiv,
                 "fp64_equivalent_frac_of_fp64_peak": fp64_equiv / PEAK["fp64"]}
+    ceiling = mfma_ceiling()
+    roofline["measured_mfma_ceiling"] = ceiling["bf16_tflops" if args.precision == "split" else "fp64_tflops"]
+    roofline["frac_of_measured_ceiling"] = achieved / roofline["measured_mfma_ceiling"]
     stage_summary = {k: {"ms_per_step": s["total_ms"] / steps, "launches_per_step": s["launches"] / steps,
                          "tflops": (s["flops"] / (s["total_ms"] * 1e-3) / 1e12) if s["total_ms"] > 0 else None}
                      for k, s in stages.items()}
@@ -453,7 +478,7 @@ def main():
                    "path": "dense" if args.dense else "+/- packed",
                    "decay": args.decay},
         "energy": float(E.cpu()),
-        "roofline": roofline, "stages": stage_summary, "cpu_baseline": cpu,
+        "roofline": roofline, "stages": stage_summary, "cpu_baseline": cpu, "mfma_probe": ceiling,
         "frac_fp64_peak": value / PEAK["fp64"],
         "flop_count": "value counts the dense nominal F = 4 v^4 (n + o^2) + 2 o^2 v^2 per step; the default "
                       "+/- packed path executes fewer GEMM flops (executed_gemm_flops)",

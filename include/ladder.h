@@ -324,6 +324,20 @@ int ladder_batched(int count, const ladder_instance* inst, uint32_t what, void* 
                    const ladder_options* opts, void* stream);
 
 /*
+ * Matrix-core ceiling probe (measurement support): `blocks` workgroups of four
+ * waves each issue `iters` rounds of four independent MFMAs on register operands
+ * and write one checksum per thread to out[blocks * 256] (device, caller-owned).
+ * LADDER_PROBE_BF16 runs v_mfma_f32_32x32x16_bf16 (the split GEMM's instruction),
+ * LADDER_PROBE_FP64 v_mfma_f64_16x16x4_f64 (the FP64 GEMM's).  *flops (host, may be
+ * NULL) receives the flops of the launch; timing it gives the rate the chip sustains
+ * under its clock and power limits, beside the published peaks.  Asynchronous on
+ * `stream`.  iters in [1, 2^32], blocks in [1, 2^20].
+ */
+#define LADDER_PROBE_BF16 0
+#define LADDER_PROBE_FP64 1
+int ladder_mfma_probe(int kind, int64_t iters, int64_t blocks, double* out, double* flops, void* stream);
+
+/*
  * Per-stage timing with HIP events (for measurement, off by default).
  * ladder_profile_start() clears the record and makes every later kernel launch
  * of this library bracketed by two hipEvents recorded on the launch stream.

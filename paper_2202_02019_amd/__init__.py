@@ -10,6 +10,6 @@ from .ladder import (  # noqa: F401
     workspace_size, forward, adjoint, tau_gradient_workspace_size, tau_gradient, autotune, autotune_load,
     autotune_reset, w_intermediate, metric_contraction,
     back_transform_workspace_size, back_transform, excited_amplitudes, ov3_abci_workspace_size, ov3_abci,
-    ov3_abic_workspace_size, ov3_abic, metric_contraction_pairs, mp2_amplitudes, amplitude_update, batched,
+    ov3_abic_workspace_size, ov3_abic, metric_contraction_pairs, mfma_probe, PROBE_BF16, PROBE_FP64, mp2_amplitudes, amplitude_update, batched,
     batched_workspace_size, LadderEnergy, ladder_energy, library_path, exported_symbols, profile_start, profile_stop,
 )

@@ -661,6 +661,50 @@ __global__ __launch_bounds__(256) void abic_wam_kernel(const double* __restrict_
     }
 }
 
+// MFMA ceiling probe: every wave issues `iters` rounds of four independent MFMAs on
+// register operands (no memory traffic besides one checksum per thread), so the time
+// of a launch is the matrix-core rate the chip sustains under its own clock and power
+// limits.  KIND 0: v_mfma_f32_32x32x16_bf16 (32768 flops), KIND 1: v_mfma_f64_16x16x4_f64
+// (2048 flops).  The operands vary per lane, like real slice data.
+template <int KIND>
+__global__ __launch_bounds__(256) void mfma_probe_kernel(int64_t iters, double* __restrict__ out) {
+    const int lane = threadIdx.x & 63;
+    double sum = 0.0;
+    if constexpr (KIND == 0) {
+        bx8 a, b;
+#pragma unroll
+        for (int i = 0; i < 8; ++i) {
+            a[i] = (__bf16)(1.0f + 0.0078125f * (float)((lane * 8 + i) % 97));
+            b[i] = (__bf16)(0.5f - 0.00390625f * (float)((lane * 5 + 3 * i) % 89));
+        }
+        fx16 acc[4];
+#pragma unroll
+        for (int k = 0; k < 4; ++k)
+#pragma unroll
+            for (int r = 0; r < 16; ++r) acc[k][r] = 0.0f;
+        for (int64_t it = 0; it < iters; ++it) {
+#pragma unroll
+            for (int k = 0; k < 4; ++k) acc[k] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, b, acc[k], 0, 0, 0);
+        }
+#pragma unroll
+        for (int k = 0; k < 4; ++k)
+#pragma unroll
+            for (int r = 0; r < 16; ++r) sum += (double)acc[k][r];
+    } else {
+        const double a = 1.0 + 0.001 * (double)lane, b = 0.5 - 0.0005 * (double)lane;
+        dx4 acc[4];
+#pragma unroll
+        for (int k = 0; k < 4; ++k) acc[k] = dx4{0.0, 0.0, 0.0, 0.0};
+        for (int64_t it = 0; it < iters; ++it) {
+#pragma unroll
+            for (int k = 0; k < 4; ++k) acc[k] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, acc[k], 0, 0, 0);
+        }
+#pragma unroll
+        for (int k = 0; k < 4; ++k) sum += acc[k][0] + acc[k][1] + acc[k][2] + acc[k][3];
+    }
+    out[(int64_t)blockIdx.x * blockDim.x + threadIdx.x] = sum;
+}
+
 // Grid of the tiled packing kernels: tile pairs in x, rows over (y, z).
 dim3 pm_grid(int64_t v, int64_t rows) {
     const int64_t gy = std::min<int64_t>(std::max<int64_t>(rows, 1), 65535);
@@ -1903,6 +1947,22 @@ int ladder_ov3_abic(int64_t o, int64_t v, int64_t n, double R0, const double* L1
     tm.rec.flops = fl;
     tm.rec.bytes = by;
     return LADDER_OK;
+}
+
+int ladder_mfma_probe(int kind, int64_t iters, int64_t blocks, double* out, double* flops, void* stream) {
+    g_last_error.clear();
+    if (kind != LADDER_PROBE_BF16 && kind != LADDER_PROBE_FP64) return fail(LADDER_EUNSUPPORTED, "probe kind %d", kind);
+    if (iters < 1 || iters > ((int64_t)1 << 32) || blocks < 1 || blocks > ((int64_t)1 << 20))
+        return fail(LADDER_EINVAL, "iters must be in [1, 2^32] and blocks in [1, 2^20]");
+    if (!out || !aligned8(out)) return fail(LADDER_EINVAL, "out must be a non-NULL 8-byte aligned device pointer");
+    const double per = kind == LADDER_PROBE_BF16 ? 2.0 * 32 * 32 * 16 : 2.0 * 16 * 16 * 4;
+    if (flops) *flops = (double)blocks * 4.0 * (double)iters * 4.0 * per;  // 4 waves x 4 MFMAs per round
+    hipStream_t st = (hipStream_t)stream;
+    if (kind == LADDER_PROBE_BF16)
+        hipLaunchKernelGGL(mfma_probe_kernel<0>, dim3((unsigned)blocks), dim3(256), 0, st, iters, out);
+    else
+        hipLaunchKernelGGL(mfma_probe_kernel<1>, dim3((unsigned)blocks), dim3(256), 0, st, iters, out);
+    return hip_check(hipGetLastError(), "probe launch");
 }
 
 int ladder_mp2_amplitudes(int64_t o, int64_t v, int64_t n, const double* Lov, const double* eps, double* t,

@@ -31,7 +31,7 @@ EXPORTS = (
     "ladder_autotune_reset", "ladder_metric_contraction",
     "ladder_back_transform_workspace_size", "ladder_back_transform", "ladder_excited_amplitudes",
     "ladder_ov3_abci_workspace_size", "ladder_ov3_abci", "ladder_ov3_abic_workspace_size", "ladder_ov3_abic",
-    "ladder_metric_contraction_pairs",
+    "ladder_metric_contraction_pairs", "ladder_mfma_probe",
     "ladder_mp2_amplitudes", "ladder_amplitude_update", "ladder_batched_workspace_size",
     "ladder_batched", "ladder_strerror", "ladder_last_error", "ladder_shutdown",
     "ladder_profile_start", "ladder_profile_stop",
@@ -110,6 +110,7 @@ def _load():
     lib.ladder_ov3_abci_workspace_size.argtypes = [i64, i64, i64, ctypes.POINTER(sz)]
     lib.ladder_ov3_abci.argtypes = [i64, i64, i64, vp, vp, vp, vp, dbl, dbl, vp, vp, vp, sz, vp]
     lib.ladder_metric_contraction_pairs.argtypes = [i64, i64, vp, vp, dbl, dbl, vp, vp]
+    lib.ladder_mfma_probe.argtypes = [ctypes.c_int, i64, i64, vp, ctypes.POINTER(dbl), vp]
     lib.ladder_ov3_abic_workspace_size.argtypes = [i64, i64, i64, op, ctypes.POINTER(sz)]
     lib.ladder_ov3_abic.argtypes = [i64, i64, i64, dbl, vp, vp, vp, vp, vp, vp, vp, dbl, dbl, vp, vp, vp, sz, op, vp]
     lib.ladder_mp2_amplitudes.argtypes = [i64, i64, i64, vp, vp, vp, vp]
@@ -122,7 +123,7 @@ def _load():
               "ladder_back_transform_workspace_size",
               "ladder_back_transform", "ladder_excited_amplitudes", "ladder_ov3_abci_workspace_size",
               "ladder_ov3_abci", "ladder_ov3_abic_workspace_size", "ladder_ov3_abic", "ladder_metric_contraction_pairs",
-              "ladder_mp2_amplitudes",
+              "ladder_mp2_amplitudes", "ladder_mfma_probe",
               "ladder_amplitude_update", "ladder_batched_workspace_size", "ladder_batched"):
         getattr(lib, f).restype = ctypes.c_int
     lib.ladder_strerror.argtypes = [ctypes.c_int]
@@ -403,6 +404,21 @@ def metric_contraction_pairs(Z, W, *, pairs, n, V=None, alpha=1.0, beta=0.0, str
     _check(_load().ladder_metric_contraction_pairs(pairs, n, _ptr(Z), _ptr(W), float(alpha), float(beta), _ptr(V),
                                                    _stream(stream)))
     return V
+
+
+PROBE_BF16 = 0
+PROBE_FP64 = 1
+
+
+def mfma_probe(kind, iters, blocks, out=None, stream=None):
+    """Launches the matrix-core ceiling probe; returns (out [blocks*256] checksums, flops)."""
+    if out is None:
+        out = torch.empty((blocks * 256,), dtype=torch.float64, device="cuda")
+    _need(out, "out", (blocks * 256,))
+    fl = ctypes.c_double(0.0)
+    _check(_load().ladder_mfma_probe(int(kind), int(iters), int(blocks), _ptr(out), ctypes.byref(fl),
+                                     _stream(stream)))
+    return out, fl.value
 
 
 def mp2_amplitudes(Lov, eps, *, o, v, n, t=None, stream=None):

@@ -197,6 +197,16 @@ def test_ov3_abic_validation():
     assert call(opts=_opts(precision=B.SPLIT_BF16, n_slices=9)) == EUNSUPPORTED
 
 
+def test_mfma_probe_validation():
+    lib = _lib()
+    fl = ctypes.c_double(0.0)
+    assert lib.ladder_mfma_probe(7, 10, 4, FAKE, ctypes.byref(fl), None) == EUNSUPPORTED
+    assert lib.ladder_mfma_probe(B.PROBE_BF16, 0, 4, FAKE, ctypes.byref(fl), None) == EINVAL
+    assert lib.ladder_mfma_probe(B.PROBE_FP64, 10, 0, FAKE, ctypes.byref(fl), None) == EINVAL
+    assert lib.ladder_mfma_probe(B.PROBE_FP64, 10, 4, None, ctypes.byref(fl), None) == EINVAL
+    assert lib.ladder_mfma_probe(B.PROBE_FP64, 10, 4, FAKE + 4, ctypes.byref(fl), None) == EINVAL
+
+
 def test_autotune_validation_and_cache(tmp_path):
     """Argument checks run before any HIP call; the cache file is parsed line by line (other
     devices' lines and junk are skipped) and a tuned batch size changes the ragged-batch plan."""

@@ -369,6 +369,18 @@ def test_retinal_split_sampled(dev):
     assert eR <= SPLIT_TOL_RX and eX <= SPLIT_TOL_RX
 
 
+@pytest.mark.parametrize("kind", [P.PROBE_BF16, P.PROBE_FP64])
+def test_mfma_probe(dev, kind):
+    """The ceiling probe runs, reports the flops of its launch and writes finite, repeatable
+    checksums (the same register-only arithmetic twice)."""
+    a, fl = P.mfma_probe(kind, 64, 16)
+    b, fl2 = P.mfma_probe(kind, 64, 16)
+    torch.cuda.synchronize()
+    per = 2 * 32 * 32 * 16 if kind == P.PROBE_BF16 else 2 * 16 * 16 * 4
+    assert fl == fl2 == 16 * 4 * 64 * 4 * per
+    assert torch.isfinite(a).all() and torch.equal(a, b) and float(a.abs().sum()) > 0
+
+
 def test_split_autograd(dev):
     o, v, n = 3, 21, 25
     L, tau, w = gaussian_inputs(19, o, v, n)
