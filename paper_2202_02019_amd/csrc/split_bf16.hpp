@@ -339,21 +339,24 @@ __global__ __launch_bounds__(SPLIT_THREADS) void gemm_split_kernel(SplitShape sh
         __builtin_amdgcn_s_barrier();  // every wave's step-kt loads landed; step kt-1 reads are finished
         if (kt + 2 < kend) dma(nxt, kt + 2);
 
-        bx8 bq[S][2];
+        // every fragment of the step is read before the first MFMA, so no LDS wait sits
+        // between MFMAs (S A-fragments and 2S B-fragments, 12 S registers)
+        bx8 bq[S][2], ap[S];
 #pragma unroll
         for (int q = 0; q < S; ++q) {
             bq[q][0] = __builtin_bit_cast(bx8, *(const ux8*)(&cur.t[1][q][b_off0]));
             bq[q][1] = __builtin_bit_cast(bx8, *(const ux8*)(&cur.t[1][q][b_off1]));
+            ap[q] = __builtin_bit_cast(bx8, *(const ux8*)(&cur.t[0][q][a_off]));
         }
+        __builtin_amdgcn_sched_barrier(0);  // keep the scheduler from sinking reads between the MFMAs
 #pragma unroll
         for (int p = 0; p < S; ++p) {
-            const bx8 ap = __builtin_bit_cast(bx8, *(const ux8*)(&cur.t[0][p][a_off]));
 #pragma unroll
             for (int q = 0; q < S - p; ++q) {
                 const int g = (p + q) < 2 ? (p + q) : 2;
 #pragma unroll
                 for (int bj = 0; bj < 2; ++bj)
-                    acc[g][bj] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ap, bq[q][bj], acc[g][bj], 0, 0, 0);
+                    acc[g][bj] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ap[p], bq[q][bj], acc[g][bj], 0, 0, 0);
             }
         }
 
