@@ -146,7 +146,7 @@ def main():
     args = ap.parse_args()
 
     if args.gpus != 1:
-        print("bench.py: this build measures one GPU only (the ladder runs on one MI355X); "
+        print("bench.py: the ladder is measured on one GPU (one MI355X); "
               "--gpus %d is not supported" % args.gpus, file=sys.stderr)
         sys.exit(2)
 
