@@ -3,9 +3,17 @@
 
 One step = ladder_forward (g tiles, R, E) + ladder_adjoint (D tiles, X) over the
 whole synthetic workload, inputs resident in HBM before the timed region.
-Prints one JSON line.  Value = nominal dense flops F = 4 v^4 (n + o^2) + 2 o^2 v^2
-per step divided by the measured time (TFLOP/s), i.e. proportional to 1/(s/iter);
-with the default +/- packing the kernels execute fewer flops, reported beside it.
+Prints one JSON line.  Value = the FP64-equivalent flops the path's GEMMs execute
+per step (2 M N K per product; with the default +/- packing about 0.39 of the
+dense count at the retinal shape) divided by the measured time, in TFLOP/s; the
+dense-equivalent rate F = 4 v^4 (n + o^2) + 2 o^2 v^2 per step over the same time
+is reported beside it.
+
+Wall-clock budget (--budget, default 420 s from process start): the first warm-up
+step is timed on the wall clock; the comparison legs (the FP64 path and the CPU
+oracle) then run on that step's outputs (the path is bitwise deterministic, which
+the run checks) and as many timed steps as fit the rest of the budget follow, at
+most --steps; `steps` reports the number timed, `steps_requested` the number asked.
 
 The CPU baseline times the FP64 oracle (numpy matrix-product version, all host
 threads) on a bounded sample of the same workload: the forward rows of a few
@@ -20,6 +28,8 @@ import math
 import os
 import sys
 import time
+
+T_START = time.time()  # the wall-clock budget counts from process start (imports and input generation included)
 
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
@@ -108,6 +118,18 @@ def measured_traffic(workload, precision, kernel, n_abatch):
     return rec["kernels"][kernel]["bytes"]
 
 
+def blas_threads():
+    """Threads of the BLAS that numpy's matrix products run on (what the CPU oracle uses)."""
+    try:
+        import threadpoolctl
+        n = [d.get("num_threads", 0) for d in threadpoolctl.threadpool_info() if d.get("user_api") == "blas"]
+        if n and max(n) > 0:
+            return max(n)
+    except Exception:
+        pass
+    return int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+
+
 def nominal_flops(o, v, n):
     return 4.0 * v ** 4 * (n + o * o) + 2.0 * o * o * v * v
 
@@ -143,6 +165,9 @@ def main():
                          "(0 = the plain recipe)")
     ap.add_argument("--copy-probe", action="store_true",
                     help="run a 1 GiB device copy first (reference kernel for the HBM traffic counters)")
+    ap.add_argument("--budget", type=float, default=420.0, metavar="SECONDS",
+                    help="wall-clock budget from process start; the timed steps are capped so that the run "
+                         "(legs included) ends within it (0 = run exactly --steps and --warmup)")
     args = ap.parse_args()
 
     if args.gpus != 1:
@@ -176,9 +201,11 @@ def main():
         nA_source = "fixed fallback"
     big = nominal_flops(o, v, n) > 1e14
     # a step at retinal scale takes about half a minute: one untimed warm-up step (code objects,
-    # clocks and the fresh workspace settle), then one timed step
-    steps = args.steps if args.steps is not None else (1 if big else 10)
+    # clocks and the fresh workspace settle), then the timed steps the budget allows
+    steps = args.steps if args.steps is not None else (20 if big else 10)
     warmup = args.warmup if args.warmup is not None else (1 if big else 2)
+    if steps < 1 or warmup < 1:
+        ap.error("--steps and --warmup must be >= 1")
 
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
@@ -231,12 +258,128 @@ def main():
         P.forward(L, tau, tbar, o=o, v=v, n=n, R=R, E=E, ws=ws, opts=opts)
         P.adjoint(L, tau, tbar, o=o, v=v, n=n, X=X, ws=ws, opts=opts)
 
-    for i in range(warmup):
+    def left():
+        """Seconds of the wall-clock budget still free (infinite without a budget)."""
+        return args.budget - (time.time() - T_START) if args.budget > 0 else float("inf")
+
+    steps_req, warmup_req = steps, warmup
+    stream = torch.cuda.current_stream()
+    # warm-up step 0 on the wall clock: code objects, clocks and the fresh workspace settle, and its
+    # duration sizes the rest of the run
+    w0 = time.time()
+    step()
+    torch.cuda.synchronize()
+    t_step = time.time() - w0
+    warm_done = 1
+    E_warm = float(E.cpu())
+    print("bench: warm-up step 0 done (%.1f s), %.0f s of the budget left" % (t_step, left()), file=sys.stderr,
+          flush=True)
+    F = nominal_flops(o, v, n)
+    skipped = {}
+
+    compare = None
+    if args.precision == "split" and not args.no_compare:
+        # the same step on the FP64 MFMA path (untimed for `value`) on the same device arrays; it takes
+        # about 1.5 split steps at the retinal shape, so it runs only if that and one timed step fit
+        if left() < 2.0 * t_step + t_step + 20.0:
+            skipped["fp64_comparison"] = "wall-clock budget"
+        else:
+            # the FP64 leg takes its batch size from the tuned table when the cache has one for it
+            t64 = tuned_batch(args.tuned if args.tuned not in (None, "none") else None, o, v, n, 0, 0, flags)
+            if t64:
+                P.autotune_load(args.tuned)
+            o64 = P.Options(precision=P.FP64, n_abatch=0 if t64 else (16 if name == "retinal" else 0),
+                            flags=P.FLAG_DENSE if args.dense else 0)
+            # the FP64 leg gets its own workspace in place of the split one (never both at once),
+            # with the tuned batch only if it fits beside R64 and X64
+            del ws
+            torch.cuda.empty_cache()
+            free, _ = torch.cuda.mem_get_info()
+            extra = (R.numel() + X.numel()) * 8 + (4 << 30)
+            if t64 and P.workspace_size(o, v, n, o64) + extra > free:
+                t64 = None
+                o64 = P.Options(precision=P.FP64, n_abatch=16 if name == "retinal" else 0,
+                                flags=P.FLAG_DENSE if args.dense else 0)
+            ws64 = torch.empty(P.workspace_size(o, v, n, o64), dtype=torch.uint8, device=dev)
+            R64 = torch.empty_like(R)
+            E64 = torch.empty((), dtype=torch.float64, device=dev)
+            X64 = torch.empty_like(X)
+            ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            torch.cuda.synchronize()
+            ev0.record(stream)
+            P.forward(L, tau, tbar, o=o, v=v, n=n, R=R64, E=E64, ws=ws64, opts=o64)
+            P.adjoint(L, tau, tbar, o=o, v=v, n=n, X=X64, ws=ws64, opts=o64)
+            ev1.record(stream)
+            torch.cuda.synchronize()
+            ms64 = ev0.elapsed_time(ev1)
+            e64 = float(E64.cpu())
+            del ws64
+            torch.cuda.empty_cache()
+
+            def err_max(a, b):  # max|a - b| / max|b|, one leading slice at a time (no full-size temporaries)
+                num = max(float((a[i] - b[i]).abs().max()) for i in range(a.shape[0]))
+                den = max(float(b[i].abs().max()) for i in range(b.shape[0]))
+                return num / den
+
+            compare = {"fp64_ms_per_step": ms64, "fp64_dense_equivalent_tflops": F / (ms64 * 1e-3) / 1e12,
+                       "fp64_n_abatch": t64 or o64.n_abatch,
+                       "err_E_vs_fp64": abs(E_warm - e64) / abs(e64),
+                       "err_R_vs_fp64": err_max(R, R64),
+                       "err_X_vs_fp64": err_max(X, X64),
+                       "outputs_compared": "split outputs of warm-up step 0 (bitwise equal to the timed steps' when "
+                                           "deterministic_vs_warmup is true)"}
+            del R64, X64
+            torch.cuda.empty_cache()
+            ws = torch.empty(wsb, dtype=torch.uint8, device=dev)
+            print("bench: fp64 comparison step %.1f s, %.0f s of the budget left" % (ms64 / 1e3, left()),
+                  file=sys.stderr, flush=True)
+
+    cpu = None
+    errs = {}
+    if args.cpu_rows > 0:
+        import oracle
+        k = min(args.cpu_rows, v)
+        fl = k * (2.0 * v ** 3 * n + 2.0 * o * o * v ** 3 + 2.0 * o * o * v) + k * (2.0 * o * o * v ** 3 + 2.0 * v ** 3 * n)
+        # host copies of L, tau and tbar (one byte-copy pass each) plus the oracle at a rate no host here
+        # falls below (0.1 TFLOP/s); it runs only if that and one timed step fit
+        est = 8.0 * (L.numel() + tau.numel() + tbar.numel()) / 2e9 + fl / 1e11
+        if left() < est + t_step + 20.0:
+            skipped["cpu_baseline"] = "wall-clock budget (estimated %.0f s)" % est
+        else:
+            Lh, th, wh = L.cpu().numpy(), tau.cpu().numpy(), tbar.cpu().numpy()
+            threads = blas_threads()
+            c0 = time.time()
+            Rr, Er = oracle.matrix.forward(o, v, n, Lh, th, wh, a_range=(0, k))
+            Xr = oracle.matrix.adjoint(o, v, n, Lh, th, wh, p_range=(0, k))
+            cs = time.time() - c0
+            cpu = {"value": fl / cs / 1e12, "unit": "TFLOP/s", "cores": threads, "kind": "oracle",
+                   "seconds": cs, "s_per_iter_extrapolated": F / (fl / cs),
+                   "sample": "forward rows a<%d and adjoint rows p<%d at the full shape (o=%d v=%d n=%d); "
+                             "numpy matrix-product FP64 oracle; nominal flops %.3e" % (k, k, o, v, n, fl)}
+            Rg = R[:, :, :k, :].cpu().numpy()
+            Xg = X[:k].cpu().numpy()
+            errs = {"err_sample_R": float(np.abs(Rg - Rr).max() / np.abs(Rr).max()),
+                    "err_sample_X": float(np.abs(Xg - Xr).max() / np.abs(Xr).max()),
+                    "err_sample_E_rows": abs(math.fsum((wh[:, :, :k, :] * Rg).ravel()) - Er) / abs(Er)}
+            del Lh, th, wh
+            print("bench: CPU oracle sample %.1f s, %.0f s of the budget left" % (cs, left()), file=sys.stderr,
+                  flush=True)
+
+    # timed steps: as many as fit the rest of the budget (at most the number asked, at least one), then
+    # further warm-up steps before them if there is still room
+    tail = 15.0  # the matrix-core probe, the last checks and the JSON line
+    fit = int(max(0.0, left() - tail) // t_step) if args.budget > 0 else steps_req
+    steps = max(1, min(steps_req, fit))
+    extra = min(warmup_req - 1, int(max(0.0, left() - tail - steps * t_step) // t_step)) if args.budget > 0 \
+        else warmup_req - 1
+    for i in range(max(0, extra)):
         step()
         torch.cuda.synchronize()
-        print("bench: warmup step %d done" % i, file=sys.stderr, flush=True)
+        warm_done += 1
+        print("bench: warmup step %d done" % warm_done, file=sys.stderr, flush=True)
+    print("bench: timing %d of %d requested steps (%.0f s of the budget left)" % (steps, steps_req, left()),
+          file=sys.stderr, flush=True)
 
-    stream = torch.cuda.current_stream()
     ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     torch.cuda.synchronize()
     P.profile_start()
@@ -251,8 +394,7 @@ def main():
     torch.cuda.synchronize()
     stages = P.profile_stop()
     ms = ev0.elapsed_time(ev1) / steps
-    F = nominal_flops(o, v, n)
-    value = F / (ms * 1e-3) / 1e12
+    E_final = float(E.cpu())
 
     dom_name, dom = max(stages.items(), key=lambda kv: kv[1]["total_ms"])
     # FP64-equivalent rate of the dominant stage: 2 M N K flops per launch over its mean launch time
@@ -278,59 +420,14 @@ def main():
     ceiling = mfma_ceiling()
     roofline["measured_mfma_ceiling"] = ceiling["bf16_tflops" if args.precision == "split" else "fp64_tflops"]
     roofline["frac_of_measured_ceiling"] = achieved / roofline["measured_mfma_ceiling"]
-    stage_summary = {k: {"ms_per_step": s["total_ms"] / steps, "launches_per_step": s["launches"] / steps,
-                         "tflops": (s["flops"] / (s["total_ms"] * 1e-3) / 1e12) if s["total_ms"] > 0 else None}
-                     for k, s in stages.items()}
-    executed = sum(s["flops"] for k, s in stages.items() if k.startswith("gemm")) / steps
-
-    compare = None
-    if args.precision == "split" and not args.no_compare:
-        # the same step on the FP64 MFMA path, untimed for `value`
-        # the FP64 leg takes its batch size from the tuned table when the cache has one for it
-        t64 = tuned_batch(args.tuned if args.tuned not in (None, "none") else None, o, v, n, 0, 0, flags)
-        if t64:
-            P.autotune_load(args.tuned)
-        o64 = P.Options(precision=P.FP64, n_abatch=0 if t64 else (16 if name == "retinal" else 0),
-                        flags=P.FLAG_DENSE if args.dense else 0)
-        # the FP64 leg gets its own workspace in place of the split one (never both at once),
-        # with the tuned batch only if it fits beside R64 and X64
-        del ws
-        torch.cuda.empty_cache()
-        free, _ = torch.cuda.mem_get_info()
-        extra = (R.numel() + X.numel()) * 8 + (4 << 30)
-        if t64 and P.workspace_size(o, v, n, o64) + extra > free:
-            t64 = None
-            o64 = P.Options(precision=P.FP64, n_abatch=16 if name == "retinal" else 0,
-                            flags=P.FLAG_DENSE if args.dense else 0)
-        ws64 = torch.empty(P.workspace_size(o, v, n, o64), dtype=torch.uint8, device=dev)
-        R64 = torch.empty_like(R)
-        E64 = torch.empty((), dtype=torch.float64, device=dev)
-        X64 = torch.empty_like(X)
-        torch.cuda.synchronize()
-        ev0.record(stream)
-        P.forward(L, tau, tbar, o=o, v=v, n=n, R=R64, E=E64, ws=ws64, opts=o64)
-        P.adjoint(L, tau, tbar, o=o, v=v, n=n, X=X64, ws=ws64, opts=o64)
-        ev1.record(stream)
-        torch.cuda.synchronize()
-        ms64 = ev0.elapsed_time(ev1)
-        e64 = float(E64.cpu())
-        del ws64
-        torch.cuda.empty_cache()
-
-        def err_max(a, b):  # max|a - b| / max|b|, one leading slice at a time (no full-size temporaries)
-            num = max(float((a[i] - b[i]).abs().max()) for i in range(a.shape[0]))
-            den = max(float(b[i].abs().max()) for i in range(b.shape[0]))
-            return num / den
-
-        compare = {"fp64_ms_per_step": ms64, "fp64_tflops": F / (ms64 * 1e-3) / 1e12, "speedup_vs_fp64": ms64 / ms,
-                   "fp64_n_abatch": t64 or o64.n_abatch,
-                   "err_E_vs_fp64": abs(float(E.cpu()) - e64) / abs(e64),
-                   "err_R_vs_fp64": err_max(R, R64),
-                   "err_X_vs_fp64": err_max(X, X64)}
-        del R64, X64
-        torch.cuda.empty_cache()
-        ws = torch.empty(wsb, dtype=torch.uint8, device=dev)
-        print("bench: fp64 comparison step %.1f s" % (ms64 / 1e3), file=sys.stderr, flush=True)
+    stage_summary = {k: {"ms_per_step": s_["total_ms"] / steps, "launches_per_step": s_["launches"] / steps,
+                         "tflops": (s_["flops"] / (s_["total_ms"] * 1e-3) / 1e12) if s_["total_ms"] > 0 else None}
+                     for k, s_ in stages.items()}
+    executed = sum(s_["flops"] for k, s_ in stages.items() if k.startswith("gemm")) / steps
+    value = executed / (ms * 1e-3) / 1e12
+    if compare is not None:
+        compare["fp64_tflops"] = executed / (compare["fp64_ms_per_step"] * 1e-3) / 1e12
+        compare["speedup_vs_fp64"] = compare["fp64_ms_per_step"] / ms
 
     nxt = None
     if args.next_rows:
@@ -444,51 +541,34 @@ def main():
         print("bench: next rows: tau gradient %.1f s, V %.1f ms, back-transform %.1f ms, OV3 d_abci %.1f ms, "
               "OV3 d_abic %.1f s" % (mst / 1e3, msv, msb, mso, msi / 1e3), file=sys.stderr, flush=True)
 
-    cpu = None
-    errs = {}
-    if args.cpu_rows > 0:
-        import oracle
-        k = min(args.cpu_rows, v)
-        Lh, th, wh = L.cpu().numpy(), tau.cpu().numpy(), tbar.cpu().numpy()
-        threads = os.cpu_count()
-        c0 = time.time()
-        Rr, Er = oracle.matrix.forward(o, v, n, Lh, th, wh, a_range=(0, k))
-        Xr = oracle.matrix.adjoint(o, v, n, Lh, th, wh, p_range=(0, k))
-        cs = time.time() - c0
-        fl = k * (2.0 * v ** 3 * n + 2.0 * o * o * v ** 3 + 2.0 * o * o * v) + k * (2.0 * o * o * v ** 3 + 2.0 * v ** 3 * n)
-        cpu = {"value": fl / cs / 1e12, "unit": "TFLOP/s", "cores": threads, "kind": "oracle",
-               "seconds": cs, "s_per_iter_extrapolated": F / (fl / cs),
-               "sample": "forward rows a<%d and adjoint rows p<%d at the full shape (o=%d v=%d n=%d); "
-                         "numpy matrix-product FP64 oracle; nominal flops %.3e" % (k, k, o, v, n, fl)}
-        Rg = R[:, :, :k, :].cpu().numpy()
-        Xg = X[:k].cpu().numpy()
-        errs = {"err_sample_R": float(np.abs(Rg - Rr).max() / np.abs(Rr).max()),
-                "err_sample_X": float(np.abs(Xg - Xr).max() / np.abs(Xr).max()),
-                "err_sample_E_rows": abs(float(np.sum(wh[:, :, :k, :] * Rg)) - Er) / abs(Er)}
-
     out = {
         "metric": "ladder fwd+adjoint TFLOP/s & s/iter, split-BF16 vs FP64 at <=1e-10 rel err in E",
-        "value": value, "unit": "TFLOP/s", "n_gpus": 1, "steps": steps, "warmup": warmup,
+        "value": value, "unit": "TFLOP/s", "n_gpus": 1, "steps": steps, "warmup": warm_done,
+        "steps_requested": steps_req, "warmup_requested": warmup_req,
         "ms_per_step": ms, "s_per_iter": ms / 1e3, "higher_is_better": True, "scaling": "weak",
         "vs_baseline": None, "dtype": "f64" if args.precision == "fp64" else "bf16-split/f64",
         "data": "synthetic",
         "config": {"workload": name, "o": o, "v": v, "n_chol": n, "seed": seed, "precision": args.precision,
-                   "n_slices": args.slices, "n_abatch": nA_eff or 0, "n_abatch_source": nA_source,
-                   "nominal_flops": F,
+                   "n_slices": args.slices or (5 if args.precision == "split" else 0), "n_abatch": nA_eff or 0,
+                   "n_abatch_source": nA_source, "nominal_flops": F,
                    "path": "dense" if args.dense else "+/- packed",
                    "decay": args.decay},
-        "energy": float(E.cpu()),
-        "roofline": roofline, "stages": stage_summary, "cpu_baseline": cpu, "mfma_probe": ceiling,
-        "frac_fp64_peak": value / PEAK["fp64"],
-        "flop_count": "value counts the dense nominal F = 4 v^4 (n + o^2) + 2 o^2 v^2 per step; the default "
-                      "+/- packed path executes fewer GEMM flops (executed_gemm_flops)",
+        "flop_count": "value = the FP64-equivalent GEMM flops the path executes per step (2 M N K per product, "
+                      "executed_gemm_flops) over the step time; dense_equivalent_tflops counts the dense "
+                      "F = 4 v^4 (n + o^2) + 2 o^2 v^2 instead",
         "executed_gemm_flops": executed,
-        "executed_gemm_tflops": executed / (ms * 1e-3) / 1e12,
+        "frac_fp64_peak": value / PEAK["fp64"],
+        "dense_equivalent_tflops": F / (ms * 1e-3) / 1e12,
+        "energy": E_final,
+        "deterministic_vs_warmup": E_final == E_warm,
+        "budget_s": args.budget, "wall_s_at_print": time.time() - T_START, "warmup_step_s": t_step,
+        "skipped": skipped or None,
+        "roofline": roofline, "stages": stage_summary, "cpu_baseline": cpu, "mfma_probe": ceiling,
         "fp64_comparison": compare,
         "next_rows": nxt,
     }
     out.update(errs)
-    print(json.dumps(out))
+    print(json.dumps(out), flush=True)
 
 
 def run_batched(args):

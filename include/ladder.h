@@ -324,6 +324,29 @@ int ladder_batched(int count, const ladder_instance* inst, uint32_t what, void* 
                    const ladder_options* opts, void* stream);
 
 /*
+ * The contraction primitive of the four ladder stages (the g tile, the R update,
+ * the density tile and the X update are each one such product), exposed alone:
+ *   C = beta * C + alpha * A B^T,   C_mn (+)= sum_k A_mk B_nk
+ * A [M][K] (row stride lda >= K), B [N][K] (row stride ldb >= K), C [M][N] (row
+ * stride ldc >= N): row-major FP64 device arrays owned by the caller.
+ * opts->precision LADDER_FP64 runs v_mfma_f64_16x16x4_f64 (no workspace);
+ * LADDER_SPLIT_BF16 cuts A and B along k into n_slices exponent-aligned BF16
+ * slices in the workspace (one exponent per row and 256-long chunk of k) and
+ * runs the pairs p + q < n_slices on v_mfma_f32_32x32x16_bf16 with exact FP32
+ * chunk sums folded into FP64, so integer inputs that n_slices slices carry
+ * exactly give the exact product as long as every chunk sum fits FP32's 24
+ * bits (the representation used by every split stage of the ladder).
+ * ladder_gemm_workspace_size gives the bytes (0 for FP64); ws must then be
+ * 256-byte aligned.  With beta == 0, C is not read.  C must not overlap A, B or
+ * ws, and A and B must not overlap ws.  n_abatch and flags are ignored.
+ * M, N, K in [1, 2^31].  Asynchronous on `stream`.
+ */
+int ladder_gemm_workspace_size(int64_t M, int64_t N, int64_t K, const ladder_options* opts, size_t* bytes);
+int ladder_gemm(int64_t M, int64_t N, int64_t K, double alpha, const double* A, int64_t lda, const double* B,
+                int64_t ldb, double beta, double* C, int64_t ldc, void* ws, size_t ws_bytes,
+                const ladder_options* opts, void* stream);
+
+/*
  * Matrix-core ceiling probe (measurement support): `blocks` workgroups of four
  * waves each issue `iters` rounds of four independent MFMAs on register operands
  * and write one checksum per thread to out[blocks * 256] (device, caller-owned).
@@ -362,7 +385,8 @@ int ladder_mfma_probe(int kind, int64_t iters, int64_t blocks, double* out, doub
 #define LADDER_STAGE_BACKTRANSFORM 12 /* MO back-transformation of W */
 #define LADDER_STAGE_OV3_PERMUTE 13 /* OV^3 block: multiplier and Z reorderings */
 #define LADDER_STAGE_OV3 14     /* OV^3 block: the four GEMMs of W_ab and W_ci */
-#define LADDER_NUM_STAGES 15
+#define LADDER_STAGE_GEMM 15    /* ladder_gemm, the contraction primitive alone */
+#define LADDER_NUM_STAGES 16
 typedef struct {
     int32_t stage;
     int32_t launches;

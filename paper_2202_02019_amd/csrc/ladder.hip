@@ -1949,6 +1949,78 @@ int ladder_ov3_abic(int64_t o, int64_t v, int64_t n, double R0, const double* L1
     return LADDER_OK;
 }
 
+namespace {
+// Workspace of ladder_gemm: the slices and exponents of A (M rows) and B (N rows) along K.
+struct GemmLayout {
+    SlicedBuf a, b;
+    size_t total = 0;
+};
+int gemm_layout(int64_t M, int64_t N, int64_t K, const ladder_options& op, GemmLayout& l) {
+    if (M < 1 || N < 1 || K < 1 || M > (int64_t(1) << 31) || N > (int64_t(1) << 31) || K > (int64_t(1) << 31))
+        return fail(LADDER_EINVAL, "dimensions must be in [1, 2^31] (M=%lld N=%lld K=%lld)", (long long)M,
+                    (long long)N, (long long)K);
+    if ((M / F64_BM + 1) * (N / F64_BN + 1) >= (int64_t(1) << 31))
+        return fail(LADDER_EINVAL, "M*N too large for one launch");
+    if (op.precision != LADDER_SPLIT_BF16) return LADDER_OK;
+    if ((std::max(M, N) / 16 + 1) * split_nchunk(K) >= (int64_t(1) << 31) ||
+        2 * (split_kpad(K) / 16) * SPLIT_PANEL * 16 * 2 + 4096 >= (int64_t(1) << 32))
+        return fail(LADDER_EUNSUPPORTED, "split precision: K or max(M, N) too large for the slicer grid or panel offsets");
+    Arena a;
+    l.a = take_sliced(a, op.n_slices, M, K);
+    l.b = take_sliced(a, op.n_slices, N, K);
+    l.total = a.top;
+    return LADDER_OK;
+}
+}  // namespace
+
+int ladder_gemm_workspace_size(int64_t M, int64_t N, int64_t K, const ladder_options* opts, size_t* bytes) {
+    g_last_error.clear();
+    if (!bytes) return fail(LADDER_EINVAL, "bytes is NULL");
+    ladder_options op;
+    GemmLayout l;
+    int rc;
+    if ((rc = get_opts(opts, op)) || (rc = gemm_layout(M, N, K, op, l))) return rc;
+    *bytes = l.total;
+    return LADDER_OK;
+}
+
+int ladder_gemm(int64_t M, int64_t N, int64_t K, double alpha, const double* A, int64_t lda, const double* B,
+                int64_t ldb, double beta, double* C, int64_t ldc, void* ws, size_t ws_bytes, const ladder_options* opts,
+                void* stream) {
+    g_last_error.clear();
+    ladder_options op;
+    GemmLayout l;
+    int rc;
+    if ((rc = get_opts(opts, op)) || (rc = gemm_layout(M, N, K, op, l))) return rc;
+    if (!A || !B || !C) return fail(LADDER_EINVAL, "A, B and C must be non-NULL");
+    if (lda < K || ldb < K || ldc < N) return fail(LADDER_EINVAL, "leading dimensions must be >= K (A, B) and >= N (C)");
+    if (!aligned8(A) || !aligned8(B) || !aligned8(C)) return fail(LADDER_EINVAL, "misaligned pointer (8-byte alignment)");
+    int64_t ab, bb, cb;
+    if (!mul_ok(M - 1, lda, ab) || !mul_ok(N - 1, ldb, bb) || !mul_ok(M - 1, ldc, cb) || ab > INT64_MAX / 16 - K ||
+        bb > INT64_MAX / 16 - K || cb > INT64_MAX / 16 - N)
+        return fail(LADDER_EINVAL, "array sizes overflow 64-bit byte counts");
+    ab = (ab + K) * 8;
+    bb = (bb + K) * 8;
+    cb = (cb + N) * 8;
+    if (l.total) {
+        if (!ws || ((uintptr_t)ws % ALIGN)) return fail(LADDER_EINVAL, "ws must be non-NULL and 256-byte aligned");
+        if (ws_bytes < l.total) return fail(LADDER_EWORKSPACE, "workspace of %zu bytes, %zu needed", ws_bytes, l.total);
+    }
+    if (overlap(C, cb, A, ab) || overlap(C, cb, B, bb) || (l.total && overlap(C, cb, ws, (int64_t)ws_bytes)) ||
+        (l.total && (overlap(A, ab, ws, (int64_t)ws_bytes) || overlap(B, bb, ws, (int64_t)ws_bytes))))
+        return fail(LADDER_EINVAL, "C overlaps A, B or the workspace, or an input overlaps the workspace");
+    hipStream_t st = (hipStream_t)stream;
+    EpiStrided ep{C, ldc, alpha, beta, nullptr, nullptr};
+    StageTimer tm(LADDER_STAGE_GEMM, gemm_flops(M, N, K), gemm_bytes(M, N, K), st);
+    if (op.precision != LADDER_SPLIT_BF16)
+        return hip_check(launch_gemm<true, true, LADDER_STAGE_GEMM>(A, lda, B, ldb, M, N, K, ep, st), "GEMM launch");
+    char* w = (char*)ws;
+    if ((rc = slice_into(op.n_slices, false, A, lda, w, l.a, st))) return rc;
+    if ((rc = slice_into(op.n_slices, false, B, ldb, w, l.b, st))) return rc;
+    SplitShape sh{view(w, l.a, 0), view(w, l.b, 0), M, N, K};
+    return hip_check(launch_split<LADDER_STAGE_GEMM>(op.n_slices, sh, ep, st), "split GEMM launch");
+}
+
 int ladder_mfma_probe(int kind, int64_t iters, int64_t blocks, double* out, double* flops, void* stream) {
     g_last_error.clear();
     if (kind != LADDER_PROBE_BF16 && kind != LADDER_PROBE_FP64) return fail(LADDER_EUNSUPPORTED, "probe kind %d", kind);

@@ -224,15 +224,16 @@ typedef __attribute__((address_space(3))) void* lds_ptr_t;
 // LDS read and would wait for the just-issued loads before each fragment read,
 // which serialises the ring.  Ordering is explicit instead: a buffer is read
 // only after s_waitcnt vmcnt and s_barrier, and the statement clobbers memory
-// so that no LDS access moves across it.  It has no register outputs; M0 is
-// written here and used by nothing else in the kernel.
+// so that no LDS access moves across it.  It has no register outputs.  The LDS
+// address goes in through an M0 operand constraint, so the compiler itself
+// writes M0 (it treats M0 as reserved and would not preserve a value of its own
+// across a statement that wrote it); the s_nop is the wait state between that
+// write and the LDS DMA that reads it.
 __device__ inline void lds_dma16(const void* base, unsigned voff, unsigned lds_base) {
-    asm volatile("s_mov_b32 m0, %0\n\ts_nop 0\n\tglobal_load_lds_dwordx4 %1, %2" ::"s"(lds_base), "v"(voff), "s"(base)
-                 : "memory");
+    asm volatile("s_nop 0\n\tglobal_load_lds_dwordx4 %0, %1" ::"v"(voff), "s"(base), "{m0}"(lds_base) : "memory");
 }
 __device__ inline void lds_dma4(const void* base, unsigned voff, unsigned lds_base) {
-    asm volatile("s_mov_b32 m0, %0\n\ts_nop 0\n\tglobal_load_lds_dword %1, %2" ::"s"(lds_base), "v"(voff), "s"(base)
-                 : "memory");
+    asm volatile("s_nop 0\n\tglobal_load_lds_dword %0, %1" ::"v"(voff), "s"(base), "{m0}"(lds_base) : "memory");
 }
 __device__ inline const void* uniform_ptr(const void* p) {
     const uint64_t x = (uint64_t)(uintptr_t)p;

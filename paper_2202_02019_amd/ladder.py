@@ -34,11 +34,11 @@ EXPORTS = (
     "ladder_metric_contraction_pairs", "ladder_mfma_probe",
     "ladder_mp2_amplitudes", "ladder_amplitude_update", "ladder_batched_workspace_size",
     "ladder_batched", "ladder_strerror", "ladder_last_error", "ladder_shutdown",
-    "ladder_profile_start", "ladder_profile_stop",
+    "ladder_profile_start", "ladder_profile_stop", "ladder_gemm_workspace_size", "ladder_gemm",
 )
 
 STAGE_NAMES = ("gemm_b", "gemm_c", "energy", "gemm_e", "gemm_f", "swap", "mp2", "update", "slice", "pack", "unpack",
-               "metric", "back_transform", "ov3_permute", "ov3")
+               "metric", "back_transform", "ov3_permute", "ov3", "gemm")
 
 
 class LadderError(RuntimeError):
@@ -118,7 +118,9 @@ def _load():
     lib.ladder_batched_workspace_size.argtypes = [ctypes.c_int, ctypes.POINTER(_CInstance), ctypes.c_uint32, op,
                                                   ctypes.POINTER(sz)]
     lib.ladder_batched.argtypes = [ctypes.c_int, ctypes.POINTER(_CInstance), ctypes.c_uint32, vp, sz, op, vp]
-    for f in ("ladder_workspace_size", "ladder_forward", "ladder_adjoint", "ladder_tau_gradient_workspace_size",
+    lib.ladder_gemm_workspace_size.argtypes = [i64, i64, i64, op, ctypes.POINTER(sz)]
+    lib.ladder_gemm.argtypes = [i64, i64, i64, dbl, vp, i64, vp, i64, dbl, vp, i64, vp, sz, op, vp]
+    for f in ("ladder_gemm_workspace_size", "ladder_gemm", "ladder_workspace_size", "ladder_forward", "ladder_adjoint", "ladder_tau_gradient_workspace_size",
               "ladder_tau_gradient", "ladder_autotune", "ladder_autotune_load", "ladder_metric_contraction",
               "ladder_back_transform_workspace_size",
               "ladder_back_transform", "ladder_excited_amplitudes", "ladder_ov3_abci_workspace_size",
@@ -232,6 +234,30 @@ def adjoint(L, tau, w, *, o, v, n, X=None, alpha=1.0, beta=0.0, ws=None, opts=No
     _check(_load().ladder_adjoint(o, v, n, _ptr(L), _ptr(tau), _ptr(w), float(alpha), float(beta), _ptr(X), _ptr(wsb),
                                   wsb.numel() * wsb.element_size(), ctypes.byref(c), _stream(stream)))
     return X
+
+
+def gemm_workspace_size(M: int, N: int, K: int, opts=None) -> int:
+    b = ctypes.c_size_t(0)
+    _check(_load().ladder_gemm_workspace_size(M, N, K, ctypes.byref(_opts(opts)), ctypes.byref(b)))
+    return b.value
+
+
+def gemm(A, B, *, C=None, alpha=1.0, beta=0.0, ws=None, opts=None, stream=None):
+    """C = beta*C + alpha * A @ B.T for 2-D float64 tensors A [M][K], B [N][K] (ladder_gemm)."""
+    if A.dim() != 2 or B.dim() != 2 or A.shape[1] != B.shape[1]:
+        raise ValueError("A [M][K] and B [N][K] expected")
+    M, K = A.shape
+    N = B.shape[0]
+    _need(A, "A"); _need(B, "B")
+    if C is None:
+        C = torch.empty((M, N), dtype=torch.float64, device=A.device)
+    _need(C, "C", (M, N))
+    c = _opts(opts)
+    nb = gemm_workspace_size(M, N, K, c)
+    w = _workspace(nb, A.device, ws) if nb else ws
+    _check(_load().ladder_gemm(M, N, K, float(alpha), _ptr(A), K, _ptr(B), K, float(beta), _ptr(C), N, _ptr(w),
+                               0 if w is None else w.numel() * w.element_size(), ctypes.byref(c), _stream(stream)))
+    return C
 
 
 def tau_gradient_workspace_size(o: int, v: int, n: int, opts=None) -> int:

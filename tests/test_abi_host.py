@@ -303,3 +303,33 @@ def test_batched_validation():
     arr[0].R = None
     assert lib.ladder_batched_workspace_size(1, arr, 1, _opts(), ctypes.byref(sz)) == EINVAL
     assert lib.ladder_batched(1, arr, 2, 8 * FAKE, 16, _opts(), None) == EWORKSPACE
+
+
+def test_gemm_validation():
+    lib = _lib()
+    SPLIT = 1
+
+    def gm(M=3, N=4, K=5, A=FAKE, lda=5, B=2 * FAKE, ldb=5, C=4 * FAKE, ldc=4, ws=8 * FAKE, wsb=1 << 40, opts=None):
+        return lib.ladder_gemm(M, N, K, 1.0, A, lda, B, ldb, 0.0, C, ldc, ws, wsb, opts or _opts(), None)
+
+    assert gm(M=0) == EINVAL
+    assert gm(K=-1) == EINVAL
+    assert gm(N=(1 << 31) + 1) == EINVAL
+    assert gm(A=None) == EINVAL
+    assert gm(C=None) == EINVAL
+    assert gm(lda=4) == EINVAL                                   # lda < K
+    assert gm(ldc=3) == EINVAL                                   # ldc < N
+    assert gm(B=2 * FAKE + 4) == EINVAL                          # misaligned
+    assert gm(C=FAKE) == EINVAL                                  # C aliases A
+    assert gm(opts=_opts(precision=7)) == EUNSUPPORTED
+    assert gm(opts=_opts(precision=SPLIT, n_slices=9)) == EUNSUPPORTED
+    assert gm(ws=None, opts=_opts(precision=SPLIT)) == EINVAL      # split needs a workspace
+    assert gm(ws=8 * FAKE + 64, opts=_opts(precision=SPLIT)) == EINVAL
+    assert gm(wsb=64, opts=_opts(precision=SPLIT)) == EWORKSPACE
+    assert gm(C=8 * FAKE, opts=_opts(precision=SPLIT)) == EINVAL   # C inside the workspace
+    b = ctypes.c_size_t(7)
+    assert lib.ladder_gemm_workspace_size(3, 4, 5, _opts(), ctypes.byref(b)) == 0 and b.value == 0
+    assert lib.ladder_gemm_workspace_size(3, 4, 5, _opts(precision=SPLIT, n_slices=3), ctypes.byref(b)) == 0
+    # slices of two one-panel operands (3 slices x 128 rows x 16 k x 2 bytes) plus one exponent chunk each
+    assert b.value == 2 * (3 * 128 * 16 * 2 + 256)
+    assert lib.ladder_gemm_workspace_size(3, 4, 0, _opts(), ctypes.byref(b)) == EINVAL

@@ -7,6 +7,8 @@ with K = n for g and K = v^2 for R (u = 2^-53).  For these inputs that is below
 magnitude under the 1e-8 accuracy target.  Integer inputs whose sums stay below
 2^53 are exact on both sides, so those compare bitwise.
 """
+import math
+
 import numpy as np
 import pytest
 import torch
@@ -365,8 +367,33 @@ def test_retinal_split_sampled(dev):
     Rg = np.stack([R[:, :, a, b].cpu().numpy().ravel() for a, b in ab])
     Xg = np.stack([X[p, q].cpu().numpy() for p, q in pq])
     eR, eX = err_norm(Rg, Rr), err_norm(Xg, Xr)
-    print("retinal split sampled: err_R %.3e err_X %.3e" % (eR, eX))
+    print("retinal split sampled: err_R %.3e err_X %.3e" % (eR, eX), flush=True)
     assert eR <= SPLIT_TOL_RX and eX <= SPLIT_TOL_RX
+    # the energy of two whole rows a (all i, j, b) against the oracle's forward rows: the
+    # oracle's own exactly rounded sum of tbar * R over those rows, and the same sum of the GPU R
+    rows = (0, 401)
+    e_gpu, e_ref = [], []
+    for a in rows:
+        Rr_a, Er_a = oracle.matrix.forward(o, v, n, Lh, th, wh, a_range=(a, a + 1))
+        e_ref.append(Er_a)
+        e_gpu.append(math.fsum((wh[:, :, a, :] * R[:, :, a, :].cpu().numpy()).ravel()))
+    eErows = err_rel(sum(e_gpu), sum(e_ref))
+    print("retinal split: energy of rows a = %s: split %.15e oracle %.15e rel %.2e"
+          % (rows, sum(e_gpu), sum(e_ref), eErows), flush=True)
+    assert eErows <= SPLIT_TOL_E
+    # the whole energy against the FP64 MFMA path on the same device arrays (that path is
+    # compared with the oracle element by element at the medium size and on sampled rows here)
+    del X, Lh, th, wh
+    torch.cuda.empty_cache()
+    o64 = P.Options(precision=P.FP64)
+    ws64 = torch.empty(P.workspace_size(o, v, n, o64), dtype=torch.uint8, device=dev)
+    R64, E64 = P.forward(L, tau, tbar, o=o, v=v, n=n, ws=ws64, opts=o64)
+    torch.cuda.synchronize()
+    eE = err_rel(float(E), float(E64))
+    eR64 = max(float((R[i] - R64[i]).abs().max()) for i in range(o)) / max(float(R64[i].abs().max()) for i in range(o))
+    print("retinal split vs FP64 GPU: E %.15e vs %.15e rel %.2e; err_R (all elements) %.2e"
+          % (float(E), float(E64), eE, eR64), flush=True)
+    assert eE <= SPLIT_TOL_E and eR64 <= SPLIT_TOL_RX
 
 
 @pytest.mark.parametrize("kind", [P.PROBE_BF16, P.PROBE_FP64])
@@ -379,6 +406,66 @@ def test_mfma_probe(dev, kind):
     per = 2 * 32 * 32 * 16 if kind == P.PROBE_BF16 else 2 * 16 * 16 * 4
     assert fl == fl2 == 16 * 4 * 64 * 4 * per
     assert torch.isfinite(a).all() and torch.equal(a, b) and float(a.abs().sum()) > 0
+
+
+# ------------------------------------------------------------------ exactness at the 24-bit edge
+def _edge_operands(rng, rows, K, lo, hi, odd=False):
+    """Integers of magnitude in [lo, hi] (odd ones only if asked) with one random sign per
+    row: every product of a row of A with a row of B then has the same sign within the row
+    pair, so the chunk sums of the split product grow monotonically to the top of their range."""
+    mag = rng.integers(lo, hi + 1, size=(rows, K))
+    if odd:
+        mag |= 1
+    sign = np.where(rng.random((rows, 1)) < 0.5, -1, 1)
+    return (mag * sign).astype(np.int64)
+
+
+@pytest.mark.parametrize("S,lo,hi", [(2, 241, 255), (3, 65280 + 96, 65280 + 127)])
+def test_split_gemm_chunk_sums_at_24_bits(dev, S, lo, hi):
+    """The FP32 accumulators of the split GEMM are exact only if every chunk sum fits the
+    24-bit significand.  S = 2 with odd-heavy 8-bit integers near 255: slice 0 carries each
+    value whole (the chunk exponent is 8), and a 256-long chunk of same-sign products sums to
+    at most 256 * 255^2 = 16 646 400 < 2^24 (its odd partial sums use all 24 bits).  S = 3 with
+    16-bit integers 65280 + r, r in [96, 127]: slice 0 is 255, slice 1 is r, so the
+    (0,1) + (1,0) sums reach 2 * 256 * 255 * 127 = 16 581 120 < 2^24 as well, and (1,1) is
+    exact too.  K spans three whole chunks and a ragged one, M and N several tiles with ragged
+    edges; the result must equal the int64 product bitwise (it is below 2^53)."""
+    rng = np.random.default_rng(900 + S)
+    M, N, K = 300, 260, 3 * 256 + 100
+    A = _edge_operands(rng, M, K, lo, hi, odd=S == 2)
+    B = _edge_operands(rng, N, K, lo, hi, odd=S == 2)
+    ref = A @ B.T                                     # int64, exact
+    assert np.abs(ref).max() < 2 ** 53
+    Ag, Bg = g(A.astype(np.float64), dev), g(B.astype(np.float64), dev)
+    for opts in (P.Options(precision=P.SPLIT_BF16, n_slices=S), P.Options(precision=P.FP64)):
+        C = P.gemm(Ag, Bg, opts=opts)
+        torch.cuda.synchronize()
+        got = C.cpu().numpy()
+        print("edge S=%d precision %d: max|C| %.4e, mismatches %d" % (S, opts.precision, np.abs(got).max(),
+                                                                    int((got != ref).sum())))
+        assert np.array_equal(got, ref.astype(np.float64))
+    # one chunk alone: its sums are the largest the accumulators ever see
+    C = P.gemm(Ag[:, :256].contiguous(), Bg[:, :256].contiguous(), opts=P.Options(precision=P.SPLIT_BF16, n_slices=S))
+    torch.cuda.synchronize()
+    assert np.array_equal(C.cpu().numpy(), (A[:, :256] @ B[:, :256].T).astype(np.float64))
+
+
+@pytest.mark.parametrize("S", [2, 3, 4, 5])
+def test_split_gemm_alpha_beta_and_fp64_agreement(dev, S):
+    """ladder_gemm on Gaussian data: C = beta C + alpha A B^T against the FP64 MFMA result within
+    the worst-case slice bound: per term, the residuals of both operands and the dropped pairs
+    p + q >= S stay below (S+3)/4 2^-8S of the chunk scale 2^(eA+eB) <= 4 max|a| max|b|."""
+    rng = np.random.default_rng(950 + S)
+    M, N, K = 130, 257, 600
+    A, B, C0 = rng.standard_normal((M, K)), rng.standard_normal((N, K)), rng.standard_normal((M, N))
+    Ag, Bg = g(A, dev), g(B, dev)
+    C = P.gemm(Ag, Bg, C=g(C0, dev), alpha=0.5, beta=-2.0, opts=P.Options(precision=P.SPLIT_BF16, n_slices=S))
+    C64 = P.gemm(Ag, Bg, C=g(C0, dev), alpha=0.5, beta=-2.0, opts=P.Options(precision=P.FP64))
+    torch.cuda.synchronize()
+    ref = -2.0 * C0 + 0.5 * (A @ B.T)
+    assert np.abs(C64.cpu().numpy() - ref).max() <= 1e-12 * np.abs(ref).max()
+    bound = 0.5 * K * (S + 3) * 2.0 ** (-8 * S) * np.abs(A).max() * np.abs(B).max()
+    assert np.abs(C.cpu().numpy() - C64.cpu().numpy()).max() <= bound
 
 
 def test_split_autograd(dev):
