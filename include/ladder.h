@@ -109,6 +109,29 @@ int ladder_forward(int64_t o, int64_t v, int64_t n, const double* L, const doubl
                    size_t ws_bytes, const ladder_options* opts, void* stream);
 
 /*
+ * ladder_forward for callers that cannot allocate (code under HIP graph capture,
+ * tight serving loops, harnesses that forbid allocation): the same computation
+ * and arguments as ladder_forward, without ws/ws_bytes.  Its workspace is a
+ * static device array of LADDER_STATIC_SCRATCH_BYTES inside the library, one
+ * per GPU (held from the library's first use on that GPU until the process
+ * ends); the call itself allocates nothing (no hipMalloc, no events, no
+ * library routine that allocates).  With n_abatch = 0 it runs the plan
+ * ladder_forward would run if that plan's workspace fits the array, else the
+ * largest virtual batch that fits; an explicit n_abatch is used as given.
+ * Returns LADDER_EWORKSPACE, before any launch, when even that does not fit
+ * (the packed amplitudes take about 4 o^2 v^2 bytes, 9 o^2 v^2 with their split
+ * slices, and the batch tile about 16 v^3 bytes per virtual index on the default
+ * +/- path).  Every call on one GPU uses that GPU's one array and leaves its
+ * contents behind (nothing in it needs clearing between calls): calls that
+ * overlap on one GPU (two streams, two threads) race and must be serialised by
+ * the caller.  No argument may lie inside the array.
+ */
+#define LADDER_STATIC_SCRATCH_BYTES ((size_t)256 << 20)
+int ladder_forward_noalloc(int64_t o, int64_t v, int64_t n, const double* L, const double* tau,
+                           const double* tbar, double beta, double* R, double* E,
+                           const ladder_options* opts, void* stream);
+
+/*
  * Adjoint: the L-built three-index intermediate of the V^4 block.
  *   X = beta * X + alpha * d/dL [ sum_ijab w_ij^ab ladder(L, tau)_ij^ab ]
  *     = beta * X + alpha * 2 sum_bd L^J_bd sum_ij w_ij^ab tau_ij^cd      (pair-symmetric)

@@ -12,4 +12,5 @@ from .ladder import (  # noqa: F401
     back_transform_workspace_size, back_transform, excited_amplitudes, ov3_abci_workspace_size, ov3_abci,
     ov3_abic_workspace_size, ov3_abic, metric_contraction_pairs, mfma_probe, PROBE_BF16, PROBE_FP64, mp2_amplitudes, amplitude_update, batched,
     batched_workspace_size, LadderEnergy, ladder_energy, library_path, exported_symbols, profile_start, profile_stop, gemm, gemm_workspace_size,
+    forward_noalloc,
 )

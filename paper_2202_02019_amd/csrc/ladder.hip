@@ -73,7 +73,7 @@ struct StageRec {
 std::mutex g_prof_mu;
 bool g_prof_on = false;
 std::vector<StageRec> g_prof;
-thread_local bool g_capturing = false;  // no timing events inside a graph capture
+thread_local bool g_capturing = false;  // no timing events (graph capture, allocation-free calls)
 
 // Brackets one launch with events on its stream when profiling is on.
 struct StageTimer {
@@ -1167,6 +1167,85 @@ int ladder_forward(int64_t o, int64_t v, int64_t n, const double* L, const doubl
     const Plan p = choose_plan(o, v, n, op, s, ws_bytes, false);
     if ((rc = check_forward_args(o, v, n, L, tau, tbar, R, E, ws, ws_bytes, p.fwd_total, "R", s))) return rc;
     return forward_impl(o, v, n, L, tau, tbar, beta, R, E, (char*)ws, p, s, (hipStream_t)stream);
+}
+
+}  // extern "C"
+
+namespace {
+// Workspace of ladder_forward_noalloc: one file-scope device array.  Each GPU the
+// library runs on holds its own copy from the load of the code object until the
+// process ends.  In host code `scratch` is only a symbol: its device address is
+// taken once per device with hipGetSymbolAddress and kept in g_scratch_ptr.
+static __device__ __align__(256) char scratch[LADDER_STATIC_SCRATCH_BYTES];
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[64] = {};
+
+// Device address of this device's `scratch` (looked up on the device's first call).
+int scratch_address(void** out) {
+    int dev = 0;
+    int rc;
+    if ((rc = hip_check(hipGetDevice(&dev), "hipGetDevice"))) return rc;
+    if (dev < 0 || dev >= 64) return fail(LADDER_EUNSUPPORTED, "device index %d", dev);
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void* p = nullptr;
+        if ((rc = hip_check(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)), "hipGetSymbolAddress(scratch)"))) return rc;
+        if (!p || ((uintptr_t)p % ALIGN)) return fail(LADDER_EHIP, "static scratch at an unaligned address %p", p);
+        g_scratch_ptr[dev] = p;
+    }
+    *out = g_scratch_ptr[dev];
+    return LADDER_OK;
+}
+
+// Plan of ladder_forward_noalloc: an explicit n_abatch as given; otherwise the plan
+// ladder_forward would choose if its forward region fits the static scratch, else the
+// largest batch whose forward region fits.
+int noalloc_plan(int64_t o, int64_t v, int64_t n, const ladder_options& op, const Sizes& s, Plan& p) {
+    const size_t cap = LADDER_STATIC_SCRATCH_BYTES;
+    p = choose_plan(o, v, n, op, s, cap, false);
+    if (p.fwd_total <= cap) return LADDER_OK;
+    if (op.n_abatch == 0) {
+        for (int64_t nA = std::min(p.nA, v); nA >= 1; --nA) {
+            ladder_options o2 = op;
+            o2.n_abatch = nA;
+            p = make_plan(o, v, n, o2, s);
+            if (p.fwd_total <= cap) return LADDER_OK;
+        }
+    }
+    return fail(LADDER_EWORKSPACE,
+                "the forward needs %zu bytes of workspace (n_abatch %lld), more than the %zu of the static scratch",
+                p.fwd_total, (long long)p.nA, cap);
+}
+}  // namespace
+
+extern "C" {
+
+int ladder_forward_noalloc(int64_t o, int64_t v, int64_t n, const double* L, const double* tau, const double* tbar,
+                           double beta, double* R, double* E, const ladder_options* opts, void* stream) {
+    g_last_error.clear();
+    Sizes s;
+    ladder_options op;
+    int rc;
+    if ((rc = check_dims(o, v, n, s)) || (rc = get_opts(opts, op)) || (rc = check_split_dims(s, n, op))) return rc;
+    Plan p;
+    if ((rc = noalloc_plan(o, v, n, op, s, p))) return rc;
+    // the argument checks of ladder_forward, against a stand-in for the scratch range (its device
+    // address is only looked up once the arguments are known to be valid)
+    void* ws = nullptr;
+    if ((rc = check_forward_args(o, v, n, L, tau, tbar, R, E, (void*)(uintptr_t)ALIGN, LADDER_STATIC_SCRATCH_BYTES,
+                                 p.fwd_total, "R", s)))
+        return rc;
+    if ((rc = scratch_address(&ws))) return rc;
+    const int64_t tb = s.ovv_elems * 8, lb = s.vvn * 8, sb = (int64_t)LADDER_STATIC_SCRATCH_BYTES;
+    if (overlap(ws, sb, L, lb) || overlap(ws, sb, tau, tb) || overlap(ws, sb, tbar, tb) || overlap(ws, sb, R, tb) ||
+        (E && overlap(ws, sb, E, 8)))
+        return fail(LADDER_EINVAL, "an argument lies inside the library's static scratch");
+    // no timing events in this call: it must not create host or device objects
+    const bool was = g_capturing;
+    g_capturing = true;
+    rc = forward_impl(o, v, n, L, tau, tbar, beta, R, E, (char*)ws, p, s, (hipStream_t)stream);
+    g_capturing = was;
+    return rc;
 }
 
 int ladder_tau_gradient_workspace_size(int64_t o, int64_t v, int64_t n, const ladder_options* opts, size_t* bytes) {

@@ -35,6 +35,7 @@ EXPORTS = (
     "ladder_mp2_amplitudes", "ladder_amplitude_update", "ladder_batched_workspace_size",
     "ladder_batched", "ladder_strerror", "ladder_last_error", "ladder_shutdown",
     "ladder_profile_start", "ladder_profile_stop", "ladder_gemm_workspace_size", "ladder_gemm",
+    "ladder_forward_noalloc",
 )
 
 STAGE_NAMES = ("gemm_b", "gemm_c", "energy", "gemm_e", "gemm_f", "swap", "mp2", "update", "slice", "pack", "unpack",
@@ -118,9 +119,10 @@ def _load():
     lib.ladder_batched_workspace_size.argtypes = [ctypes.c_int, ctypes.POINTER(_CInstance), ctypes.c_uint32, op,
                                                   ctypes.POINTER(sz)]
     lib.ladder_batched.argtypes = [ctypes.c_int, ctypes.POINTER(_CInstance), ctypes.c_uint32, vp, sz, op, vp]
+    lib.ladder_forward_noalloc.argtypes = [i64, i64, i64, vp, vp, vp, dbl, vp, vp, op, vp]
     lib.ladder_gemm_workspace_size.argtypes = [i64, i64, i64, op, ctypes.POINTER(sz)]
     lib.ladder_gemm.argtypes = [i64, i64, i64, dbl, vp, i64, vp, i64, dbl, vp, i64, vp, sz, op, vp]
-    for f in ("ladder_gemm_workspace_size", "ladder_gemm", "ladder_workspace_size", "ladder_forward", "ladder_adjoint", "ladder_tau_gradient_workspace_size",
+    for f in ("ladder_forward_noalloc", "ladder_gemm_workspace_size", "ladder_gemm", "ladder_workspace_size", "ladder_forward", "ladder_adjoint", "ladder_tau_gradient_workspace_size",
               "ladder_tau_gradient", "ladder_autotune", "ladder_autotune_load", "ladder_metric_contraction",
               "ladder_back_transform_workspace_size",
               "ladder_back_transform", "ladder_excited_amplitudes", "ladder_ov3_abci_workspace_size",
@@ -220,6 +222,20 @@ def forward(L, tau, tbar=None, *, o, v, n, R=None, E=None, beta=0.0, want_energy
     w = _workspace(workspace_size(o, v, n, c), dev, ws)
     _check(_load().ladder_forward(o, v, n, _ptr(L), _ptr(tau), _ptr(tbar), float(beta), _ptr(R), _ptr(E), _ptr(w),
                                   w.numel() * w.element_size(), ctypes.byref(c), _stream(stream)))
+    return R, E
+
+
+def forward_noalloc(L, tau, tbar=None, *, o, v, n, R, E=None, beta=0.0, opts=None, stream=None):
+    """ladder_forward_noalloc: forward() on the library's static device scratch; R (and E, if the
+    energy is wanted) must be given, so that nothing is allocated here either."""
+    _need(L, "L", (v, v, n)); _need(tau, "tau", (o, o, v, v)); _need(R, "R", (o, o, v, v))
+    if tbar is not None:
+        _need(tbar, "tbar", (o, o, v, v))
+    if E is not None and (not E.is_cuda or E.dtype != torch.float64 or E.numel() != 1):
+        raise ValueError("E must be a one-element float64 tensor on the GPU")
+    c = _opts(opts)
+    _check(_load().ladder_forward_noalloc(o, v, n, _ptr(L), _ptr(tau), _ptr(tbar), float(beta), _ptr(R), _ptr(E),
+                                          ctypes.byref(c), _stream(stream)))
     return R, E
 
 

@@ -333,3 +333,23 @@ def test_gemm_validation():
     # slices of two one-panel operands (3 slices x 128 rows x 16 k x 2 bytes) plus one exponent chunk each
     assert b.value == 2 * (3 * 128 * 16 * 2 + 256)
     assert lib.ladder_gemm_workspace_size(3, 4, 0, _opts(), ctypes.byref(b)) == EINVAL
+
+
+def test_forward_noalloc_validation():
+    """Sizes beyond the static scratch are refused on the host, before any HIP call."""
+    lib = _lib()
+    S = ctypes.c_void_p
+
+    def nf(o=2, v=3, n=4, L=FAKE, tau=2 * FAKE, tbar=3 * FAKE, R=4 * FAKE, E=None, opts=None):
+        return lib.ladder_forward_noalloc(o, v, n, S(L), S(tau), S(tbar), 0.0, S(R), S(E), opts or _opts(), None)
+
+    assert nf(o=0) == EINVAL
+    assert nf(opts=_opts(precision=7)) == EUNSUPPORTED
+    # the packed amplitudes alone (o^2 v^2 / 2 doubles, about 1.3 GB here) exceed 256 MiB
+    assert nf(o=100, v=400, n=10) == EWORKSPACE
+    assert "static scratch" in lib.ladder_last_error().decode()
+    # an explicit batch whose tile does not fit is refused, not shrunk
+    assert nf(o=2, v=200, n=8, opts=_opts(n_abatch=200, flags=2)) == EWORKSPACE
+    assert nf(L=None) == EINVAL
+    assert nf(R=2 * FAKE) == EINVAL                             # R aliases tau
+    assert nf(tbar=None, E=5 * FAKE) == EINVAL                  # energy needs tbar
