@@ -46,14 +46,17 @@ WORKLOADS = {
     "azobenzene": (48, 364, 1444, 7),
 }
 PEAK = {"fp64": 78.6, "bf16": 2516.6}  # dense MFMA TFLOP/s, MI355X
+DEFAULT_SLICES = (5, 4)  # (forward, adjoint) slice counts the committed traffic counters are taken at
 
 
 TUNED_CACHE = os.path.join(ROOT, "paper_2202_02019_amd", "tuned_mi355x.jsonl")
 
 
-def tuned_batch(path, o, v, n, precision, slices, flags):
+def tuned_batch(path, o, v, n, precision, slices, flags, slices_adj=None):
     """The batch size a ladder_autotune cache file holds for this shape and options (last line
-    wins, as in ladder_autotune_load), or None."""
+    wins, as in ladder_autotune_load; a line without n_slices_adjoint has the forward's count), or None."""
+    if slices_adj is None:
+        slices_adj = slices
     if not path or not os.path.exists(path):
         return None
     found = None
@@ -63,8 +66,9 @@ def tuned_batch(path, o, v, n, precision, slices, flags):
                 d = json.loads(line)
             except ValueError:
                 continue
-            if (d.get("o"), d.get("v"), d.get("n"), d.get("precision"), d.get("n_slices"), d.get("flags")) == \
-                    (o, v, n, precision, slices if precision == 1 else 0, flags):
+            key = (d.get("o"), d.get("v"), d.get("n"), d.get("precision"), d.get("n_slices"),
+                   d.get("n_slices_adjoint", d.get("n_slices")), d.get("flags"))
+            if key == (o, v, n, precision, slices if precision == 1 else 0, slices_adj if precision == 1 else 0, flags):
                 found = d.get("n_abatch")
     return found
 
@@ -142,7 +146,10 @@ def main():
     ap.add_argument("--workload", default="retinal", choices=sorted(WORKLOADS))
     ap.add_argument("--shape", default=None, help="o,v,n override (probe shapes)")
     ap.add_argument("--precision", default="split", choices=["fp64", "split"])
-    ap.add_argument("--slices", type=int, default=0)
+    ap.add_argument("--slices", type=int, default=0, help="BF16 slices of the forward GEMMs (0 = the library default)")
+    ap.add_argument("--slices-adjoint", type=int, default=None,
+                    help="BF16 slices of the adjoint GEMMs (default: 4 with the default forward count, else the "
+                         "forward's; 4 keeps X within 1e-8 with margin, 5 are needed only for the energy)")
     ap.add_argument("--n-abatch", type=int, default=0)
     ap.add_argument("--cpu-rows", type=int, default=1, help="a (and p) rows the CPU baseline computes; 0 = skip")
     ap.add_argument("--no-compare", action="store_true",
@@ -189,11 +196,16 @@ def main():
         o, v, n = (int(x) for x in args.shape.split(","))
         name = "probe"
     prec_code = 0 if args.precision == "fp64" else 1
+    # the library's rule: n_slices 0 means 5, n_slices_adjoint 0 means n_slices
+    S_fwd = args.slices or 5
+    if args.slices_adjoint is None:
+        args.slices_adjoint = 4 if S_fwd == 5 else 0
+    S_adj = args.slices_adjoint or S_fwd
     flags = 2 if args.dense else 0
     nA_source = "explicit" if args.n_abatch else "library default"
     tuned = None
     if args.n_abatch == 0 and not args.autotune and args.tuned not in (None, "none"):
-        tuned = tuned_batch(args.tuned, o, v, n, prec_code, args.slices or 5, flags)
+        tuned = tuned_batch(args.tuned, o, v, n, prec_code, S_fwd, flags, S_adj)
         if tuned:
             nA_source = "autotune cache " + os.path.relpath(args.tuned, ROOT)
     if args.n_abatch == 0 and tuned is None and not args.autotune and name == "retinal":
@@ -232,7 +244,7 @@ def main():
     E = torch.empty((), dtype=torch.float64, device=dev)
     prec = P.FP64 if args.precision == "fp64" else P.SPLIT_BF16
     opts = P.Options(precision=prec, n_slices=args.slices, n_abatch=args.n_abatch,
-                     flags=P.FLAG_DENSE if args.dense else 0)
+                     flags=P.FLAG_DENSE if args.dense else 0, n_slices_adjoint=args.slices_adjoint)
     tune_s = None
     if tuned:
         P.autotune_load(args.tuned)
@@ -400,11 +412,11 @@ def main():
     # FP64-equivalent rate of the dominant stage: 2 M N K flops per launch over its mean launch time
     fp64_equiv = dom["flops"] / dom["launches"] / (dom["avg_ms"] * 1e-3) / 1e12
     nA_eff = args.n_abatch or tuned
-    default_shape = args.slices in (0, 5) and not args.dense
+    default_shape = (S_fwd, S_adj) == DEFAULT_SLICES and not args.dense
     traffic = measured_traffic(name, args.precision, dom_name, nA_eff) if default_shape else None
     if args.precision == "split":
         # the split method's unit of work: S(S+1)/2 BF16 slice products per FP64-equivalent MAC
-        S = args.slices or 5
+        S = S_adj if dom_name in ("gemm_e", "gemm_f") else S_fwd
         prods = S * (S + 1) // 2
         achieved, peak = fp64_equiv * prods, PEAK["bf16"]
     else:
@@ -549,7 +561,8 @@ def main():
         "vs_baseline": None, "dtype": "f64" if args.precision == "fp64" else "bf16-split/f64",
         "data": "synthetic",
         "config": {"workload": name, "o": o, "v": v, "n_chol": n, "seed": seed, "precision": args.precision,
-                   "n_slices": args.slices or (5 if args.precision == "split" else 0), "n_abatch": nA_eff or 0,
+                   "n_slices": S_fwd if args.precision == "split" else 0,
+                   "n_slices_adjoint": S_adj if args.precision == "split" else 0, "n_abatch": nA_eff or 0,
                    "n_abatch_source": nA_source, "nominal_flops": F,
                    "path": "dense" if args.dense else "+/- packed",
                    "decay": args.decay},

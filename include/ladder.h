@@ -75,11 +75,14 @@ extern "C" {
 #define LADDER_FLAG_DENSE 2u   /* contract all (i,j), (a,b), (c,d): skip the +/- packing */
 
 typedef struct {
-    int32_t precision; /* LADDER_FP64 or LADDER_SPLIT_BF16 */
-    int32_t n_slices;  /* split mode: BF16 slices per operand, 0 = default (see ladder.c docs) */
-    int64_t n_abatch;  /* virtual indices a per batch, 0 = automatic */
-    uint32_t flags;    /* LADDER_FLAG_* */
-    uint32_t reserved; /* must be 0 */
+    int32_t precision;        /* LADDER_FP64 or LADDER_SPLIT_BF16 */
+    int32_t n_slices;         /* split mode: BF16 slices per operand of the forward's GEMMs (the g tile and
+                                 the R update) and of every other split product; 0 = the default, 5;
+                                 otherwise 2..6 */
+    int64_t n_abatch;         /* virtual indices a per batch, 0 = automatic */
+    uint32_t flags;           /* LADDER_FLAG_* */
+    int32_t n_slices_adjoint; /* split mode: slices of the adjoint's GEMMs (the density tile and the X
+                                 update); 0 = n_slices, otherwise 2..6; ignored (normalised to 0) in FP64 */
 } ladder_options;
 
 /* Defaults: precision FP64, automatic batch, no flags.  `opts` may be NULL in

@@ -135,16 +135,22 @@ int get_opts(const ladder_options* in, ladder_options& o) {
     if (in) o = *in;
     if (o.precision != LADDER_FP64 && o.precision != LADDER_SPLIT_BF16)
         return fail(LADDER_EUNSUPPORTED, "unknown precision %d", (int)o.precision);
+    if (o.n_slices_adjoint < 0) return fail(LADDER_EINVAL, "n_slices_adjoint must be >= 0");
     if (o.precision == LADDER_SPLIT_BF16) {
         if (o.n_slices == 0) o.n_slices = DEFAULT_SLICES;
         if (o.n_slices < 2 || o.n_slices > SPLIT_MAX_S)
             return fail(LADDER_EUNSUPPORTED, "n_slices must be 0 (default %d) or in [2, %d], got %d", DEFAULT_SLICES,
                         SPLIT_MAX_S, (int)o.n_slices);
+        if (o.n_slices_adjoint == 0) o.n_slices_adjoint = o.n_slices;
+        if (o.n_slices_adjoint < 2 || o.n_slices_adjoint > SPLIT_MAX_S)
+            return fail(LADDER_EUNSUPPORTED, "n_slices_adjoint must be 0 (= n_slices) or in [2, %d], got %d",
+                        SPLIT_MAX_S, (int)o.n_slices_adjoint);
+    } else {
+        o.n_slices_adjoint = 0;
     }
     if (o.n_abatch < 0) return fail(LADDER_EINVAL, "n_abatch must be >= 0");
     if (o.flags & ~(LADDER_FLAG_GENERAL | LADDER_FLAG_DENSE))
         return fail(LADDER_EUNSUPPORTED, "unknown flag bits 0x%x", o.flags);
-    if (o.reserved != 0) return fail(LADDER_EINVAL, "reserved option field must be 0");
     return LADDER_OK;
 }
 
@@ -186,7 +192,8 @@ SlicedBuf take_sliced(Arena& a, int S, int64_t R, int64_t K) {
 // pair-swapped copies of the general adjoint), and both directions start at the
 // same offset.
 struct Plan {
-    int S = 0;  // 0: FP64
+    int S = 0;   // slices of the forward GEMMs (B, C); 0: FP64
+    int Sa = 0;  // slices of the adjoint GEMMs (E, F); 0: FP64
     int64_t nA = 0, nbatch = 0;
     int64_t b_lo = 0, b_hi = 0;          // batches this call runs (all of them except when timing samples)
     size_t tile_off = 0;                 // FP64 g_A or D_A, nA*v^3 doubles
@@ -217,11 +224,13 @@ constexpr int PM_UNPACK_GRID = 1024;  // blocks of the R unpack kernel (one ener
 Plan make_plan(int64_t o, int64_t v, int64_t n, const ladder_options& op, const Sizes& s) {
     Plan p;
     p.S = op.precision == LADDER_SPLIT_BF16 ? op.n_slices : 0;
+    p.Sa = op.precision == LADDER_SPLIT_BF16 ? op.n_slices_adjoint : 0;
+    const int Smax = std::max(p.S, p.Sa);
     const bool packed = !(op.flags & (LADDER_FLAG_GENERAL | LADDER_FLAG_DENSE));
     int64_t nA = op.n_abatch;
     if (nA == 0) {
         int64_t per_a = s.vvv * 8 * (packed ? 2 : 1);  // the tile, plus its packed halves on the +/- path
-        if (p.S) per_a += (int64_t)(slice_bytes(p.S, v, s.vv) + exp_bytes(v, s.vv));
+        if (Smax) per_a += (int64_t)(slice_bytes(Smax, v, s.vv) + exp_bytes(v, s.vv));
         nA = (int64_t)(LADDER_DEFAULT_TILE_BYTES / (size_t)per_a);
         // several batches, so that no v^4-sized array is ever held at once
         nA = std::min(nA, packed ? (v + 3) / 4 : (v + 1) / 2);
@@ -240,7 +249,7 @@ Plan make_plan(int64_t o, int64_t v, int64_t n, const ladder_options& op, const 
         // packed path's tile (alpha)), or rows v^2 along K = n_A v (tile (beta)); room for either
         p.tile_sl.R = nA * v;
         p.tile_sl.K = s.vv;
-        p.tile_sl.s_off = a.take(std::max(slice_bytes(p.S, nA * v, s.vv), slice_bytes(p.S, s.vv, nA * v)));
+        p.tile_sl.s_off = a.take(std::max(slice_bytes(Smax, nA * v, s.vv), slice_bytes(Smax, s.vv, nA * v)));
         p.tile_sl.e_off = a.take(std::max(exp_bytes(nA * v, s.vv), exp_bytes(s.vv, nA * v)));
     }
     const size_t common = a.top;
@@ -286,12 +295,12 @@ Plan make_plan(int64_t o, int64_t v, int64_t n, const ladder_options& op, const 
     if (!p.pm) {
         if (general) p.swap_off = d.take((size_t)s.ovv_elems * 16);
         if (p.S) {
-            p.w_ij = take_sliced(d, p.S, s.vv, s.oo);
-            p.tau_ij = take_sliced(d, p.S, s.vv, s.oo);
-            p.L_bd = take_sliced(d, p.S, n, s.vv);
+            p.w_ij = take_sliced(d, p.Sa, s.vv, s.oo);
+            p.tau_ij = take_sliced(d, p.Sa, s.vv, s.oo);
+            p.L_bd = take_sliced(d, p.Sa, n, s.vv);
             if (general) {
-                p.pw_ij = take_sliced(d, p.S, s.vv, s.oo);
-                p.ptau_ij = take_sliced(d, p.S, s.vv, s.oo);
+                p.pw_ij = take_sliced(d, p.Sa, s.vv, s.oo);
+                p.ptau_ij = take_sliced(d, p.Sa, s.vv, s.oo);
             }
         }
     } else {
@@ -302,12 +311,12 @@ Plan make_plan(int64_t o, int64_t v, int64_t n, const ladder_options& op, const 
         p.a_dp = d.take((size_t)(nA * v * p.P2v) * 8);
         p.a_dm = d.take((size_t)(nA * v * p.Q2v) * 8 + 8);
         if (p.S) {
-            p.wp_ij = take_sliced(d, p.S, p.P2v, p.P2o);
-            p.wm_ij = take_sliced(d, p.S, std::max<int64_t>(p.Q2v, 1), std::max<int64_t>(p.Q2o, 1));
-            p.tp_ij = take_sliced(d, p.S, p.P2v, p.P2o);
-            p.tm_ij = take_sliced(d, p.S, std::max<int64_t>(p.Q2v, 1), std::max<int64_t>(p.Q2o, 1));
-            p.L_bd = take_sliced(d, p.S, n, s.vv);
-            p.L_b = take_sliced(d, p.S, n, nA * v);
+            p.wp_ij = take_sliced(d, p.Sa, p.P2v, p.P2o);
+            p.wm_ij = take_sliced(d, p.Sa, std::max<int64_t>(p.Q2v, 1), std::max<int64_t>(p.Q2o, 1));
+            p.tp_ij = take_sliced(d, p.Sa, p.P2v, p.P2o);
+            p.tm_ij = take_sliced(d, p.Sa, std::max<int64_t>(p.Q2v, 1), std::max<int64_t>(p.Q2o, 1));
+            p.L_bd = take_sliced(d, p.Sa, n, s.vv);
+            p.L_b = take_sliced(d, p.Sa, n, nA * v);
         }
     }
     if (p.S) {
@@ -326,10 +335,11 @@ Plan make_plan(int64_t o, int64_t v, int64_t n, const ladder_options& op, const 
 // whenever its workspace fits the one they are given.
 struct TuneKey {
     int64_t o, v, n;
-    int32_t precision, slices;
+    int32_t precision, slices, slices_adj;
     uint32_t flags;
     bool operator<(const TuneKey& b) const {
-        return std::tie(o, v, n, precision, slices, flags) < std::tie(b.o, b.v, b.n, b.precision, b.slices, b.flags);
+        return std::tie(o, v, n, precision, slices, slices_adj, flags) <
+               std::tie(b.o, b.v, b.n, b.precision, b.slices, b.slices_adj, b.flags);
     }
 };
 std::mutex g_tune_mu;
@@ -337,7 +347,8 @@ std::map<TuneKey, int64_t> g_tuned;
 int64_t g_tune_gen = 0;  // bumped on every change: part of the batched graph cache key
 
 TuneKey tune_key(int64_t o, int64_t v, int64_t n, const ladder_options& op) {
-    return TuneKey{o, v, n, op.precision, op.precision == LADDER_SPLIT_BF16 ? op.n_slices : 0, op.flags};
+    const bool sp = op.precision == LADDER_SPLIT_BF16;
+    return TuneKey{o, v, n, op.precision, sp ? op.n_slices : 0, sp ? op.n_slices_adjoint : 0, op.flags};
 }
 
 bool tuned_batch(const TuneKey& k, int64_t& nA) {
@@ -840,7 +851,7 @@ int forward_pm(int64_t o, int64_t v, int64_t n, const double* L, const double* t
 int adjoint_pm(int64_t o, int64_t v, int64_t n, const double* L, const double* tau, const double* wt, double alpha,
                double beta, double* X, char* w, const Plan& p, const Sizes& s, hipStream_t st) {
     int rc;
-    const int S = p.S;
+    const int S = p.Sa;  // the adjoint's slice count
     double* D = (double*)(w + p.tile_off);
     double *wp = (double*)(w + p.a_wp), *wm = (double*)(w + p.a_wm), *tp = (double*)(w + p.a_tp),
            *tm = (double*)(w + p.a_tm), *dp = (double*)(w + p.a_dp), *dm = (double*)(w + p.a_dm);
@@ -972,7 +983,8 @@ int batch_plan(int count, const ladder_instance* inst, uint32_t what, const ladd
         if (oi.n_abatch == 0 && tuned_batch(tune_key(x.o, x.v, x.n, oi), tuned)) oi.n_abatch = tuned;
         if (oi.n_abatch == 0) {
             int64_t per_a = s.vvv * 8;
-            if (oi.precision == LADDER_SPLIT_BF16) per_a += (int64_t)(slice_bytes(oi.n_slices, x.v, s.vv) + exp_bytes(x.v, s.vv));
+            if (oi.precision == LADDER_SPLIT_BF16)
+                per_a += (int64_t)(slice_bytes(std::max(oi.n_slices, oi.n_slices_adjoint), x.v, s.vv) + exp_bytes(x.v, s.vv));
             oi.n_abatch = std::max<int64_t>(1, std::min<int64_t>((int64_t)(BATCH_TILE_BYTES / (size_t)per_a), (x.v + 1) / 2));
         }
         bp.inst_opts[i] = oi;
@@ -1297,7 +1309,7 @@ int adjoint_impl(int64_t o, int64_t v, int64_t n, const double* L, const double*
     const bool general = (op.flags & LADDER_FLAG_GENERAL) != 0;
     double* pw = general ? (double*)(w + p.swap_off) : nullptr;
     double* pt = general ? pw + s.ovv_elems : nullptr;
-    const int S = p.S;
+    const int S = p.Sa;  // the adjoint's slice count
     if (general) {
         StageTimer tm(LADDER_STAGE_SWAP, 0.0, 32.0 * (double)s.ovv_elems, st);
         hipLaunchKernelGGL(pair_swap_kernel, dim3(grid_for(s.ovv_elems)), dim3(256), 0, st, wt, pw, o, v);
@@ -1470,9 +1482,11 @@ int ladder_autotune(int64_t o, int64_t v, int64_t n, const double* L, const doub
         if (!f) return fail(LADDER_EINVAL, "cannot append to %s", cache_path);
         fprintf(f,
                 "{\"device\": \"%s\", \"o\": %lld, \"v\": %lld, \"n\": %lld, \"precision\": %d, \"n_slices\": %d, "
-                "\"flags\": %u, \"n_abatch\": %lld, \"est_ms\": %.1f}\n",
+                "\"n_slices_adjoint\": %d, \"flags\": %u, \"n_abatch\": %lld, \"est_ms\": %.1f}\n",
                 device_tag().c_str(), (long long)o, (long long)v, (long long)n, (int)op.precision,
-                op.precision == LADDER_SPLIT_BF16 ? (int)op.n_slices : 0, (unsigned)op.flags, (long long)best, best_est);
+                op.precision == LADDER_SPLIT_BF16 ? (int)op.n_slices : 0,
+                op.precision == LADDER_SPLIT_BF16 ? (int)op.n_slices_adjoint : 0, (unsigned)op.flags, (long long)best,
+                best_est);
         fclose(f);
     }
     return LADDER_OK;
@@ -1503,8 +1517,10 @@ int ladder_autotune_load(const char* cache_path, int* n_loaded) {
         if (!field("\"o\"", o) || !field("\"v\"", v) || !field("\"n\"", n) || !field("\"precision\"", prec) ||
             !field("\"n_slices\"", sl) || !field("\"flags\"", fl) || !field("\"n_abatch\"", nA) || nA < 1 || nA > v)
             continue;
+        long long sla = sl;  // lines without the field: the adjoint uses the forward's count
+        (void)field("\"n_slices_adjoint\"", sla);
         std::lock_guard<std::mutex> g(g_tune_mu);
-        g_tuned[TuneKey{o, v, n, (int32_t)prec, (int32_t)sl, (uint32_t)fl}] = nA;  // later lines win
+        g_tuned[TuneKey{o, v, n, (int32_t)prec, (int32_t)sl, (int32_t)sla, (uint32_t)fl}] = nA;  // later lines win
         ++g_tune_gen;
         ++count;
     }
@@ -2192,7 +2208,7 @@ int ladder_batched(int count, const ladder_instance* inst, uint32_t what, void* 
         gen = g_tune_gen;
     }
     std::vector<int64_t> key = {count, (int64_t)what, (int64_t)(uintptr_t)ws, (int64_t)ws_bytes, bp.op.precision,
-                                bp.op.n_slices, bp.op.n_abatch, (int64_t)bp.op.flags, gen};
+                                bp.op.n_slices, bp.op.n_slices_adjoint, bp.op.n_abatch, (int64_t)bp.op.flags, gen};
     for (int i = 0; i < count; ++i) {
         const ladder_instance& x = inst[i];
         for (int64_t f : {x.o, x.v, x.n, (int64_t)(uintptr_t)x.L, (int64_t)(uintptr_t)x.tau, (int64_t)(uintptr_t)x.tbar,

@@ -50,7 +50,7 @@ class LadderError(RuntimeError):
 
 class _COptions(ctypes.Structure):
     _fields_ = [("precision", ctypes.c_int32), ("n_slices", ctypes.c_int32), ("n_abatch", ctypes.c_int64),
-                ("flags", ctypes.c_uint32), ("reserved", ctypes.c_uint32)]
+                ("flags", ctypes.c_uint32), ("n_slices_adjoint", ctypes.c_int32)]
 
 
 class _CStageStats(ctypes.Structure):
@@ -70,9 +70,10 @@ class Options:
     n_slices: int = 0
     n_abatch: int = 0
     flags: int = 0
+    n_slices_adjoint: int = 0
 
     def c(self) -> _COptions:
-        return _COptions(self.precision, self.n_slices, self.n_abatch, self.flags, 0)
+        return _COptions(self.precision, self.n_slices, self.n_abatch, self.flags, self.n_slices_adjoint)
 
 
 _lib = None

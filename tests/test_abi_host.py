@@ -353,3 +353,19 @@ def test_forward_noalloc_validation():
     assert nf(L=None) == EINVAL
     assert nf(R=2 * FAKE) == EINVAL                             # R aliases tau
     assert nf(tbar=None, E=5 * FAKE) == EINVAL                  # energy needs tbar
+
+
+def test_adjoint_slice_count_option():
+    """n_slices_adjoint: 0 means n_slices; 2..6 otherwise (split only); it sizes the adjoint region."""
+    SPLIT = 1
+    assert fwd(opts=_opts(precision=SPLIT, n_slices_adjoint=7)) == EUNSUPPORTED
+    assert fwd(opts=_opts(precision=SPLIT, n_slices_adjoint=1)) == EUNSUPPORTED
+    assert fwd(opts=_opts(n_slices_adjoint=-1)) == EINVAL
+    o, v, n = 6, 40, 90
+    w44 = P.workspace_size(o, v, n, P.Options(precision=SPLIT, n_slices=4, n_abatch=4))
+    w45 = P.workspace_size(o, v, n, P.Options(precision=SPLIT, n_slices=4, n_slices_adjoint=5, n_abatch=4))
+    w55 = P.workspace_size(o, v, n, P.Options(precision=SPLIT, n_slices=5, n_abatch=4))
+    w54 = P.workspace_size(o, v, n, P.Options(precision=SPLIT, n_slices=5, n_slices_adjoint=4, n_abatch=4))
+    assert w44 < w45 <= w55 and w44 < w54 <= w55
+    # in FP64 the field is ignored
+    assert P.workspace_size(o, v, n, P.Options(n_slices_adjoint=3)) == P.workspace_size(o, v, n)
