@@ -40,6 +40,8 @@ WORKLOADS = {
     "retinal": (78, 657, 2200, 3),
     "autograd": (40, 350, 1200, 5),
     "batched": (None, None, None, 4),
+    # 64 small instances (o in 4..12, v in 20..80, n = 4(o+v)), sizes from seed 8: launch-bound shapes
+    "batched_small": (None, None, None, 8),
     # shapes derived from the paper's other molecules (electrons from the formulas,
     # aug-cc-pVDZ functions, the Cholesky counts the paper quotes): thymine, azobenzene
     "thymine": (33, 228, 967, 6),
@@ -172,6 +174,10 @@ def main():
                          "(0 = the plain recipe)")
     ap.add_argument("--copy-probe", action="store_true",
                     help="run a 1 GiB device copy first (reference kernel for the HBM traffic counters)")
+    ap.add_argument("--fd", type=int, default=200, metavar="K",
+                    help="autograd workload: LadderEnergy forward + backward (split) timed, then K central finite "
+                         "differences of the FP64 energy (step 1e-6) on random L entries against its dE/dL "
+                         "(0 = time the plain forward + adjoint step instead)")
     ap.add_argument("--budget", type=float, default=420.0, metavar="SECONDS",
                     help="wall-clock budget from process start; the timed steps are capped so that the run "
                          "(legs included) ends within it (0 = run exactly --steps and --warmup)")
@@ -188,8 +194,10 @@ def main():
     import paper_2202_02019_amd as P
     from synthetic import gpu as SG
 
-    if args.workload == "batched":
+    if args.workload in ("batched", "batched_small"):
         return run_batched(args)
+    if args.workload == "autograd" and args.fd > 0:
+        return run_autograd(args)
     o, v, n, seed = WORKLOADS[args.workload]
     name = args.workload
     if args.shape:
@@ -584,6 +592,108 @@ def main():
     print(json.dumps(out), flush=True)
 
 
+def run_autograd(args):
+    """The differentiation workload (o=40, v=350, n=1200, seed 5): E = LadderEnergy(L, tau, tbar) with the
+    split forward (R, E) and the library backward (dE/dL by the adjoint, dE/dtau by the transposed ladder),
+    timed per step; then K central differences of the FP64 GPU energy, (E(L + h e_k) - E(L - h e_k)) / 2h with
+    h = 1e-6, on random (a, c, J) entries against the backward's dE/dL.  E is quadratic in each entry, so the
+    central difference has no truncation error: the deviation is rounding only, about u |E| / h."""
+    import numpy as np
+    import torch
+
+    import paper_2202_02019_amd as P
+    from synthetic import gpu as SG
+
+    o, v, n, seed = WORKLOADS["autograd"]
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    L = SG.draw_L_vv(seed, o, v, n)
+    Lov = SG.draw_L_ov(seed, o, v, n)
+    tau = P.mp2_amplitudes(Lov, SG.draw_eps(seed, o, v), o=o, v=v, n=n)
+    del Lov
+    tbar = SG.add_noise(seed, o, v, tau)
+    S_fwd = args.slices or 5
+    S_adj = args.slices_adjoint if args.slices_adjoint is not None else (4 if S_fwd == 5 else 0)
+    opts = P.Options(precision=P.SPLIT_BF16, n_slices=args.slices, n_slices_adjoint=S_adj)
+    Lq = L.clone().requires_grad_(True)
+    tq = tau.clone().requires_grad_(True)
+    steps = args.steps or 3
+    warmup = args.warmup or 1
+
+    def step():
+        Lq.grad = None
+        tq.grad = None
+        E = P.ladder_energy(Lq, tq, tbar, (o, v, n), opts)
+        E.backward()
+        return E
+
+    for _ in range(warmup):
+        step()
+    torch.cuda.synchronize()
+    stream = torch.cuda.current_stream()
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    P.profile_start()
+    ev0.record(stream)
+    for _ in range(steps):
+        E = step()
+    ev1.record(stream)
+    torch.cuda.synchronize()
+    stages = P.profile_stop()
+    ms = ev0.elapsed_time(ev1) / steps
+    executed = sum(s_["flops"] for k, s_ in stages.items() if k.startswith("gemm")) / steps
+    X = Lq.grad.detach()
+    e_split = float(E.detach())
+    print("bench: autograd step %.1f ms, E %.15e" % (ms, e_split), file=sys.stderr, flush=True)
+
+    # central differences of the FP64 energy on K random entries
+    o64 = P.Options(precision=P.FP64)
+    ws64 = torch.empty(P.workspace_size(o, v, n, o64), dtype=torch.uint8, device=dev)
+    R64 = torch.empty_like(tau)
+    E64 = torch.empty((), dtype=torch.float64, device=dev)
+    P.forward(L, tau, tbar, o=o, v=v, n=n, R=R64, E=E64, ws=ws64, opts=o64)
+    e_fp64 = float(E64.cpu())
+    rng = np.random.default_rng(seed)
+    a_, c_, J_ = rng.integers(v, size=args.fd), rng.integers(v, size=args.fd), rng.integers(n, size=args.fd)
+    h = 1e-6
+    fd = np.empty(args.fd)
+    t0 = time.time()
+    for k in range(args.fd):
+        a, c, J = int(a_[k]), int(c_[k]), int(J_[k])
+        x0 = float(L[a, c, J])
+        vals = []
+        for sgn in (1.0, -1.0):
+            L[a, c, J] = x0 + sgn * h
+            P.forward(L, tau, tbar, o=o, v=v, n=n, R=R64, E=E64, ws=ws64, opts=o64)
+            vals.append(float(E64.cpu()))
+        L[a, c, J] = x0
+        fd[k] = (vals[0] - vals[1]) / (2.0 * h)
+        if k % 50 == 49:
+            print("bench: %d central differences (%.0f s)" % (k + 1, time.time() - t0), file=sys.stderr, flush=True)
+    fd_s = time.time() - t0
+    got = X[a_, c_, J_].cpu().numpy()
+    scale = float(X.abs().max())
+    dev_abs = np.abs(fd - got)
+    out = {
+        "metric": "ladder fwd+adjoint TFLOP/s & s/iter, split-BF16 vs FP64 at <=1e-10 rel err in E",
+        "value": executed / (ms * 1e-3) / 1e12, "unit": "TFLOP/s", "n_gpus": 1, "steps": steps, "warmup": warmup,
+        "ms_per_step": ms, "s_per_iter": ms / 1e3, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "bf16-split/f64", "data": "synthetic",
+        "config": {"workload": "autograd", "o": o, "v": v, "n_chol": n, "seed": seed, "precision": "split",
+                   "n_slices": S_fwd, "n_slices_adjoint": S_adj or S_fwd,
+                   "step": "LadderEnergy forward (split R, E) + backward (adjoint dE/dL, transposed ladder dE/dtau)"},
+        "executed_gemm_flops": executed,
+        "stages": {k: {"ms_per_step": s_["total_ms"] / steps} for k, s_ in stages.items()},
+        "energy_split": e_split, "energy_fp64": e_fp64, "err_E_split_vs_fp64": abs(e_split - e_fp64) / abs(e_fp64),
+        "finite_differences": {"count": args.fd, "h": h, "seconds": fd_s,
+                               "max_abs_dev": float(dev_abs.max()), "max_abs_dev_over_max_abs_X": float(dev_abs.max()) / scale,
+                               "median_rel_dev": float(np.median(dev_abs / np.maximum(np.abs(fd), 1e-300))),
+                               "rounding_scale_u_E_over_h": 2.0 ** -53 * abs(e_fp64) / h,
+                               "entries": "(a, c, J) uniform, numpy default_rng(5)"},
+        "roofline": None, "cpu_baseline": None,
+    }
+    print(json.dumps(out), flush=True)
+
+
 def run_batched(args):
     """64 ragged instances: one graph launch of ladder_batched vs 64 sequential calls."""
     import torch
@@ -592,7 +702,8 @@ def run_batched(args):
     import synthetic
     from synthetic import gpu as SG
 
-    sizes = synthetic.batched_sizes(4, 64)
+    small = args.workload == "batched_small"
+    sizes = synthetic.batched_sizes(8, 64, (4, 12), (20, 80)) if small else synthetic.batched_sizes(4, 64)
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
     prec = P.FP64 if args.precision == "fp64" else P.SPLIT_BF16
@@ -665,7 +776,9 @@ def run_batched(args):
         "value": F / (ms * 1e-3) / 1e12, "unit": "TFLOP/s", "n_gpus": 1, "steps": steps, "warmup": warmup,
         "ms_per_step": ms, "s_per_iter": ms / 1e3, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
         "dtype": "f64" if args.precision == "fp64" else "bf16-split/f64", "data": "synthetic",
-        "config": {"workload": "batched", "instances": 64, "sizes_seed": 4, "data_seeds": "1000+m",
+        "config": {"workload": args.workload, "instances": 64, "sizes_seed": 8 if small else 4,
+                   "o_range": [4, 12] if small else [8, 40], "v_range": [20, 80] if small else [60, 300],
+                   "data_seeds": "1000+m",
                    "precision": args.precision, "n_abatch": args.n_abatch,
                    "n_abatch_source": tuned_src or ("explicit" if args.n_abatch else "library default"),
                    "nominal_flops": F},

@@ -161,10 +161,11 @@ def asym_noise_full(seed: int, o: int, v: int, stream: int = STREAM_ASYM) -> np.
     return gaussian(seed, stream, np.arange(o * o * v * v)).reshape(o, o, v, v)
 
 
-def batched_sizes(seed: int = 4, count: int = 64):
-    """(o, v, n) for the ragged batch: o ~ U{8..40}, v ~ U{60..300}, n = 4(o+v)."""
+def batched_sizes(seed: int = 4, count: int = 64, o_range=(8, 40), v_range=(60, 300)):
+    """(o, v, n) for a ragged batch: o ~ U{o_range}, v ~ U{v_range} (inclusive), n = 4(o+v).
+    The defaults are the 64-instance workload (o in 8..40, v in 60..300)."""
     uo = uniform(seed, STREAM_SIZES, np.arange(count))
     uv = uniform(seed, STREAM_SIZES, np.arange(count) + count)
-    o = 8 + np.floor(uo * 33).astype(np.int64)
-    v = 60 + np.floor(uv * 241).astype(np.int64)
+    o = o_range[0] + np.floor(uo * (o_range[1] - o_range[0] + 1)).astype(np.int64)
+    v = v_range[0] + np.floor(uv * (v_range[1] - v_range[0] + 1)).astype(np.int64)
     return [(int(a), int(b), int(4 * (a + b))) for a, b in zip(o, v)]

@@ -546,6 +546,54 @@ def test_batched_matches_single_calls_and_oracle(dev, precision):
         assert e_err(float(d["E"].cpu()), Er) <= tol_e
 
 
+def _recipe_instances(dev, sizes, seed0):
+    """The ragged-batch recipe on the GPU: per instance m, Cholesky vectors and orbital energies
+    drawn with seed seed0 + m, first-order amplitudes by the library, tbar = t + noise."""
+    from synthetic import gpu as SG
+    insts = []
+    for m, (o, v, n) in enumerate(sizes):
+        seed = seed0 + m
+        L = SG.draw_L_vv(seed, o, v, n)
+        Lov = SG.draw_L_ov(seed, o, v, n)
+        tau = P.mp2_amplitudes(Lov, SG.draw_eps(seed, o, v), o=o, v=v, n=n)
+        del Lov
+        tbar = SG.add_noise(seed, o, v, tau)
+        insts.append(dict(o=o, v=v, n=n, L=L, tau=tau, tbar=tbar, R=torch.empty_like(tau),
+                          E=torch.empty((), dtype=torch.float64, device=dev), X=torch.empty_like(L)))
+    return insts
+
+
+@pytest.mark.parametrize("sizes_seed,o_range,v_range", [(4, (8, 40), (60, 300)), (8, (4, 12), (20, 80))],
+                         ids=["config4", "small"])
+def test_batched_64_recipe_instances(dev, sizes_seed, o_range, v_range):
+    """The 64-instance ragged workload (sizes from seed 4, data seeds 1000 + m; and a set of small
+    instances): one ladder_batched graph launch (split precision, the default options) against 64
+    single forward + adjoint calls bitwise, and the four smallest instances against the oracle."""
+    import synthetic
+    sizes = synthetic.batched_sizes(sizes_seed, 64, o_range, v_range)
+    insts = _recipe_instances(dev, sizes, 1000)
+    opts = P.Options(precision=P.SPLIT_BF16)
+    P.batched(insts, P.DO_FORWARD | P.DO_ADJOINT, opts=opts)
+    torch.cuda.synchronize()
+    for d in insts:
+        o, v, n = d["o"], d["v"], d["n"]
+        R1, E1 = P.forward(d["L"], d["tau"], d["tbar"], o=o, v=v, n=n, opts=opts)
+        X1 = P.adjoint(d["L"], d["tau"], d["tbar"], o=o, v=v, n=n, opts=opts)
+        torch.cuda.synchronize()
+        assert torch.equal(d["R"], R1) and torch.equal(d["E"], E1) and torch.equal(d["X"], X1), (o, v, n)
+        del R1, E1, X1
+    small = sorted(range(64), key=lambda m: sizes[m][1] ** 4 * (sizes[m][2] + sizes[m][0] ** 2))[:4]
+    for m in small:
+        d = insts[m]
+        o, v, n = d["o"], d["v"], d["n"]
+        Lh, th, wh = (d[k].cpu().numpy() for k in ("L", "tau", "tbar"))
+        Rr, Er = oracle.matrix.forward(o, v, n, Lh, th, wh)
+        Xr = oracle.matrix.adjoint(o, v, n, Lh, th, wh)
+        eR, eE, eX = err_norm(d["R"].cpu().numpy(), Rr), err_rel(float(d["E"].cpu()), Er), err_norm(d["X"].cpu().numpy(), Xr)
+        print("batched instance %d (%d, %d, %d): err_R %.2e err_E %.2e err_X %.2e" % (m, o, v, n, eR, eE, eX))
+        assert eR <= SPLIT_TOL_RX and eE <= SPLIT_TOL_E and eX <= SPLIT_TOL_RX
+
+
 def test_batched_graph_replay_sees_new_data(dev):
     """The second call with the same shapes and pointers replays the captured graph;
     it must compute on the current contents of the inputs."""
