@@ -487,7 +487,8 @@ hipError_t slice_s(bool transposed, const double* src, int64_t ld, int64_t R, in
     const int64_t nch = split_nchunk(K);
     if (!transposed) {
         const int64_t blocks = ((R + 15) / 16) * nch;
-        hipLaunchKernelGGL((slice_rows_kernel<S>), dim3((unsigned)blocks), dim3(256), 0, st, src, ld, R, K, sl, ex, R);
+        hipLaunchKernelGGL((slice_rows_kernel<S, DenseRows>), dim3((unsigned)blocks), dim3(256), 0, st, DenseRows{src, ld},
+                           R, K, sl, ex, R);
     } else {
         const int64_t blocks = ((R + 31) / 32) * nch;
         hipLaunchKernelGGL((slice_cols_kernel<S>), dim3((unsigned)blocks), dim3(256), 0, st, src, ld, R, K, sl, ex, R);
@@ -511,6 +512,29 @@ int slice_into(int S, bool transposed, const double* src, int64_t ld, char* ws, 
         default: e = hipErrorInvalidValue;
     }
     return hip_check(e, "slice launch");
+}
+
+// Slices of a density tile of the +/- adjoint (rows b.R, length b.K) computed from its packed
+// rows by the row slicer (the same exponents and slices as slicing the FP64 tile).
+template <int S>
+hipError_t slice_tile_s(const PmTileRows& src, const SlicedBuf& b, char* ws, hipStream_t st) {
+    const int64_t blocks = ((b.R + 15) / 16) * split_nchunk(b.K);
+    hipLaunchKernelGGL((slice_rows_kernel<S, PmTileRows>), dim3((unsigned)blocks), dim3(256), 0, st, src, b.R, b.K,
+                       (unsigned short*)(ws + b.s_off), (int*)(ws + b.e_off), b.R);
+    return hipGetLastError();
+}
+int slice_tile_into(int S, const PmTileRows& src, char* ws, const SlicedBuf& b, hipStream_t st) {
+    StageTimer tm(LADDER_STAGE_SLICE, 0.0, (16.0 + 2.0 * S) * (double)b.R * (double)b.K, st);
+    hipError_t e;
+    switch (S) {
+        case 2: e = slice_tile_s<2>(src, b, ws, st); break;
+        case 3: e = slice_tile_s<3>(src, b, ws, st); break;
+        case 4: e = slice_tile_s<4>(src, b, ws, st); break;
+        case 5: e = slice_tile_s<5>(src, b, ws, st); break;
+        case 6: e = slice_tile_s<6>(src, b, ws, st); break;
+        default: e = hipErrorInvalidValue;
+    }
+    return hip_check(e, "tile slice launch");
 }
 
 __global__ void fill_zero_kernel(double* __restrict__ x, int64_t count) {
@@ -910,16 +934,17 @@ int adjoint_pm(int64_t o, int64_t v, int64_t n, const double* L, const double* t
         }
         for (int pass = 0; pass < 2; ++pass) {  // 0: tile (alpha), 1: tile (beta)
             const int64_t M = pass ? A * v : nB * v, K = pass ? nB * v : A * v;
-            {
+            SlicedBuf tl = p.tile_sl;
+            tl.R = M;
+            tl.K = K;
+            if (!S) {  // the FP64 tile for the FP64 GEMM
                 StageTimer tm_(LADDER_STAGE_UNPACK, 0.0, 8.0 * (double)(M * K) + 8.0 * (double)(rowsP * p.P2v + rowsQ * p.Q2v), st);
                 hipLaunchKernelGGL(pm_tile_ab_kernel, pm_grid(v, nB * A), dim3(256), 0, st, dp, dm, v, b0, nB,
                                    pass ? 0 : 1, D);
                 if ((rc = hip_check(hipGetLastError(), "tile launch"))) return rc;
+            } else if ((rc = slice_tile_into(S, PmTileRows{dp, dm, v, b0, nB, pass ? 0 : 1}, w, tl, st))) {
+                return rc;  // the slices of the tile straight from the packed rows (no FP64 tile)
             }
-            SlicedBuf tl = p.tile_sl;
-            tl.R = M;
-            tl.K = K;
-            if (S && (rc = slice_into(S, false, D, K, w, tl, st))) return rc;
             StageTimer tm_(LADDER_STAGE_GEMM_F, gemm_flops(M, n, K), gemm_bytes(M, n, K), st);
             // alpha: X rows (b, y), B = L rows (a, w) for a < A;  beta: X rows (a, y), B = L rows (b, w) of the batch
             EpiStrided ex{X + (pass ? 0 : b0 * v * n), n, 2.0 * alpha, 1.0, nullptr, nullptr};

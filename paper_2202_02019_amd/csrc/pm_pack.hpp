@@ -191,6 +191,30 @@ __host__ __device__ inline void pm_tile_beta_elem(int64_t t, const double* dp, c
     T[t] = a <= b ? pm_density(dp, dm, v, b0, a, b, y, w) : 0.0;
 }
 
+// Element (r, k) of tile (alpha) or (beta) of batch [b0, b0+nB), as pm_tile_alpha_elem /
+// pm_tile_beta_elem define it (rows r, contraction index k), read from the packed rows.
+__host__ __device__ inline double pm_tile_value(const double* dp, const double* dm, int64_t v, int64_t b0, int64_t nB,
+                                                bool alpha, int64_t r, int64_t k) {
+    if (alpha) {  // r = (b - b0) v + y, k = a v + w: D_{ab, w y} for a < b
+        const int64_t b = b0 + r / v, y = r % v, a = k / v, w = k % v;
+        return a < b ? pm_density(dp, dm, v, b0, a, b, w, y) : 0.0;
+    }
+    // r = a v + y, k = (b - b0) v + w: D_{ab, y w} for a <= b
+    const int64_t a = r / v, y = r % v, b = b0 + k / v, w = k % v;
+    (void)nB;
+    return a <= b ? pm_density(dp, dm, v, b0, a, b, y, w) : 0.0;
+}
+
+// Source functor of the split slicer for the density tiles: the slices of a tile are
+// written straight from the packed rows, without the FP64 tile in between.
+struct PmTileRows {
+    const double* dp;
+    const double* dm;
+    int64_t v, b0, nB;
+    int alpha;
+    __device__ double operator()(int64_t r, int64_t k) const { return pm_tile_value(dp, dm, v, b0, nB, alpha != 0, r, k); }
+};
+
 #define PM_GRID_STRIDE(total) \
     for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < (total); t += (int64_t)gridDim.x * blockDim.x)
 

@@ -92,13 +92,20 @@ __host__ __device__ inline int64_t split_index(int64_t r, int64_t k, int64_t nkb
     return ((r >> 7) * nkb + (k >> 4)) * (SPLIT_PANEL * 16) + (r & 127) * 16 + (k & 15);
 }
 
-// K-contiguous source: element (r, k) at src[r*ld + k], r < R, k < K.
+// Row-wise source: element (r, k) = src(r, k), r < R, k < K (DenseRows: src[r*ld + k];
+// the +/- path also slices its density tiles straight from their packed rows).
 // One workgroup per 16 rows and one chunk: thread (rr, kk) = (t/16, t%16) holds
 // k = chunk*256 + 16*kb + kk for kb < 16, so each k-block of the 16 rows is written
 // as one 512-byte run per slice.
-template <int S>
-__global__ __launch_bounds__(256) void slice_rows_kernel(const double* __restrict__ src, int64_t ld, int64_t R,
-                                                         int64_t K, unsigned short* __restrict__ slices,
+struct DenseRows {
+    const double* p;
+    int64_t ld;
+    __device__ double operator()(int64_t r, int64_t k) const { return p[r * ld + k]; }
+};
+
+template <int S, class Src>
+__global__ __launch_bounds__(256) void slice_rows_kernel(Src src, int64_t R, int64_t K,
+                                                         unsigned short* __restrict__ slices,
                                                          int* __restrict__ exps, int64_t exp_ld) {
     constexpr int RB = 16, NKB = SPLIT_KC / 16;
     const int64_t nch = split_nchunk(K), Kp = split_kpad(K);
@@ -112,7 +119,7 @@ __global__ __launch_bounds__(256) void slice_rows_kernel(const double* __restric
 #pragma unroll
     for (int kb = 0; kb < NKB; ++kb) {
         const int64_t k = ch * SPLIT_KC + 16 * kb + kk;
-        x[kb] = (r < R && k < K) ? src[r * ld + k] : 0.0;
+        x[kb] = (r < R && k < K) ? src(r, k) : 0.0;
         mx = fmax(mx, fabs(x[kb]));
     }
 #pragma unroll

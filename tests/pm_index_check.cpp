@@ -192,6 +192,11 @@ int check(int64_t o, int64_t v, int64_t n, int64_t nA, unsigned long long seed) 
                     pm_tile_ab_block(dp.data(), dm.data(), v, b0, nB, r, t, alpha, T2.data(), Pa, Pb, 0, 1, PmNoBarrier{});
                 });
                 bad |= same(T2, T, rows * K, alpha ? "tile alpha" : "tile beta");
+                // the element source of the split tile slicer, (row, k) -> value, equals the tile
+                std::vector<double> T3(rows * K, NAN);
+                for (int64_t r = 0; r < rows; ++r)
+                    for (int64_t k = 0; k < K; ++k) T3[r * K + k] = pm_tile_value(dp.data(), dm.data(), v, b0, nB, alpha, r, k);
+                bad |= same(T3, T, rows * K, alpha ? "tile alpha source" : "tile beta source");
                 // X rows: alpha (b, y) += T[(b-b0, y)][(a, w)] L[(a, w)];  beta (a, y) += T[(a, y)][(b-b0, w)] L[(b, w)]
                 const int64_t row0 = alpha ? b0 * v : 0, k0 = alpha ? 0 : b0 * v;
                 for (int64_t r = 0; r < rows; ++r)

@@ -369,8 +369,9 @@ def test_autograd_gradcheck(dev, o, v, n, seed):
 
 
 def test_retinal_split_sampled(dev):
-    """o=78, v=657, n=2200, seed 3, in the configuration the benchmark times (split BF16, S = 5,
-    +/- packed, the batch size of the committed autotune cache): one forward and one adjoint on
+    """o=78, v=657, n=2200, seed 3, in the configuration the benchmark times (split BF16, 5 forward
+    and 4 adjoint slices, +/- packed, the batch size of the committed autotune cache): one forward
+    and one adjoint on
     the GPU-drawn recipe inputs, then sampled rows of R (all ij for chosen ab) and of X (all J for
     chosen ac) against the oracle, computed one by one from host copies of the same arrays."""
     import os
@@ -384,7 +385,7 @@ def test_retinal_split_sampled(dev):
     tau = P.mp2_amplitudes(Lov, SG.draw_eps(seed, o, v), o=o, v=v, n=n)
     del Lov
     tbar = SG.add_noise(seed, o, v, tau)
-    opts = P.Options(precision=P.SPLIT_BF16)
+    opts = P.Options(precision=P.SPLIT_BF16, n_slices_adjoint=4)
     ws = torch.empty(P.workspace_size(o, v, n, opts), dtype=torch.uint8, device=dev)
     R, E = P.forward(L, tau, tbar, o=o, v=v, n=n, ws=ws, opts=opts)
     X = P.adjoint(L, tau, tbar, o=o, v=v, n=n, ws=ws, opts=opts)
@@ -567,12 +568,13 @@ def _recipe_instances(dev, sizes, seed0):
                          ids=["config4", "small"])
 def test_batched_64_recipe_instances(dev, sizes_seed, o_range, v_range):
     """The 64-instance ragged workload (sizes from seed 4, data seeds 1000 + m; and a set of small
-    instances): one ladder_batched graph launch (split precision, the default options) against 64
-    single forward + adjoint calls bitwise, and the four smallest instances against the oracle."""
+    instances): one ladder_batched graph launch (split precision, 8 virtual indices per batch for
+    every instance, so that the single calls run the same plans) against 64 single forward + adjoint
+    calls bitwise, and the four smallest instances against the oracle."""
     import synthetic
     sizes = synthetic.batched_sizes(sizes_seed, 64, o_range, v_range)
     insts = _recipe_instances(dev, sizes, 1000)
-    opts = P.Options(precision=P.SPLIT_BF16)
+    opts = P.Options(precision=P.SPLIT_BF16, n_abatch=8)
     P.batched(insts, P.DO_FORWARD | P.DO_ADJOINT, opts=opts)
     torch.cuda.synchronize()
     for d in insts:
