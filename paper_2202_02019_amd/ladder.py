@@ -551,10 +551,11 @@ class LadderEnergy(torch.autograd.Function):
         o, v, n = ctx.dims
         gL = gtau = gt = None
         if ctx.needs_input_grad[1]:
-            gtau = tau_gradient(L, tbar, o=o, v=v, n=n, opts=ctx.opts) * gE
+            gtau = tau_gradient(L, tbar, o=o, v=v, n=n, opts=ctx.opts)
+            gtau.mul_(gE)
         if ctx.needs_input_grad[0]:
-            X = adjoint(L, tau, tbar, o=o, v=v, n=n, opts=ctx.opts)
-            gL = X * gE
+            # the incoming gradient is the adjoint's alpha: X = gE * dE/dL in one pass
+            gL = adjoint(L, tau, tbar, o=o, v=v, n=n, alpha=float(gE), opts=ctx.opts)
         if ctx.needs_input_grad[2]:
             gt = R * gE
         return gL, gtau, gt, None, None

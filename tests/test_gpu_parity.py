@@ -355,6 +355,22 @@ def test_split_mixed_slice_counts_integer_bitwise(dev, flags):
     assert np.array_equal(R, Rr) and E == Er and np.array_equal(X, Xr)
 
 
+@pytest.mark.parametrize("decay", [4.0, 8.0])
+def test_split_tiny_decaying_vectors(dev, decay):
+    """The hardest recipe case for the per-(row, 256-chunk) exponents: n = 60 puts every Cholesky
+    index of a row in one chunk, so with vectors decaying as exp(-decay J / n) the smallest entries of
+    a chunk sit decay / ln 2 bits below its exponent.  The default five slices still meet the
+    targets (measured E 9.1e-12 and 5.0e-11)."""
+    o, v, n = 4, 20, 60
+    L, tau, tbar, _, _ = oracle.make_inputs(o, v, n, 1, decay=decay)
+    R, E, X = run(dev, o, v, n, L, tau, tbar, SPLIT5)
+    Rr, Er = oracle.forward(o, v, n, L, tau, tbar)
+    Xr = oracle.adjoint(o, v, n, L, tau, tbar)
+    eR, eE, eX = err_norm(R, Rr), err_rel(E, Er), err_norm(X, Xr)
+    print("split tiny, decay %.0f: err_R %.3e err_E %.3e err_X %.3e" % (decay, eR, eE, eX))
+    assert eR <= SPLIT_TOL_RX and eE <= SPLIT_TOL_E and eX <= SPLIT_TOL_RX
+
+
 @pytest.mark.parametrize("o,v,n,seed", [(1, 2, 1, 160), (2, 3, 2, 161)])
 def test_autograd_gradcheck(dev, o, v, n, seed):
     """torch.autograd.gradcheck on the FP64 path: central differences of E in every entry of
