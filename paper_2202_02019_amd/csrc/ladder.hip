@@ -749,9 +749,8 @@ dim3 pm_grid(int64_t v, int64_t rows) {
 // Packs amplitudes x[o][o][v][v] to xp[P(i,j)][P(c,d)] and xm[Q(i,j)][Q(c,d)].
 void pm_pack_amp(const double* x, int64_t o, int64_t v, double* xp, double* xm, hipStream_t st) {
     const PmRows rw{0, o, 0, 0};
-    hipLaunchKernelGGL(pm_pack_sym_tiled_kernel, pm_grid(v, pm_P2(o)), dim3(256), 0, st, x, v, rw, pm_P2(o), 1, xp);
-    if (pm_Q2(o) > 0 && pm_Q2(v) > 0)
-        hipLaunchKernelGGL(pm_pack_sym_tiled_kernel, pm_grid(v, pm_Q2(o)), dim3(256), 0, st, x, v, rw, pm_Q2(o), 0, xm);
+    hipLaunchKernelGGL(pm_pack_pair_tiled_kernel, pm_grid(v, pm_P2(o)), dim3(256), 0, st, x, v, rw, pm_P2(o), xp,
+                       pm_Q2(o) > 0 && pm_Q2(v) > 0 ? xm : nullptr);
 }
 
 unsigned grid_for(int64_t total) {
@@ -821,9 +820,8 @@ int forward_pm(int64_t o, int64_t v, int64_t n, const double* L, const double* t
             const int64_t cnt = pm_g_count(v, a0, nA);
             StageTimer tm_(LADDER_STAGE_PACK, 0.0, 24.0 * (double)cnt, st);
             const PmRows rw{1, 0, a0, nA};
-            hipLaunchKernelGGL(pm_pack_sym_tiled_kernel, pm_grid(v, NPb), dim3(256), 0, st, g, v, rw, NPb, 1, gp);
-            if (NMb > 0 && p.Q2v > 0)
-                hipLaunchKernelGGL(pm_pack_sym_tiled_kernel, pm_grid(v, NMb), dim3(256), 0, st, g, v, rw, NMb, 0, gm);
+            hipLaunchKernelGGL(pm_pack_pair_tiled_kernel, pm_grid(v, NPb), dim3(256), 0, st, g, v, rw, NPb, gp,
+                               NMb > 0 && p.Q2v > 0 ? gm : nullptr);
             if ((rc = hip_check(hipGetLastError(), "pack launch"))) return rc;
         }
         const bool minus_b = minus && NMb > 0;
@@ -883,9 +881,8 @@ int adjoint_pm(int64_t o, int64_t v, int64_t n, const double* L, const double* t
         StageTimer tm_(LADDER_STAGE_PACK, 0.0, 16.0 * (double)(2 * pm_amp_count(o, v)), st);
         pm_pack_amp(tau, o, v, tp, tm, st);
         const PmRows rw{2, o, 0, 0};
-        hipLaunchKernelGGL(pm_pack_sym_tiled_kernel, pm_grid(v, p.P2o), dim3(256), 0, st, wt, v, rw, p.P2o, 1, wp);
-        if (p.Q2o > 0 && p.Q2v > 0)
-            hipLaunchKernelGGL(pm_pack_sym_tiled_kernel, pm_grid(v, p.Q2o), dim3(256), 0, st, wt, v, rw, p.Q2o, 0, wm);
+        hipLaunchKernelGGL(pm_pack_pair_tiled_kernel, pm_grid(v, p.P2o), dim3(256), 0, st, wt, v, rw, p.P2o, wp,
+                           p.Q2o > 0 && p.Q2v > 0 ? wm : nullptr);
         if ((rc = hip_check(hipGetLastError(), "pack launch"))) return rc;
     }
     {   // X = beta X (not read when beta = 0); every product below adds to it

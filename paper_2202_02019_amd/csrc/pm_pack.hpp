@@ -322,23 +322,41 @@ struct PmNoBarrier {
     __host__ __device__ void operator()() const {}
 };
 
-// Packed row r of a symmetric / antisymmetric pack, tile pair tpair.
+// The antisymmetric row that shares plus row r's source matrix, or -1 when the
+// source pair is diagonal (i = j, or b = a for g) and has no antisymmetric part.
+__host__ __device__ inline int64_t pm_minus_row(const PmRows& rw, int64_t v, int64_t r) {
+    if (rw.mode != 1) {
+        int64_t i, j;
+        pm_unP(r, i, j);
+        return i < j ? pm_Q(i, j) : -1;
+    }
+    const int64_t K = v - rw.a0, src = pm_src_row(rw, v, r, true);  // ap K + (b - a0)
+    const int64_t ap = src / K, b = rw.a0 + src % K, a = rw.a0 + ap;
+    return b > a ? pm_gm_off(ap, v, rw.a0) + (b - a - 1) : -1;
+}
+
+// Plus row r and its minus row (when there is one and outm is not NULL) from one
+// staging of tile pair tpair of their common source matrix.
 template <class Sync>
-__host__ __device__ inline void pm_pack_sym_block(const double* src, int64_t v, const PmRows& rw, int64_t r, int64_t tpair,
-                                                  bool plus, double* out, PmTile& A, PmTile& B, int tid, int nth, Sync sync) {
+__host__ __device__ inline void pm_pack_pair_block(const double* src, int64_t v, const PmRows& rw, int64_t r, int64_t tpair,
+                                                   double* outp, double* outm, PmTile& A, PmTile& B, int tid, int nth,
+                                                   Sync sync) {
     int64_t cb, db;
     pm_unP(tpair, cb, db);
     const int64_t c0 = cb * PM_T, d0 = db * PM_T;
-    pm_stage_pair(src + pm_src_row(rw, v, r, plus) * v * v, v, c0, d0, A, B, tid, nth);
+    pm_stage_pair(src + pm_src_row(rw, v, r, true) * v * v, v, c0, d0, A, B, tid, nth);
     sync();
-    double off = rw.mode == 0 ? 0.5 : 1.0, dg = 1.0;
+    const double moff = rw.mode == 0 ? 0.5 : 1.0;
+    double off = moff, dg = 1.0;
     if (rw.mode == 2) {
-        int64_t i = 0, j = 0;
-        if (plus) pm_unP(r, i, j);
-        off = (plus && i == j) ? 0.5 : 1.0;
+        int64_t i, j;
+        pm_unP(r, i, j);
+        off = i == j ? 0.5 : 1.0;
         dg = 2.0 * off;
     }
-    pm_pack_sym_tile(A, B, v, c0, d0, plus, off, dg, out + r * (plus ? pm_P2(v) : pm_Q2(v)), tid, nth);
+    pm_pack_sym_tile(A, B, v, c0, d0, true, off, dg, outp + r * pm_P2(v), tid, nth);
+    const int64_t rm = outm ? pm_minus_row(rw, v, r) : -1;
+    if (rm >= 0) pm_pack_sym_tile(A, B, v, c0, d0, false, moff, 1.0, outm + rm * pm_Q2(v), tid, nth);
 }
 
 // Tiles (alpha) and (beta) of a batch [b0, b0+nB): block row `row` = (b - b0)(b0 + nB) + a
@@ -404,12 +422,14 @@ __host__ __device__ inline void pm_tile_ab_block(const double* dp, const double*
 // row test is uniform per block, so every thread of a working block reaches the barrier.
 __device__ inline int64_t pm_block_row() { return (int64_t)blockIdx.y + (int64_t)blockIdx.z * gridDim.y; }
 
-__global__ __launch_bounds__(256) void pm_pack_sym_tiled_kernel(const double* __restrict__ src, int64_t v, PmRows rw,
-                                                                 int64_t nrows, int plus, double* __restrict__ out) {
+// Grid: pm_grid(v, plus rows); outm NULL packs the plus rows only.
+__global__ __launch_bounds__(256) void pm_pack_pair_tiled_kernel(const double* __restrict__ src, int64_t v, PmRows rw,
+                                                                 int64_t nrows, double* __restrict__ outp,
+                                                                 double* __restrict__ outm) {
     __shared__ PmTile A, B;
     const int64_t r = pm_block_row();
     if (r >= nrows) return;
-    pm_pack_sym_block(src, v, rw, r, blockIdx.x, plus != 0, out, A, B, threadIdx.x, blockDim.x, PmBarrier{});
+    pm_pack_pair_block(src, v, rw, r, blockIdx.x, outp, outm, A, B, threadIdx.x, blockDim.x, PmBarrier{});
 }
 
 __global__ __launch_bounds__(256) void pm_tile_ab_kernel(const double* __restrict__ dp, const double* __restrict__ dm,

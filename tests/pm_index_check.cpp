@@ -72,10 +72,7 @@ int check(int64_t o, int64_t v, int64_t n, int64_t nA, unsigned long long seed) 
         std::vector<double> tp2(tp.size(), NAN), tm2(tm.size(), NAN);
         const PmRows rw{0, o, 0, 0};
         run_tiled(v, pm_P2(o), [&](int64_t r, int64_t t, PmTile& A, PmTile& B) {
-            pm_pack_sym_block(tau.data(), v, rw, r, t, true, tp2.data(), A, B, 0, 1, PmNoBarrier{});
-        });
-        run_tiled(v, pm_Q2(o), [&](int64_t r, int64_t t, PmTile& A, PmTile& B) {
-            pm_pack_sym_block(tau.data(), v, rw, r, t, false, tm2.data(), A, B, 0, 1, PmNoBarrier{});
+            pm_pack_pair_block(tau.data(), v, rw, r, t, tp2.data(), tm2.data(), A, B, 0, 1, PmNoBarrier{});
         });
         bad |= same(tp2, tp, pm_P2(o) * pm_P2(v), "tau+") | same(tm2, tm, pm_Q2(o) * pm_Q2(v), "tau-");
     }
@@ -95,12 +92,9 @@ int check(int64_t o, int64_t v, int64_t n, int64_t nA, unsigned long long seed) 
             std::vector<double> gp2(gp.size(), NAN), gm2(gm.size(), NAN);
             const PmRows rw{1, 0, a0, nb};
             run_tiled(v, NP, [&](int64_t r, int64_t t, PmTile& A, PmTile& B) {
-                pm_pack_sym_block(gt.data(), v, rw, r, t, true, gp2.data(), A, B, 0, 1, PmNoBarrier{});
+                pm_pack_pair_block(gt.data(), v, rw, r, t, gp2.data(), pm_Q2(v) > 0 ? gm2.data() : nullptr, A, B, 0, 1,
+                                   PmNoBarrier{});
             });
-            if (pm_Q2(v) > 0)
-                run_tiled(v, NM, [&](int64_t r, int64_t t, PmTile& A, PmTile& B) {
-                    pm_pack_sym_block(gt.data(), v, rw, r, t, false, gm2.data(), A, B, 0, 1, PmNoBarrier{});
-                });
             bad |= same(gp2, gp, NP * pm_P2(v), "g+") | same(gm2, gm, NM * pm_Q2(v), "g-");
         }
         std::vector<double> rp(pm_P2(o) * NP), rm(pm_Q2(o) * NM + 1);
@@ -134,10 +128,7 @@ int check(int64_t o, int64_t v, int64_t n, int64_t nA, unsigned long long seed) 
         std::vector<double> wpp(pm_P2(o) * pm_P2(v), NAN), wmm(pm_Q2(o) * pm_Q2(v) + 1, NAN);
         const PmRows rw{2, o, 0, 0};
         run_tiled(v, pm_P2(o), [&](int64_t r, int64_t t, PmTile& A, PmTile& B) {
-            pm_pack_sym_block(tb.data(), v, rw, r, t, true, wpp.data(), A, B, 0, 1, PmNoBarrier{});
-        });
-        run_tiled(v, pm_Q2(o), [&](int64_t r, int64_t t, PmTile& A, PmTile& B) {
-            pm_pack_sym_block(tb.data(), v, rw, r, t, false, wmm.data(), A, B, 0, 1, PmNoBarrier{});
+            pm_pack_pair_block(tb.data(), v, rw, r, t, wpp.data(), wmm.data(), A, B, 0, 1, PmNoBarrier{});
         });
         for (int64_t p = 0; p < pm_P2(o); ++p)  // Wp[P(i,j)][P(a,b)] = wp[P(i,j)][(a,b)]
             for (int64_t b = 0; b < v; ++b)
