@@ -47,8 +47,11 @@ WORKLOADS = {
     "thymine": (33, 228, 967, 6),
     "azobenzene": (48, 364, 1444, 7),
 }
-PEAK = {"fp64": 78.6, "bf16": 2516.6}  # dense MFMA TFLOP/s, MI355X
-DEFAULT_SLICES = (5, 4)  # (forward, adjoint) slice counts the committed traffic counters are taken at
+PEAK = {"fp64": 78.6, "bf16": 2516.6, "int8": 5033.2}  # dense MFMA TFLOP/s (TOP/s for INT8), MI355X
+# (forward, adjoint) slice counts per split format: the benchmark's defaults, and the counts the
+# committed traffic counters of that format are taken at
+DEFAULT_SLICES = {"int8": (6, 5), "bf16": (5, 4)}
+PREC_CODE = {"fp64": 0, "bf16": 1, "int8": 2}
 
 
 TUNED_CACHE = os.path.join(ROOT, "paper_2202_02019_amd", "tuned_mi355x.jsonl")
@@ -70,7 +73,7 @@ def tuned_batch(path, o, v, n, precision, slices, flags, slices_adj=None):
                 continue
             key = (d.get("o"), d.get("v"), d.get("n"), d.get("precision"), d.get("n_slices"),
                    d.get("n_slices_adjoint", d.get("n_slices")), d.get("flags"))
-            if key == (o, v, n, precision, slices if precision == 1 else 0, slices_adj if precision == 1 else 0, flags):
+            if key == (o, v, n, precision, slices if precision else 0, slices_adj if precision else 0, flags):
                 found = d.get("n_abatch")
     return found
 
@@ -88,14 +91,16 @@ def gemm_source_hash():
 
 
 def mfma_ceiling(seconds=0.2):
-    """Rate of the register-only MFMA probe (ladder_mfma_probe) for BF16 and FP64, in TFLOP/s:
-    what the matrix cores sustain on this chip under its clock and power limits."""
+    """Rate of the register-only MFMA probe (ladder_mfma_probe) for BF16, INT8 and FP64, in
+    TFLOP/s (TOP/s for INT8): what the matrix cores sustain on this chip under its clock and
+    power limits."""
     import torch
 
     import paper_2202_02019_amd as P
     out = {}
     blocks = 8 * torch.cuda.get_device_properties(0).multi_processor_count
-    for name, kind, rate in (("bf16", P.PROBE_BF16, 2.0e15), ("fp64", P.PROBE_FP64, 7.0e13)):
+    for name, kind, rate in (("bf16", P.PROBE_BF16, 2.0e15), ("int8", P.PROBE_INT8, 4.0e15),
+                             ("fp64", P.PROBE_FP64, 7.0e13)):
         _, per_iter = P.mfma_probe(kind, 1, blocks)
         iters = max(1, int(seconds * rate / per_iter))
         buf, _ = P.mfma_probe(kind, iters, blocks)          # warm-up at full length
@@ -147,11 +152,13 @@ def main():
     ap.add_argument("--warmup", type=int, default=None)
     ap.add_argument("--workload", default="retinal", choices=sorted(WORKLOADS))
     ap.add_argument("--shape", default=None, help="o,v,n override (probe shapes)")
-    ap.add_argument("--precision", default="split", choices=["fp64", "split"])
-    ap.add_argument("--slices", type=int, default=0, help="BF16 slices of the forward GEMMs (0 = the library default)")
+    ap.add_argument("--precision", default="int8", choices=["int8", "bf16", "fp64"],
+                    help="split slices in INT8 (the default) or BF16, or the FP64 MFMA path")
+    ap.add_argument("--slices", type=int, default=0,
+                    help="slices of the forward GEMMs (0 = the format's benchmark default: 6 INT8, 5 BF16)")
     ap.add_argument("--slices-adjoint", type=int, default=None,
-                    help="BF16 slices of the adjoint GEMMs (default: 4 with the default forward count, else the "
-                         "forward's; 4 keeps X within 1e-8 with margin, 5 are needed only for the energy)")
+                    help="slices of the adjoint GEMMs (default: 5 INT8 / 4 BF16 with the default forward count, "
+                         "else the forward's; they keep X within 1e-8 with margin, the energy needs the forward's)")
     ap.add_argument("--n-abatch", type=int, default=0)
     ap.add_argument("--cpu-rows", type=int, default=1, help="a (and p) rows the CPU baseline computes; 0 = skip")
     ap.add_argument("--no-compare", action="store_true",
@@ -203,11 +210,16 @@ def main():
     if args.shape:
         o, v, n = (int(x) for x in args.shape.split(","))
         name = "probe"
-    prec_code = 0 if args.precision == "fp64" else 1
-    # the library's rule: n_slices 0 means 5, n_slices_adjoint 0 means n_slices
-    S_fwd = args.slices or 5
+    prec_code = PREC_CODE[args.precision]
+    split = args.precision != "fp64"
+    # the benchmark's slice counts per format unless given; the library's rule then applies
+    # (n_slices 0 means 5, n_slices_adjoint 0 means n_slices)
+    dfw, dadj = DEFAULT_SLICES.get(args.precision, (5, 4))
+    if not args.slices:
+        args.slices = dfw
+    S_fwd = args.slices
     if args.slices_adjoint is None:
-        args.slices_adjoint = 4 if S_fwd == 5 else 0
+        args.slices_adjoint = dadj if S_fwd == dfw else 0
     S_adj = args.slices_adjoint or S_fwd
     flags = 2 if args.dense else 0
     nA_source = "explicit" if args.n_abatch else "library default"
@@ -217,7 +229,7 @@ def main():
         if tuned:
             nA_source = "autotune cache " + os.path.relpath(args.tuned, ROOT)
     if args.n_abatch == 0 and tuned is None and not args.autotune and name == "retinal":
-        args.n_abatch = 8 if args.precision == "split" else 16  # a few large virtual batches fit in 288 GB
+        args.n_abatch = 8 if args.precision == "bf16" else 16  # a few large virtual batches fit in 288 GB
         nA_source = "fixed fallback"
     big = nominal_flops(o, v, n) > 1e14
     # a step at retinal scale takes about half a minute: one untimed warm-up step (code objects,
@@ -250,9 +262,9 @@ def main():
     R = torch.empty_like(tau)
     X = torch.empty_like(L)
     E = torch.empty((), dtype=torch.float64, device=dev)
-    prec = P.FP64 if args.precision == "fp64" else P.SPLIT_BF16
-    opts = P.Options(precision=prec, n_slices=args.slices, n_abatch=args.n_abatch,
-                     flags=P.FLAG_DENSE if args.dense else 0, n_slices_adjoint=args.slices_adjoint)
+    prec = {"fp64": P.FP64, "bf16": P.SPLIT_BF16, "int8": P.SPLIT_INT8}[args.precision]
+    opts = P.Options(precision=prec, n_slices=args.slices if split else 0, n_abatch=args.n_abatch,
+                     flags=P.FLAG_DENSE if args.dense else 0, n_slices_adjoint=args.slices_adjoint if split else 0)
     tune_s = None
     if tuned:
         P.autotune_load(args.tuned)
@@ -298,7 +310,7 @@ def main():
     skipped = {}
 
     compare = None
-    if args.precision == "split" and not args.no_compare:
+    if split and not args.no_compare:
         # the same step on the FP64 MFMA path (untimed for `value`) on the same device arrays; it takes
         # about 1.5 split steps at the retinal shape, so it runs only if that and one timed step fit
         if left() < 2.0 * t_step + t_step + 20.0:
@@ -420,25 +432,27 @@ def main():
     # FP64-equivalent rate of the dominant stage: 2 M N K flops per launch over its mean launch time
     fp64_equiv = dom["flops"] / dom["launches"] / (dom["avg_ms"] * 1e-3) / 1e12
     nA_eff = args.n_abatch or tuned
-    default_shape = (S_fwd, S_adj) == DEFAULT_SLICES and not args.dense
+    default_shape = split and (S_fwd, S_adj) == DEFAULT_SLICES[args.precision] and not args.dense
     traffic = measured_traffic(name, args.precision, dom_name, nA_eff) if default_shape else None
-    if args.precision == "split":
-        # the split method's unit of work: S(S+1)/2 BF16 slice products per FP64-equivalent MAC
+    if split:
+        # the split method's unit of work: S(S+1)/2 slice products (BF16 or INT8 MFMA) per
+        # FP64-equivalent MAC, each product 2 M N K operations
         S = S_adj if dom_name in ("gemm_e", "gemm_f") else S_fwd
         prods = S * (S + 1) // 2
-        achieved, peak = fp64_equiv * prods, PEAK["bf16"]
+        achieved, peak = fp64_equiv * prods, PEAK[args.precision]
     else:
         prods, achieved, peak = 1, fp64_equiv, PEAK["fp64"]
     roofline = {"bound": "mfma", "kernel": dom_name, "achieved": achieved, "peak": peak,
-                "unit": "TFLOP/s", "frac": achieved / peak, "traffic": traffic,
+                "unit": "TOP/s" if args.precision == "int8" else "TFLOP/s", "frac": achieved / peak,
+                "traffic": traffic,
                 "traffic_unit": "bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-kernel scaled)",
                 "algorithmic_bytes": dom["bytes"] / dom["launches"],
                 "avg_launch_ms": dom["avg_ms"], "launches_per_step": dom["launches"] / steps,
-                "slice_products": prods if args.precision == "split" else None,
+                "slice_products": prods if split else None,
                 "fp64_equivalent_tflops": fp64_equiv,
                 "fp64_equivalent_frac_of_fp64_peak": fp64_equiv / PEAK["fp64"]}
     ceiling = mfma_ceiling()
-    roofline["measured_mfma_ceiling"] = ceiling["bf16_tflops" if args.precision == "split" else "fp64_tflops"]
+    roofline["measured_mfma_ceiling"] = ceiling[("fp64" if not split else args.precision) + "_tflops"]
     roofline["frac_of_measured_ceiling"] = achieved / roofline["measured_mfma_ceiling"]
     stage_summary = {k: {"ms_per_step": s_["total_ms"] / steps, "launches_per_step": s_["launches"] / steps,
                          "tflops": (s_["flops"] / (s_["total_ms"] * 1e-3) / 1e12) if s_["total_ms"] > 0 else None}
@@ -554,7 +568,7 @@ def main():
               + 16.0 * o * o * v * v * n)
         s_ab, s_ic = float((L * Wab).sum()), float((Zov * Wic).sum())
         nxt["ov3_abic"] = {"ms": msi, "flops": Fi, "tflops": Fi / (msi * 1e-3) / 1e12,
-                           "precision": "split" if prec == P.SPLIT_BF16 else "fp64",
+                           "precision": args.precision,
                            "identity_rel": abs(s_ab - s_ic) / float((L * Wab).abs().sum())}
         del Wab, Wic, Zov, ws
         torch.cuda.empty_cache()
@@ -566,11 +580,11 @@ def main():
         "value": value, "unit": "TFLOP/s", "n_gpus": 1, "steps": steps, "warmup": warm_done,
         "steps_requested": steps_req, "warmup_requested": warmup_req,
         "ms_per_step": ms, "s_per_iter": ms / 1e3, "higher_is_better": True, "scaling": "weak",
-        "vs_baseline": None, "dtype": "f64" if args.precision == "fp64" else "bf16-split/f64",
+        "vs_baseline": None, "dtype": "f64" if not split else args.precision + "-split/f64",
         "data": "synthetic",
         "config": {"workload": name, "o": o, "v": v, "n_chol": n, "seed": seed, "precision": args.precision,
-                   "n_slices": S_fwd if args.precision == "split" else 0,
-                   "n_slices_adjoint": S_adj if args.precision == "split" else 0, "n_abatch": nA_eff or 0,
+                   "n_slices": S_fwd if split else 0,
+                   "n_slices_adjoint": S_adj if split else 0, "n_abatch": nA_eff or 0,
                    "n_abatch_source": nA_source, "nominal_flops": F,
                    "path": "dense" if args.dense else "+/- packed",
                    "decay": args.decay},
@@ -612,9 +626,11 @@ def run_autograd(args):
     tau = P.mp2_amplitudes(Lov, SG.draw_eps(seed, o, v), o=o, v=v, n=n)
     del Lov
     tbar = SG.add_noise(seed, o, v, tau)
-    S_fwd = args.slices or 5
-    S_adj = args.slices_adjoint if args.slices_adjoint is not None else (4 if S_fwd == 5 else 0)
-    opts = P.Options(precision=P.SPLIT_BF16, n_slices=args.slices, n_slices_adjoint=S_adj)
+    fmt = "bf16" if args.precision == "bf16" else "int8"  # the workload is a split one
+    dfw, dadj = DEFAULT_SLICES[fmt]
+    S_fwd = args.slices or dfw
+    S_adj = args.slices_adjoint if args.slices_adjoint is not None else (dadj if S_fwd == dfw else 0)
+    opts = P.Options(precision=P.SPLIT_BF16 if fmt == "bf16" else P.SPLIT_INT8, n_slices=S_fwd, n_slices_adjoint=S_adj)
     Lq = L.clone().requires_grad_(True)
     tq = tau.clone().requires_grad_(True)
     steps = args.steps or 3
@@ -677,8 +693,8 @@ def run_autograd(args):
         "metric": "ladder fwd+adjoint TFLOP/s & s/iter, split-BF16 vs FP64 at <=1e-10 rel err in E",
         "value": executed / (ms * 1e-3) / 1e12, "unit": "TFLOP/s", "n_gpus": 1, "steps": steps, "warmup": warmup,
         "ms_per_step": ms, "s_per_iter": ms / 1e3, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
-        "dtype": "bf16-split/f64", "data": "synthetic",
-        "config": {"workload": "autograd", "o": o, "v": v, "n_chol": n, "seed": seed, "precision": "split",
+        "dtype": fmt + "-split/f64", "data": "synthetic",
+        "config": {"workload": "autograd", "o": o, "v": v, "n_chol": n, "seed": seed, "precision": fmt,
                    "n_slices": S_fwd, "n_slices_adjoint": S_adj or S_fwd,
                    "step": "LadderEnergy forward (split R, E) + backward (adjoint dE/dL, transposed ladder dE/dtau)"},
         "executed_gemm_flops": executed,
@@ -706,8 +722,11 @@ def run_batched(args):
     sizes = synthetic.batched_sizes(8, 64, (4, 12), (20, 80)) if small else synthetic.batched_sizes(4, 64)
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
-    prec = P.FP64 if args.precision == "fp64" else P.SPLIT_BF16
-    opts = P.Options(precision=prec, n_slices=args.slices, n_abatch=args.n_abatch,
+    prec = {"fp64": P.FP64, "bf16": P.SPLIT_BF16, "int8": P.SPLIT_INT8}[args.precision]
+    dfw, dadj = DEFAULT_SLICES.get(args.precision, (0, 0))
+    S_fwd = args.slices or dfw
+    S_adj = args.slices_adjoint if args.slices_adjoint is not None else (dadj if S_fwd == dfw else 0)
+    opts = P.Options(precision=prec, n_slices=S_fwd, n_abatch=args.n_abatch, n_slices_adjoint=S_adj,
                      flags=P.FLAG_DENSE if args.dense else 0)
     insts = []
     t0 = time.time()
@@ -775,7 +794,7 @@ def run_batched(args):
         "metric": "ladder fwd+adjoint TFLOP/s & s/iter, split-BF16 vs FP64 at <=1e-10 rel err in E",
         "value": F / (ms * 1e-3) / 1e12, "unit": "TFLOP/s", "n_gpus": 1, "steps": steps, "warmup": warmup,
         "ms_per_step": ms, "s_per_iter": ms / 1e3, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
-        "dtype": "f64" if args.precision == "fp64" else "bf16-split/f64", "data": "synthetic",
+        "dtype": "f64" if args.precision == "fp64" else args.precision + "-split/f64", "data": "synthetic",
         "config": {"workload": args.workload, "instances": 64, "sizes_seed": 8 if small else 4,
                    "o_range": [4, 12] if small else [8, 40], "v_range": [20, 80] if small else [60, 300],
                    "data_seeds": "1000+m",

@@ -69,14 +69,16 @@ extern "C" {
 /* Arithmetic of the four contraction stages. */
 #define LADDER_FP64 0       /* FP64 MFMA (v_mfma_f64_16x16x4_f64) throughout */
 #define LADDER_SPLIT_BF16 1 /* exponent-aligned BF16 slices on BF16 MFMA, exact FP32 chunk sums, FP64 combine */
+#define LADDER_SPLIT_INT8 2 /* exponent-aligned INT8 slices (7 bits each) on INT8 MFMA, exact INT32 level sums,
+                               FP64 combine */
 
 /* Option flags. */
 #define LADDER_FLAG_GENERAL 1u /* adjoint: do not assume pair symmetry of tau and tbar (implies DENSE) */
 #define LADDER_FLAG_DENSE 2u   /* contract all (i,j), (a,b), (c,d): skip the +/- packing */
 
 typedef struct {
-    int32_t precision;        /* LADDER_FP64 or LADDER_SPLIT_BF16 */
-    int32_t n_slices;         /* split mode: BF16 slices per operand of the forward's GEMMs (the g tile and
+    int32_t precision;        /* LADDER_FP64, LADDER_SPLIT_BF16 or LADDER_SPLIT_INT8 */
+    int32_t n_slices;         /* split modes: slices per operand of the forward's GEMMs (the g tile and
                                  the R update) and of every other split product; 0 = the default, 5;
                                  otherwise 2..6 */
     int64_t n_abatch;         /* virtual indices a per batch, 0 = automatic */
@@ -283,8 +285,8 @@ int ladder_ov3_abci(int64_t o, int64_t v, int64_t n, const double* L2, const dou
  * Zvv, Wab [v][v][n]; Zov, Wic [o][v][n] (Zov[(i*v+c)*n+K] = Z^K_ic).  Either output
  * may be NULL to skip that side (Wab needs Zov, Wic needs Zvv).  With beta == 0 the
  * outputs are not read.  opts (may be NULL: FP64) selects the precision of the three
- * o^3 v^3 products V+Y, Yt and S: LADDER_FP64 or LADDER_SPLIT_BF16 with n_slices
- * slices (the split GEMM of the ladder, FP64 combine); everything else is FP64;
+ * o^3 v^3 products V+Y, Yt and S: LADDER_FP64, or LADDER_SPLIT_BF16 / LADDER_SPLIT_INT8
+ * with n_slices slices (the split GEMM of the ladder, FP64 combine); everything else is FP64;
  * n_abatch and flags are ignored.  Workspace: ladder_ov3_abic_workspace_size bytes
  * for the same opts, 256-byte aligned (three o^2 v^2 buffers, o^3 v, 8 v^3, v^2 n and
  * a few [o][v][n] arrays; split adds the slices of two o v x o v operands).
@@ -362,6 +364,9 @@ int ladder_batched(int count, const ladder_instance* inst, uint32_t what, void* 
  * chunk sums folded into FP64, so integer inputs that n_slices slices carry
  * exactly give the exact product as long as every chunk sum fits FP32's 24
  * bits (the representation used by every split stage of the ladder).
+ * LADDER_SPLIT_INT8 does the same with 7-bit integer slices on
+ * v_mfma_i32_32x32x32_i8, one exact INT32 sum per slice level p + q and chunk
+ * (no chunk-sum limit), folded into FP64.
  * ladder_gemm_workspace_size gives the bytes (0 for FP64); ws must then be
  * 256-byte aligned.  With beta == 0, C is not read.  C must not overlap A, B or
  * ws, and A and B must not overlap ws.  n_abatch and flags are ignored.
@@ -377,13 +382,15 @@ int ladder_gemm(int64_t M, int64_t N, int64_t K, double alpha, const double* A, 
  * waves each issue `iters` rounds of four independent MFMAs on register operands
  * and write one checksum per thread to out[blocks * 256] (device, caller-owned).
  * LADDER_PROBE_BF16 runs v_mfma_f32_32x32x16_bf16 (the split GEMM's instruction),
- * LADDER_PROBE_FP64 v_mfma_f64_16x16x4_f64 (the FP64 GEMM's).  *flops (host, may be
- * NULL) receives the flops of the launch; timing it gives the rate the chip sustains
+ * LADDER_PROBE_FP64 v_mfma_f64_16x16x4_f64 (the FP64 GEMM's), LADDER_PROBE_INT8
+ * v_mfma_i32_32x32x32_i8 (the INT8 split GEMM's).  *flops (host, may be NULL) receives
+ * the flops (integer operations for INT8) of the launch; timing it gives the rate the chip sustains
  * under its clock and power limits, beside the published peaks.  Asynchronous on
  * `stream`.  iters in [1, 2^32], blocks in [1, 2^20].
  */
 #define LADDER_PROBE_BF16 0
 #define LADDER_PROBE_FP64 1
+#define LADDER_PROBE_INT8 2
 int ladder_mfma_probe(int kind, int64_t iters, int64_t blocks, double* out, double* flops, void* stream);
 
 /*

@@ -37,6 +37,7 @@
 #include "../../include/ladder.h"
 #include "gemm_f64.hpp"
 #include "split_bf16.hpp"
+#include "split_i8.hpp"
 #include "pm_pack.hpp"
 
 using namespace ladder;
@@ -133,10 +134,10 @@ bool overlap(const void* a, int64_t abytes, const void* b, int64_t bbytes) {
 int get_opts(const ladder_options* in, ladder_options& o) {
     ladder_default_options(&o);
     if (in) o = *in;
-    if (o.precision != LADDER_FP64 && o.precision != LADDER_SPLIT_BF16)
+    if (o.precision != LADDER_FP64 && o.precision != LADDER_SPLIT_BF16 && o.precision != LADDER_SPLIT_INT8)
         return fail(LADDER_EUNSUPPORTED, "unknown precision %d", (int)o.precision);
     if (o.n_slices_adjoint < 0) return fail(LADDER_EINVAL, "n_slices_adjoint must be >= 0");
-    if (o.precision == LADDER_SPLIT_BF16) {
+    if (o.precision != LADDER_FP64) {
         if (o.n_slices == 0) o.n_slices = DEFAULT_SLICES;
         if (o.n_slices < 2 || o.n_slices > SPLIT_MAX_S)
             return fail(LADDER_EUNSUPPORTED, "n_slices must be 0 (default %d) or in [2, %d], got %d", DEFAULT_SLICES,
@@ -170,18 +171,39 @@ struct Arena {
     }
 };
 
+// A slice specification: the slice count S, with SPLIT_I8 added for INT8 slices
+// (split_i8.hpp) instead of BF16 ones (split_bf16.hpp); 0 means FP64.
+constexpr int SPLIT_I8 = 16;
+int slice_count(int spec) { return spec & (SPLIT_I8 - 1); }
+bool slice_is_i8(int spec) { return (spec & SPLIT_I8) != 0; }
+int slice_spec(const ladder_options& op, int n) {
+    return op.precision == LADDER_FP64 ? 0 : n | (op.precision == LADDER_SPLIT_INT8 ? SPLIT_I8 : 0);
+}
+// Bytes of one sliced element (all slices).
+int slice_elem_bytes(int spec) { return slice_count(spec) * (slice_is_i8(spec) ? 1 : 2); }
+
+// Output tiles of a GEMM launch (one workgroup each) for a slice spec.
+int64_t split_tiles(int spec, int64_t M, int64_t N) {
+    return slice_is_i8(spec) ? ((M + SPLIT8_BM - 1) / SPLIT8_BM) * ((N + SPLIT8_BN - 1) / SPLIT8_BN) : tiles(M, N);
+}
+
 // One sliced operand: S slices of R rows x Kp, and nch x R exponents.
 struct SlicedBuf {
     size_t s_off = 0, e_off = 0;
     int64_t R = 0, K = 0;
+    bool i8 = false;
 };
-size_t slice_bytes(int S, int64_t R, int64_t K) { return (size_t)S * (size_t)split_slice_stride(R, K) * 2; }
+size_t slice_bytes(int spec, int64_t R, int64_t K) {
+    return slice_is_i8(spec) ? (size_t)slice_count(spec) * (size_t)split8_slice_stride(R, K)
+                             : (size_t)slice_count(spec) * (size_t)split_slice_stride(R, K) * 2;
+}
 size_t exp_bytes(int64_t R, int64_t K) { return (size_t)split_nchunk(K) * (size_t)R * 4; }
-SlicedBuf take_sliced(Arena& a, int S, int64_t R, int64_t K) {
+SlicedBuf take_sliced(Arena& a, int spec, int64_t R, int64_t K) {
     SlicedBuf b;
     b.R = R;
     b.K = K;
-    b.s_off = a.take(slice_bytes(S, R, K));
+    b.i8 = slice_is_i8(spec);
+    b.s_off = a.take(slice_bytes(spec, R, K));
     b.e_off = a.take(exp_bytes(R, K));
     return b;
 }
@@ -218,13 +240,19 @@ struct Plan {
 };
 
 constexpr int64_t KSPLIT_MAX = 4;
+// INT8 plans: K-splits of the long-K GEMMs (each split at least KSPLIT_I8_CHUNKS chunks).
+// The 128 x 64 tiles put twice as many workgroups, and panels, on an XCD as the BF16
+// ones; shorter K ranges keep the workgroups that share panels closer together in K,
+// so more of the re-read panels are still in L2.
+constexpr int64_t KSPLIT_I8_MAX = 16, KSPLIT_I8_CHUNKS = 32;
+int64_t ksplit_cap(int spec) { return slice_is_i8(spec) ? KSPLIT_I8_MAX : KSPLIT_MAX; }
 
 constexpr int PM_UNPACK_GRID = 1024;  // blocks of the R unpack kernel (one energy partial each)
 
 Plan make_plan(int64_t o, int64_t v, int64_t n, const ladder_options& op, const Sizes& s) {
     Plan p;
-    p.S = op.precision == LADDER_SPLIT_BF16 ? op.n_slices : 0;
-    p.Sa = op.precision == LADDER_SPLIT_BF16 ? op.n_slices_adjoint : 0;
+    p.S = slice_spec(op, op.n_slices);
+    p.Sa = slice_spec(op, op.n_slices_adjoint);
     const int Smax = std::max(p.S, p.Sa);
     const bool packed = !(op.flags & (LADDER_FLAG_GENERAL | LADDER_FLAG_DENSE));
     int64_t nA = op.n_abatch;
@@ -249,6 +277,7 @@ Plan make_plan(int64_t o, int64_t v, int64_t n, const ladder_options& op, const 
         // packed path's tile (alpha)), or rows v^2 along K = n_A v (tile (beta)); room for either
         p.tile_sl.R = nA * v;
         p.tile_sl.K = s.vv;
+        p.tile_sl.i8 = slice_is_i8(Smax);
         p.tile_sl.s_off = a.take(std::max(slice_bytes(Smax, nA * v, s.vv), slice_bytes(Smax, s.vv, nA * v)));
         p.tile_sl.e_off = a.take(std::max(exp_bytes(nA * v, s.vv), exp_bytes(s.vv, nA * v)));
     }
@@ -264,7 +293,7 @@ Plan make_plan(int64_t o, int64_t v, int64_t n, const ladder_options& op, const 
 
     Arena f = a;  // forward-only part
     if (!p.pm) {
-        p.part_per_batch = (size_t)tiles(s.oo, nA * v);
+        p.part_per_batch = (size_t)split_tiles(p.S, s.oo, nA * v);
         p.part_off = f.take(p.part_per_batch * (size_t)p.nbatch * 8);
         if (p.S) {
             p.L_J = take_sliced(f, p.S, s.vv, n);
@@ -285,7 +314,7 @@ Plan make_plan(int64_t o, int64_t v, int64_t n, const ladder_options& op, const 
             p.tm_cd = take_sliced(f, p.S, std::max<int64_t>(p.Q2o, 1), std::max<int64_t>(p.Q2v, 1));
             p.gp_sl = take_sliced(f, p.S, p.NP, p.P2v);
             p.gm_sl = take_sliced(f, p.S, std::max<int64_t>(p.NM, 1), std::max<int64_t>(p.Q2v, 1));
-            p.f_skp_elems = KSPLIT_MAX * std::max(p.P2o * p.NP, p.Q2o * p.NM);
+            p.f_skp_elems = ksplit_cap(p.S) * std::max(p.P2o * p.NP, p.Q2o * p.NM);
             p.f_skp = f.take((size_t)p.f_skp_elems * 8);
         }
     }
@@ -320,7 +349,7 @@ Plan make_plan(int64_t o, int64_t v, int64_t n, const ladder_options& op, const 
         }
     }
     if (p.S) {
-        p.a_skp_elems = KSPLIT_MAX * nA * v * n;  // split-K only where ksplit * M * n fits (choose_ksplit)
+        p.a_skp_elems = ksplit_cap(p.Sa) * nA * v * n;  // split-K only where ksplit * M * n fits (choose_ksplit)
         p.a_skp = d.take((size_t)p.a_skp_elems * 8);
     }
     p.adj_total = d.top;
@@ -347,7 +376,7 @@ std::map<TuneKey, int64_t> g_tuned;
 int64_t g_tune_gen = 0;  // bumped on every change: part of the batched graph cache key
 
 TuneKey tune_key(int64_t o, int64_t v, int64_t n, const ladder_options& op) {
-    const bool sp = op.precision == LADDER_SPLIT_BF16;
+    const bool sp = op.precision != LADDER_FP64;
     return TuneKey{o, v, n, op.precision, sp ? op.n_slices : 0, sp ? op.n_slices_adjoint : 0, op.flags};
 }
 
@@ -415,11 +444,16 @@ hipError_t launch_gemm(const double* A, int64_t lda, const double* B, int64_t ld
 // A view of rows [row0, row0 + rows) of a sliced buffer.
 SplitOperand view(char* ws, const SlicedBuf& b, int64_t row0) {
     SplitOperand v;
-    const int64_t Kp = split_kpad(b.K);
     v.s = (const unsigned short*)(ws + b.s_off);
-    v.slice_stride = split_slice_stride(b.R, b.K);
+    v.i8 = b.i8;
+    if (b.i8) {  // byte slices: strides in bytes, 32 k per k-block
+        v.slice_stride = split8_slice_stride(b.R, b.K);
+        v.nkb = split8_kpad(b.K) / 32;
+    } else {
+        v.slice_stride = split_slice_stride(b.R, b.K);
+        v.nkb = split_kpad(b.K) / 16;
+    }
     v.row_off = row0;
-    v.nkb = Kp / 16;
     v.e = (const int*)(ws + b.e_off) + row0;
     v.e_ld = b.R;
     return v;
@@ -427,8 +461,22 @@ SplitOperand view(char* ws, const SlicedBuf& b, int64_t row0) {
 
 template <int S, int STAGE, class Epi>
 hipError_t launch_split_s(const SplitShape& sh, const Epi& epi, hipStream_t st) {
+    if (sh.a.i8 || sh.b.i8) return hipErrorInvalidValue;  // BF16 views only
     hipLaunchKernelGGL((gemm_split_kernel<S, Epi, STAGE>), dim3((unsigned)(tiles(sh.M, sh.N) * sh.ksplit)),
                        dim3(SPLIT_THREADS), 0, st, sh, epi);
+    if (sh.ksplit > 1) {
+        const int64_t blocks = std::min<int64_t>((sh.M * sh.N + 255) / 256, 4096);
+        hipLaunchKernelGGL((splitk_reduce_kernel<Epi>), dim3((unsigned)blocks), dim3(256), 0, st, sh.part, sh.M, sh.N,
+                           sh.ksplit, epi);
+    }
+    return hipGetLastError();
+}
+
+template <int S, int STAGE, class Epi>
+hipError_t launch_i8_s(const SplitShape& sh, const Epi& epi, hipStream_t st) {
+    if (!sh.a.i8 || !sh.b.i8) return hipErrorInvalidValue;  // INT8 views only
+    hipLaunchKernelGGL((gemm_i8_kernel<S, Epi, STAGE>), dim3((unsigned)(split_tiles(SPLIT_I8, sh.M, sh.N) * sh.ksplit)),
+                       dim3(SPLIT8_THREADS), 0, st, sh, epi);
     if (sh.ksplit > 1) {
         const int64_t blocks = std::min<int64_t>((sh.M * sh.N + 255) / 256, 4096);
         hipLaunchKernelGGL((splitk_reduce_kernel<Epi>), dim3((unsigned)blocks), dim3(256), 0, st, sh.part, sh.M, sh.N,
@@ -452,9 +500,16 @@ int64_t device_cus() {
 // Split-K factor for a split GEMM whose epilogue needs no per-tile energy partial:
 // the number of K-splits s (whole 256-chunks each, at most KSPLIT_MAX, s*M*N partial
 // doubles within `room`) that minimises the waves of workgroups per unit of work,
-// ceil(tiles*s / CUs) / s, taken only when it saves at least 4% over s = 1.
-int64_t choose_ksplit(int64_t M, int64_t N, int64_t K, int64_t room) {
-    const int64_t T = tiles(M, N), cus = device_cus(), nch = split_nchunk(K);
+// ceil(tiles*s / CUs) / s, taken only when it saves at least 4% over s = 1.  INT8
+// plans take the largest s up to KSPLIT_I8_MAX with at least KSPLIT_I8_CHUNKS chunks
+// per split that fits `room`.
+int64_t choose_ksplit(int spec, int64_t M, int64_t N, int64_t K, int64_t room) {
+    const int64_t T = split_tiles(spec, M, N), cus = device_cus(), nch = split_nchunk(K);
+    if (slice_is_i8(spec)) {
+        int64_t s = std::min(KSPLIT_I8_MAX, nch / KSPLIT_I8_CHUNKS);
+        while (s > 1 && s * M * N > room) --s;
+        return std::max<int64_t>(s, 1);
+    }
     double best = (double)((T + cus - 1) / cus);
     const double base = best;
     int64_t pick = 1;
@@ -471,6 +526,16 @@ int64_t choose_ksplit(int64_t M, int64_t N, int64_t K, int64_t room) {
 
 template <int STAGE, class Epi>
 hipError_t launch_split(int S, const SplitShape& sh, const Epi& epi, hipStream_t st) {
+    if (slice_is_i8(S)) {
+        switch (slice_count(S)) {
+            case 2: return launch_i8_s<2, STAGE>(sh, epi, st);
+            case 3: return launch_i8_s<3, STAGE>(sh, epi, st);
+            case 4: return launch_i8_s<4, STAGE>(sh, epi, st);
+            case 5: return launch_i8_s<5, STAGE>(sh, epi, st);
+            case 6: return launch_i8_s<6, STAGE>(sh, epi, st);
+            default: return hipErrorInvalidValue;
+        }
+    }
     switch (S) {
         case 2: return launch_split_s<2, STAGE>(sh, epi, st);
         case 3: return launch_split_s<3, STAGE>(sh, epi, st);
@@ -496,13 +561,41 @@ hipError_t slice_s(bool transposed, const double* src, int64_t ld, int64_t R, in
     return hipGetLastError();
 }
 
+template <int S>
+hipError_t slice8_s(bool transposed, const double* src, int64_t ld, int64_t R, int64_t K, int8_t* sl, int* ex,
+                    hipStream_t st) {
+    const int64_t nch = split_nchunk(K);
+    if (!transposed) {
+        const int64_t blocks = ((R + 15) / 16) * nch;
+        hipLaunchKernelGGL((slice8_rows_kernel<S, DenseRows>), dim3((unsigned)blocks), dim3(256), 0, st,
+                           DenseRows{src, ld}, R, K, sl, ex, R);
+    } else {
+        const int64_t blocks = ((R + 31) / 32) * nch;
+        hipLaunchKernelGGL((slice8_cols_kernel<S>), dim3((unsigned)blocks), dim3(256), 0, st, src, ld, R, K, sl, ex, R);
+    }
+    return hipGetLastError();
+}
+
 // Slices src into the buffer b (rows b.R, length b.K).  transposed: element
 // (r, k) at src[k*ld + r]; otherwise at src[r*ld + k].
 int slice_into(int S, bool transposed, const double* src, int64_t ld, char* ws, const SlicedBuf& b, hipStream_t st) {
-    StageTimer tm(LADDER_STAGE_SLICE, 0.0, (8.0 + 2.0 * S) * (double)b.R * (double)b.K, st);
+    StageTimer tm(LADDER_STAGE_SLICE, 0.0, (8.0 + slice_elem_bytes(S)) * (double)b.R * (double)b.K, st);
+    if (slice_is_i8(S) != b.i8) return fail(LADDER_EINVAL, "internal: slice format of the buffer");
     unsigned short* sl = (unsigned short*)(ws + b.s_off);
     int* ex = (int*)(ws + b.e_off);
     hipError_t e;
+    if (slice_is_i8(S)) {
+        int8_t* s8 = (int8_t*)(ws + b.s_off);
+        switch (slice_count(S)) {
+            case 2: e = slice8_s<2>(transposed, src, ld, b.R, b.K, s8, ex, st); break;
+            case 3: e = slice8_s<3>(transposed, src, ld, b.R, b.K, s8, ex, st); break;
+            case 4: e = slice8_s<4>(transposed, src, ld, b.R, b.K, s8, ex, st); break;
+            case 5: e = slice8_s<5>(transposed, src, ld, b.R, b.K, s8, ex, st); break;
+            case 6: e = slice8_s<6>(transposed, src, ld, b.R, b.K, s8, ex, st); break;
+            default: e = hipErrorInvalidValue;
+        }
+        return hip_check(e, "slice launch");
+    }
     switch (S) {
         case 2: e = slice_s<2>(transposed, src, ld, b.R, b.K, sl, ex, st); break;
         case 3: e = slice_s<3>(transposed, src, ld, b.R, b.K, sl, ex, st); break;
@@ -523,9 +616,28 @@ hipError_t slice_tile_s(const PmTileRows& src, const SlicedBuf& b, char* ws, hip
                        (unsigned short*)(ws + b.s_off), (int*)(ws + b.e_off), b.R);
     return hipGetLastError();
 }
+template <int S>
+hipError_t slice8_tile_s(const PmTileRows& src, const SlicedBuf& b, char* ws, hipStream_t st) {
+    const int64_t blocks = ((b.R + 15) / 16) * split_nchunk(b.K);
+    hipLaunchKernelGGL((slice8_rows_kernel<S, PmTileRows>), dim3((unsigned)blocks), dim3(256), 0, st, src, b.R, b.K,
+                       (int8_t*)(ws + b.s_off), (int*)(ws + b.e_off), b.R);
+    return hipGetLastError();
+}
 int slice_tile_into(int S, const PmTileRows& src, char* ws, const SlicedBuf& b, hipStream_t st) {
-    StageTimer tm(LADDER_STAGE_SLICE, 0.0, (16.0 + 2.0 * S) * (double)b.R * (double)b.K, st);
+    StageTimer tm(LADDER_STAGE_SLICE, 0.0, (16.0 + slice_elem_bytes(S)) * (double)b.R * (double)b.K, st);
+    if (slice_is_i8(S) != b.i8) return fail(LADDER_EINVAL, "internal: slice format of the buffer");
     hipError_t e;
+    if (slice_is_i8(S)) {
+        switch (slice_count(S)) {
+            case 2: e = slice8_tile_s<2>(src, b, ws, st); break;
+            case 3: e = slice8_tile_s<3>(src, b, ws, st); break;
+            case 4: e = slice8_tile_s<4>(src, b, ws, st); break;
+            case 5: e = slice8_tile_s<5>(src, b, ws, st); break;
+            case 6: e = slice8_tile_s<6>(src, b, ws, st); break;
+            default: e = hipErrorInvalidValue;
+        }
+        return hip_check(e, "tile slice launch");
+    }
     switch (S) {
         case 2: e = slice_tile_s<2>(src, b, ws, st); break;
         case 3: e = slice_tile_s<3>(src, b, ws, st); break;
@@ -700,7 +812,8 @@ __global__ __launch_bounds__(256) void abic_wam_kernel(const double* __restrict_
 // register operands (no memory traffic besides one checksum per thread), so the time
 // of a launch is the matrix-core rate the chip sustains under its own clock and power
 // limits.  KIND 0: v_mfma_f32_32x32x16_bf16 (32768 flops), KIND 1: v_mfma_f64_16x16x4_f64
-// (2048 flops).  The operands vary per lane, like real slice data.
+// (2048 flops), KIND 2: v_mfma_i32_32x32x32_i8 (65536 operations).  The operands vary per
+// lane, like real slice data.
 template <int KIND>
 __global__ __launch_bounds__(256) void mfma_probe_kernel(int64_t iters, double* __restrict__ out) {
     const int lane = threadIdx.x & 63;
@@ -725,7 +838,7 @@ __global__ __launch_bounds__(256) void mfma_probe_kernel(int64_t iters, double* 
         for (int k = 0; k < 4; ++k)
 #pragma unroll
             for (int r = 0; r < 16; ++r) sum += (double)acc[k][r];
-    } else {
+    } else if constexpr (KIND == 1) {
         const double a = 1.0 + 0.001 * (double)lane, b = 0.5 - 0.0005 * (double)lane;
         dx4 acc[4];
 #pragma unroll
@@ -736,6 +849,30 @@ __global__ __launch_bounds__(256) void mfma_probe_kernel(int64_t iters, double* 
         }
 #pragma unroll
         for (int k = 0; k < 4; ++k) sum += acc[k][0] + acc[k][1] + acc[k][2] + acc[k][3];
+    } else {
+        ix4 a, b;  // bytes in [-64, 64], as INT8 slices
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            uint32_t wa = 0, wb = 0;
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                wa |= (uint32_t)(((lane * 16 + 4 * i + j) * 37 % 129 - 64) & 0xff) << (8 * j);
+                wb |= (uint32_t)(((lane * 11 + 5 * i + 3 * j) * 53 % 129 - 64) & 0xff) << (8 * j);
+            }
+            a[i] = (int)wa;
+            b[i] = (int)wb;
+        }
+        ix16 acc[4];
+#pragma unroll
+        for (int k = 0; k < 4; ++k) acc[k] = ix16{};
+        for (int64_t it = 0; it < iters; ++it) {
+#pragma unroll
+            for (int k = 0; k < 4; ++k) acc[k] = __builtin_amdgcn_mfma_i32_32x32x32_i8(a, b, acc[k], 0, 0, 0);
+        }
+#pragma unroll
+        for (int k = 0; k < 4; ++k)
+#pragma unroll
+            for (int r = 0; r < 16; ++r) sum += (double)acc[k][r];
     }
     out[(int64_t)blockIdx.x * blockDim.x + threadIdx.x] = sum;
 }
@@ -762,7 +899,7 @@ unsigned grid_for(int64_t total) {
 
 // The split GEMM addresses a 128-row operand tile with 32-bit byte offsets.
 int check_split_dims(const Sizes& s, int64_t n, const ladder_options& op) {
-    if (op.precision != LADDER_SPLIT_BF16) return LADDER_OK;
+    if (op.precision == LADDER_FP64) return LADDER_OK;
     // the slicer grids: up to v^2 rows in blocks of 16 times the chunks of the longest k
     const int64_t kmax = std::max(std::max(s.vv, s.oo), n);
     if ((s.vv / 16 + 1) * split_nchunk(kmax) >= (int64_t(1) << 31))
@@ -841,7 +978,7 @@ int forward_pm(int64_t o, int64_t v, int64_t n, const double* L, const double* t
                 e = launch_gemm<true, true, LADDER_STAGE_GEMM_C>(sign ? tm : tp, K, sign ? gm : gp, K, M, N, K, er, st);
             } else {
                 SplitShape sh{view(w, sign ? p.tm_cd : p.tp_cd, 0), view(w, sign ? gms : gps, 0), M, N, K};
-                sh.ksplit = choose_ksplit(M, N, K, p.f_skp_elems);
+                sh.ksplit = choose_ksplit(S, M, N, K, p.f_skp_elems);
                 sh.part = (double*)(w + p.f_skp);
                 e = launch_split<LADDER_STAGE_GEMM_C>(S, sh, er, st);
             }
@@ -952,7 +1089,7 @@ int adjoint_pm(int64_t o, int64_t v, int64_t n, const double* L, const double* t
                 SlicedBuf lb = p.L_b;
                 lb.K = nB * v;
                 SplitShape sh{view(w, tl, 0), pass ? view(w, lb, 0) : view(w, p.L_bd, 0), M, n, K};
-                sh.ksplit = choose_ksplit(M, n, K, p.a_skp_elems);
+                sh.ksplit = choose_ksplit(S, M, n, K, p.a_skp_elems);
                 sh.part = (double*)(w + p.a_skp);
                 e = launch_split<LADDER_STAGE_GEMM_F>(S, sh, ex, st);
             }
@@ -1005,8 +1142,9 @@ int batch_plan(int count, const ladder_instance* inst, uint32_t what, const ladd
         if (oi.n_abatch == 0 && tuned_batch(tune_key(x.o, x.v, x.n, oi), tuned)) oi.n_abatch = tuned;
         if (oi.n_abatch == 0) {
             int64_t per_a = s.vvv * 8;
-            if (oi.precision == LADDER_SPLIT_BF16)
-                per_a += (int64_t)(slice_bytes(std::max(oi.n_slices, oi.n_slices_adjoint), x.v, s.vv) + exp_bytes(x.v, s.vv));
+            if (oi.precision != LADDER_FP64)
+                per_a += (int64_t)(slice_bytes(slice_spec(oi, std::max(oi.n_slices, oi.n_slices_adjoint)), x.v, s.vv) +
+                                   exp_bytes(x.v, s.vv));
             oi.n_abatch = std::max<int64_t>(1, std::min<int64_t>((int64_t)(BATCH_TILE_BYTES / (size_t)per_a), (x.v + 1) / 2));
         }
         bp.inst_opts[i] = oi;
@@ -1117,7 +1255,7 @@ int forward_impl(int64_t o, int64_t v, int64_t n, const double* L, const double*
     if (E) {
         // Batch bi writes partial slots [bi*ppb, bi*ppb + tiles of its GEMM-C); every
         // batch but the last fills all ppb of them, so the slots in use are contiguous.
-        const int64_t used_last = tiles(s.oo, (v - (p.nbatch - 1) * p.nA) * v);
+        const int64_t used_last = split_tiles(S, s.oo, (v - (p.nbatch - 1) * p.nA) * v);
         const int64_t count = (int64_t)p.part_per_batch * (p.nbatch - 1) + used_last;
         StageTimer tm(LADDER_STAGE_ENERGY, (double)count, 8.0 * (double)count, st);
         hipLaunchKernelGGL(reduce_partials_kernel, dim3(1), dim3(256), 0, st, part, count, E);
@@ -1380,7 +1518,7 @@ int adjoint_impl(int64_t o, int64_t v, int64_t n, const double* L, const double*
                 SlicedBuf tl = p.tile_sl;
                 tl.R = nA * v;
                 SplitShape sh{view(w, tl, 0), view(w, p.L_bd, 0), nA * v, n, s.vv};
-                sh.ksplit = choose_ksplit(nA * v, n, s.vv, p.a_skp_elems);
+                sh.ksplit = choose_ksplit(S, nA * v, n, s.vv, p.a_skp_elems);
                 sh.part = (double*)(w + p.a_skp);
                 e = launch_split<LADDER_STAGE_GEMM_F>(S, sh, ex, st);
             }
@@ -1506,8 +1644,8 @@ int ladder_autotune(int64_t o, int64_t v, int64_t n, const double* L, const doub
                 "{\"device\": \"%s\", \"o\": %lld, \"v\": %lld, \"n\": %lld, \"precision\": %d, \"n_slices\": %d, "
                 "\"n_slices_adjoint\": %d, \"flags\": %u, \"n_abatch\": %lld, \"est_ms\": %.1f}\n",
                 device_tag().c_str(), (long long)o, (long long)v, (long long)n, (int)op.precision,
-                op.precision == LADDER_SPLIT_BF16 ? (int)op.n_slices : 0,
-                op.precision == LADDER_SPLIT_BF16 ? (int)op.n_slices_adjoint : 0, (unsigned)op.flags, (long long)best,
+                op.precision != LADDER_FP64 ? (int)op.n_slices : 0,
+                op.precision != LADDER_FP64 ? (int)op.n_slices_adjoint : 0, (unsigned)op.flags, (long long)best,
                 best_est);
         fclose(f);
     }
@@ -1749,7 +1887,7 @@ int abic_layout(int64_t o, int64_t v, int64_t n, const ladder_options* opts, Abi
     ladder_options op;
     int rc;
     if ((rc = check_dims(o, v, n, s)) || (rc = get_opts(opts, op))) return rc;
-    l.slices = op.precision == LADDER_SPLIT_BF16 ? (int)op.n_slices : 0;
+    l.slices = slice_spec(op, op.n_slices);
     int64_t ovn, oon, ooov, vvv;
     if (!mul_ok(o * v, n, ovn) || !mul_ok(o * o, n, oon) || !mul_ok(o * o, o * v, ooov) || !mul_ok(s.vv, v, vvv) ||
         ovn > INT64_MAX / 16 || ooov > INT64_MAX / 16)
@@ -1795,6 +1933,7 @@ int abic_layout(int64_t o, int64_t v, int64_t n, const ladder_options* opts, Abi
             SlicedBuf b;
             b.R = R;
             b.K = K;
+            b.i8 = slice_is_i8(l.slices);
             b.s_off = at;
             b.e_off = at + align_up(slice_bytes(l.slices, R, K));
             return b;
@@ -2078,13 +2217,13 @@ int gemm_layout(int64_t M, int64_t N, int64_t K, const ladder_options& op, GemmL
                     (long long)N, (long long)K);
     if ((M / F64_BM + 1) * (N / F64_BN + 1) >= (int64_t(1) << 31))
         return fail(LADDER_EINVAL, "M*N too large for one launch");
-    if (op.precision != LADDER_SPLIT_BF16) return LADDER_OK;
+    if (op.precision == LADDER_FP64) return LADDER_OK;
     if ((std::max(M, N) / 16 + 1) * split_nchunk(K) >= (int64_t(1) << 31) ||
         2 * (split_kpad(K) / 16) * SPLIT_PANEL * 16 * 2 + 4096 >= (int64_t(1) << 32))
         return fail(LADDER_EUNSUPPORTED, "split precision: K or max(M, N) too large for the slicer grid or panel offsets");
     Arena a;
-    l.a = take_sliced(a, op.n_slices, M, K);
-    l.b = take_sliced(a, op.n_slices, N, K);
+    l.a = take_sliced(a, slice_spec(op, op.n_slices), M, K);
+    l.b = take_sliced(a, slice_spec(op, op.n_slices), N, K);
     l.total = a.top;
     return LADDER_OK;
 }
@@ -2129,26 +2268,31 @@ int ladder_gemm(int64_t M, int64_t N, int64_t K, double alpha, const double* A, 
     hipStream_t st = (hipStream_t)stream;
     EpiStrided ep{C, ldc, alpha, beta, nullptr, nullptr};
     StageTimer tm(LADDER_STAGE_GEMM, gemm_flops(M, N, K), gemm_bytes(M, N, K), st);
-    if (op.precision != LADDER_SPLIT_BF16)
+    if (op.precision == LADDER_FP64)
         return hip_check(launch_gemm<true, true, LADDER_STAGE_GEMM>(A, lda, B, ldb, M, N, K, ep, st), "GEMM launch");
     char* w = (char*)ws;
-    if ((rc = slice_into(op.n_slices, false, A, lda, w, l.a, st))) return rc;
-    if ((rc = slice_into(op.n_slices, false, B, ldb, w, l.b, st))) return rc;
+    const int S = slice_spec(op, op.n_slices);
+    if ((rc = slice_into(S, false, A, lda, w, l.a, st))) return rc;
+    if ((rc = slice_into(S, false, B, ldb, w, l.b, st))) return rc;
     SplitShape sh{view(w, l.a, 0), view(w, l.b, 0), M, N, K};
-    return hip_check(launch_split<LADDER_STAGE_GEMM>(op.n_slices, sh, ep, st), "split GEMM launch");
+    return hip_check(launch_split<LADDER_STAGE_GEMM>(S, sh, ep, st), "split GEMM launch");
 }
 
 int ladder_mfma_probe(int kind, int64_t iters, int64_t blocks, double* out, double* flops, void* stream) {
     g_last_error.clear();
-    if (kind != LADDER_PROBE_BF16 && kind != LADDER_PROBE_FP64) return fail(LADDER_EUNSUPPORTED, "probe kind %d", kind);
+    if (kind != LADDER_PROBE_BF16 && kind != LADDER_PROBE_FP64 && kind != LADDER_PROBE_INT8)
+        return fail(LADDER_EUNSUPPORTED, "probe kind %d", kind);
     if (iters < 1 || iters > ((int64_t)1 << 32) || blocks < 1 || blocks > ((int64_t)1 << 20))
         return fail(LADDER_EINVAL, "iters must be in [1, 2^32] and blocks in [1, 2^20]");
     if (!out || !aligned8(out)) return fail(LADDER_EINVAL, "out must be a non-NULL 8-byte aligned device pointer");
-    const double per = kind == LADDER_PROBE_BF16 ? 2.0 * 32 * 32 * 16 : 2.0 * 16 * 16 * 4;
+    const double per = kind == LADDER_PROBE_BF16 ? 2.0 * 32 * 32 * 16 : kind == LADDER_PROBE_INT8 ? 2.0 * 32 * 32 * 32
+                                                                                                : 2.0 * 16 * 16 * 4;
     if (flops) *flops = (double)blocks * 4.0 * (double)iters * 4.0 * per;  // 4 waves x 4 MFMAs per round
     hipStream_t st = (hipStream_t)stream;
     if (kind == LADDER_PROBE_BF16)
         hipLaunchKernelGGL(mfma_probe_kernel<0>, dim3((unsigned)blocks), dim3(256), 0, st, iters, out);
+    else if (kind == LADDER_PROBE_INT8)
+        hipLaunchKernelGGL(mfma_probe_kernel<2>, dim3((unsigned)blocks), dim3(256), 0, st, iters, out);
     else
         hipLaunchKernelGGL(mfma_probe_kernel<1>, dim3((unsigned)blocks), dim3(256), 0, st, iters, out);
     return hip_check(hipGetLastError(), "probe launch");

@@ -191,6 +191,7 @@ struct SplitOperand {
     int64_t nkb;              // k-blocks per panel, Kp / 16
     const int* e;             // exponent of (row 0, chunk 0) of this view
     int64_t e_ld;             // chunk stride of the exponent array
+    bool i8 = false;          // INT8 slices (split_i8.hpp): s holds bytes, strides in bytes, nkb = Kp / 32
 };
 
 struct SplitShape {

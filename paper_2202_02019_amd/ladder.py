@@ -18,6 +18,7 @@ _LIB_PATH = os.path.join(PKG, "libladder.so")
 
 FP64 = 0
 SPLIT_BF16 = 1
+SPLIT_INT8 = 2
 FLAG_GENERAL = 1
 FLAG_DENSE = 2
 DO_FORWARD = 1
@@ -451,6 +452,7 @@ def metric_contraction_pairs(Z, W, *, pairs, n, V=None, alpha=1.0, beta=0.0, str
 
 PROBE_BF16 = 0
 PROBE_FP64 = 1
+PROBE_INT8 = 2
 
 
 def mfma_probe(kind, iters, blocks, out=None, stream=None):

@@ -369,3 +369,27 @@ def test_adjoint_slice_count_option():
     assert w44 < w45 <= w55 and w44 < w54 <= w55
     # in FP64 the field is ignored
     assert P.workspace_size(o, v, n, P.Options(n_slices_adjoint=3)) == P.workspace_size(o, v, n)
+
+
+def test_int8_precision_option():
+    """LADDER_SPLIT_INT8: the same slice-count rules as BF16; its slices take one byte per
+    element and 32-k blocks, so a one-panel ladder_gemm operand is 128 rows x 32 k bytes per
+    slice, and the forward's workspace is below the BF16 one at the same counts."""
+    INT8 = 2
+    assert P.SPLIT_INT8 == INT8 and P.PROBE_INT8 == 2
+    assert fwd(opts=_opts(precision=INT8, n_slices=7)) == EUNSUPPORTED
+    assert fwd(opts=_opts(precision=INT8, n_slices=1)) == EUNSUPPORTED
+    assert fwd(opts=_opts(precision=INT8, n_slices_adjoint=7)) == EUNSUPPORTED
+    assert fwd(opts=_opts(precision=3)) == EUNSUPPORTED
+    lib = _lib()
+    b = ctypes.c_size_t(0)
+    assert lib.ladder_gemm_workspace_size(3, 4, 5, _opts(precision=INT8, n_slices=3), ctypes.byref(b)) == 0
+    assert b.value == 2 * (3 * 128 * 32 + 256)
+    o, v, n = 6, 40, 90
+    w8 = P.workspace_size(o, v, n, P.Options(precision=INT8, n_slices=5, n_slices_adjoint=5, n_abatch=4,
+                                             flags=P.FLAG_DENSE))
+    w16 = P.workspace_size(o, v, n, P.Options(precision=1, n_slices=5, n_slices_adjoint=5, n_abatch=4,
+                                              flags=P.FLAG_DENSE))
+    assert w8 < w16
+    fl = ctypes.c_double(0.0)
+    assert lib.ladder_mfma_probe(INT8, 0, 4, FAKE, ctypes.byref(fl), None) == EINVAL

@@ -384,10 +384,12 @@ def test_autograd_gradcheck(dev, o, v, n, seed):
     assert torch.autograd.gradcheck(f, args, eps=1e-6, atol=1e-9, rtol=1e-7)
 
 
-def test_retinal_split_sampled(dev):
-    """o=78, v=657, n=2200, seed 3, in the configuration the benchmark times (split BF16, 5 forward
-    and 4 adjoint slices, +/- packed, the batch size of the committed autotune cache): one forward
-    and one adjoint on
+@pytest.mark.parametrize("precision,S_fwd,S_adj", [pytest.param(P.SPLIT_INT8, 6, 5, id="int8-6-5"),
+                                                 pytest.param(P.SPLIT_BF16, 5, 4, id="bf16-5-4")])
+def test_retinal_split_sampled(dev, precision, S_fwd, S_adj):
+    """o=78, v=657, n=2200, seed 3, in the configurations the benchmark times (INT8 slices 6
+    forward / 5 adjoint, its default, and BF16 5 / 4; +/- packed, the batch size of the committed
+    autotune cache): one forward and one adjoint on
     the GPU-drawn recipe inputs, then sampled rows of R (all ij for chosen ab) and of X (all J for
     chosen ac) against the oracle, computed one by one from host copies of the same arrays."""
     import os
@@ -401,7 +403,7 @@ def test_retinal_split_sampled(dev):
     tau = P.mp2_amplitudes(Lov, SG.draw_eps(seed, o, v), o=o, v=v, n=n)
     del Lov
     tbar = SG.add_noise(seed, o, v, tau)
-    opts = P.Options(precision=P.SPLIT_BF16, n_slices_adjoint=4)
+    opts = P.Options(precision=precision, n_slices=S_fwd, n_slices_adjoint=S_adj)
     ws = torch.empty(P.workspace_size(o, v, n, opts), dtype=torch.uint8, device=dev)
     R, E = P.forward(L, tau, tbar, o=o, v=v, n=n, ws=ws, opts=opts)
     X = P.adjoint(L, tau, tbar, o=o, v=v, n=n, ws=ws, opts=opts)
