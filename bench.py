@@ -129,6 +129,57 @@ def measured_traffic(workload, precision, kernel, n_abatch):
     return rec["kernels"][kernel]["bytes"]
 
 
+def traffic_summary(args):
+    """rocprofv3 FETCH_SIZE / WRITE_SIZE counter CSVs (KiB per dispatch) of the default split
+    command run with --copy-probe -> HBM bytes per launch of each split GEMM stage.  Each counter
+    is scaled by what it reads for the 1 GiB device-to-device copy (its largest copy dispatch),
+    which moves 1 GiB each way; the record carries the source hash and the batch size that
+    measured_traffic checks before bench.py reports it."""
+    import collections
+    import csv
+    import re
+
+    def load(d):
+        per = collections.defaultdict(list)
+        with open(os.path.join(d, "run_counter_collection.csv")) as fh:
+            for r in csv.DictReader(fh):
+                per[r["Kernel_Name"]].append(float(r["Counter_Value"]))
+        return per
+
+    fetch, write = load(args.traffic_summary[0]), load(args.traffic_summary[1])
+
+    def probe(per):
+        return max(max(v) for k, v in per.items() if "copy" in k.lower())
+
+    ff, wf = (1 << 20) / probe(fetch), (1 << 20) / probe(write)
+    o, v, n, _ = WORKLOADS[args.workload]
+    sf, sa = DEFAULT_SLICES[args.precision]
+    nA = args.n_abatch or tuned_batch(args.tuned, o, v, n, PREC_CODE[args.precision], sf, 0, sa)
+    stage = {"0": "gemm_b", "1": "gemm_c", "3": "gemm_e", "4": "gemm_f"}
+    out = {"sources_sha256_16": gemm_source_hash(), "workload": args.workload, "precision": args.precision,
+           "n_abatch": nA, "n_slices": sf, "n_slices_adjoint": sa, "fetch_factor": ff, "write_factor": wf,
+           "kernels": {}}
+    rows = []
+    for k in fetch:
+        fk = sum(fetch[k]) / len(fetch[k])
+        wk = sum(write.get(k, [0.0])) / max(1, len(write.get(k, [])))
+        gb = (fk * ff + wk * wf) * 1024 / 1e9
+        rows.append((gb, "| `%s` | %d | %.4g | %.4g | %.2f |" % (k.split("(")[0].replace("void ", ""), len(fetch[k]),
+                                                                 fk, wk, gb)))
+        m = re.search(r"gemm_(?:split|i8)_kernel<(\d), [^,]+, (\d+)>", k)
+        if m and m.group(2) in stage:
+            out["kernels"][stage[m.group(2)]] = {"fetch_kib": fk, "write_kib": wk, "bytes": (fk * ff + wk * wf) * 1024,
+                                                 "slices": int(m.group(1))}
+    path = os.path.join(ROOT, "profiles", "traffic_%s_%s_pm.json" % (args.workload, args.precision))
+    with open(path, "w") as fh:
+        json.dump(out, fh, indent=1)
+    print("copy probe: FETCH_SIZE x %.3f, WRITE_SIZE x %.3f; written %s" % (ff, wf, os.path.relpath(path, ROOT)))
+    print("| Kernel | Launches | FETCH KiB/launch (raw) | WRITE KiB/launch (raw) | HBM GB/launch (scaled) |")
+    print("|---|---|---|---|---|")
+    for _, line in sorted(rows, key=lambda x: -x[0])[:14]:
+        print(line)
+
+
 def blas_threads():
     """Threads of the BLAS that numpy's matrix products run on (what the CPU oracle uses)."""
     try:
@@ -181,6 +232,10 @@ def main():
                          "(0 = the plain recipe)")
     ap.add_argument("--copy-probe", action="store_true",
                     help="run a 1 GiB device copy first (reference kernel for the HBM traffic counters)")
+    ap.add_argument("--traffic-summary", nargs=2, metavar=("FETCH_DIR", "WRITE_DIR"), default=None,
+                    help="no GPU: turn the counter CSVs of two rocprofv3 --pmc passes (FETCH_SIZE, then WRITE_SIZE) "
+                         "of this workload's default command with --copy-probe into "
+                         "profiles/traffic_<workload>_<precision>_pm.json and print the per-kernel table")
     ap.add_argument("--fd", type=int, default=200, metavar="K",
                     help="autograd workload: LadderEnergy forward + backward (split) timed, then K central finite "
                          "differences of the FP64 energy (step 1e-6) on random L entries against its dE/dL "
@@ -194,6 +249,8 @@ def main():
         print("bench.py: the ladder is measured on one GPU (one MI355X); "
               "--gpus %d is not supported" % args.gpus, file=sys.stderr)
         sys.exit(2)
+    if args.traffic_summary:
+        return traffic_summary(args)
 
     import numpy as np
     import torch
