@@ -270,7 +270,7 @@ def main():
     prec_code = PREC_CODE[args.precision]
     split = args.precision != "fp64"
     # the benchmark's slice counts per format unless given; the library's rule then applies
-    # (n_slices 0 means 5, n_slices_adjoint 0 means n_slices)
+    # (n_slices 0 means 5 for BF16 and 6 for INT8, n_slices_adjoint 0 means n_slices)
     dfw, dadj = DEFAULT_SLICES.get(args.precision, (5, 4))
     if not args.slices:
         args.slices = dfw

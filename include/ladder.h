@@ -79,8 +79,8 @@ extern "C" {
 typedef struct {
     int32_t precision;        /* LADDER_FP64, LADDER_SPLIT_BF16 or LADDER_SPLIT_INT8 */
     int32_t n_slices;         /* split modes: slices per operand of the forward's GEMMs (the g tile and
-                                 the R update) and of every other split product; 0 = the default, 5;
-                                 otherwise 2..6 */
+                                 the R update) and of every other split product; 0 = the default, 5 for
+                                 BF16 and 6 for INT8 (the counts that meet 1e-10 in E); otherwise 2..6 */
     int64_t n_abatch;         /* virtual indices a per batch, 0 = automatic */
     uint32_t flags;           /* LADDER_FLAG_* */
     int32_t n_slices_adjoint; /* split mode: slices of the adjoint's GEMMs (the density tile and the X

@@ -63,7 +63,8 @@ int hip_check(hipError_t e, const char* what) {
 }
 
 constexpr int64_t MAX_DIM = int64_t(1) << 20;
-constexpr int DEFAULT_SLICES = 5;
+constexpr int DEFAULT_SLICES = 5;       // BF16
+constexpr int DEFAULT_SLICES_INT8 = 6;  // seven bits per slice: six meet the energy target where five do not
 
 // ------------------------------------------------------------ stage timing
 struct StageRec {
@@ -138,9 +139,10 @@ int get_opts(const ladder_options* in, ladder_options& o) {
         return fail(LADDER_EUNSUPPORTED, "unknown precision %d", (int)o.precision);
     if (o.n_slices_adjoint < 0) return fail(LADDER_EINVAL, "n_slices_adjoint must be >= 0");
     if (o.precision != LADDER_FP64) {
-        if (o.n_slices == 0) o.n_slices = DEFAULT_SLICES;
+        const int dflt = o.precision == LADDER_SPLIT_INT8 ? DEFAULT_SLICES_INT8 : DEFAULT_SLICES;
+        if (o.n_slices == 0) o.n_slices = dflt;
         if (o.n_slices < 2 || o.n_slices > SPLIT_MAX_S)
-            return fail(LADDER_EUNSUPPORTED, "n_slices must be 0 (default %d) or in [2, %d], got %d", DEFAULT_SLICES,
+            return fail(LADDER_EUNSUPPORTED, "n_slices must be 0 (default %d) or in [2, %d], got %d", dflt,
                         SPLIT_MAX_S, (int)o.n_slices);
         if (o.n_slices_adjoint == 0) o.n_slices_adjoint = o.n_slices;
         if (o.n_slices_adjoint < 2 || o.n_slices_adjoint > SPLIT_MAX_S)

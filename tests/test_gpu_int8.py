@@ -163,3 +163,17 @@ def test_int8_mfma_probe(dev):
     torch.cuda.synchronize()
     assert ops == ops2 == 16 * 4 * 64 * 4 * (2 * 32 * 32 * 32)
     assert torch.isfinite(a).all() and torch.equal(a, b) and float(a.abs().sum()) > 0
+
+
+@pytest.mark.parametrize("flags", [0, P.FLAG_DENSE])
+def test_int8_tau_gradient(dev, flags):
+    """The transposed ladder (dE/dtau, the forward path with tbar for tau) in INT8 slices against
+    the oracle at the R tolerance."""
+    o, v, n = 6, 30, 120
+    L, tau, tbar, _, _ = oracle.make_inputs(o, v, n, 11)
+    opts = P.Options(precision=P.SPLIT_INT8, n_slices=6, n_slices_adjoint=5, flags=flags)
+    G = P.tau_gradient(g(L, dev), g(tbar, dev), o=o, v=v, n=n, opts=opts)
+    torch.cuda.synchronize()
+    eG = err_norm(G.cpu().numpy(), oracle.tau_gradient(o, v, n, L, tbar))
+    print("int8 tau gradient flags %d: err %.3e" % (flags, eG))
+    assert eG <= TOL_RX

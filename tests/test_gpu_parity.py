@@ -544,7 +544,7 @@ def _instances(dev, shapes, seed0):
     return insts, refs
 
 
-@pytest.mark.parametrize("precision", [P.FP64, P.SPLIT_BF16])
+@pytest.mark.parametrize("precision", [P.FP64, P.SPLIT_BF16, P.SPLIT_INT8])
 def test_batched_matches_single_calls_and_oracle(dev, precision):
     shapes = [(3, 17, 30), (5, 9, 11), (2, 40, 70), (4, 23, 5), (6, 31, 44), (1, 12, 9), (7, 6, 20), (3, 50, 33),
               (2, 19, 101), (4, 8, 16)]

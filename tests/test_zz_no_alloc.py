@@ -22,7 +22,8 @@ def g(x, dev):
 
 
 @pytest.mark.parametrize("precision,n_abatch,flags", [(P.FP64, 0, 0), (P.SPLIT_BF16, 0, 0), (P.FP64, 4, P.FLAG_DENSE),
-                                                      (P.SPLIT_BF16, 3, 0)])
+                                                      (P.SPLIT_BF16, 3, 0), (P.SPLIT_INT8, 0, 0),
+                                                      (P.SPLIT_INT8, 3, P.FLAG_DENSE)])
 def test_noalloc_forward_matches_forward(dev, precision, n_abatch, flags):
     opts = P.Options(precision=precision, n_abatch=n_abatch, flags=flags)
     for k, (o, v, n) in enumerate([(5, 37, 70), (3, 20, 33)]):   # the second call is smaller
