@@ -691,3 +691,17 @@ def test_mp2_amplitudes_and_update(oracle_lib):
     t2 = oracle_lib.amplitude_update(o, v, eps, R, t)
     den = (eps[:o, None, None, None] + eps[None, :o, None, None]) - (eps[None, None, o:, None] + eps[None, None, None, o:])
     np.testing.assert_allclose((t2 - t) * den, R, rtol=1e-12, atol=0)
+
+
+def test_mp2_amplitudes_minimal_basis_h2(oracle_lib):
+    """A textbook case independent of the oracle's formula: H2 in the minimal STO-3G basis at
+    R = 1.4 bohr (Szabo and Ostlund, Modern Quantum Chemistry, ch. 3 and 6), one occupied and
+    one virtual orbital with eps_1 = -0.578, eps_2 = 0.670 and K_12 = (12|21) = 0.1813 Eh,
+    whose second-order energy is E(2) = K_12^2 / (2 (eps_1 - eps_2)) = -0.0132 Eh.  With one
+    Cholesky vector sqrt(K_12), the oracle's amplitude t_11^22 must give
+    E(2) = sum t_ij^ab (2 (ia|jb) - (ib|ja)) = t K_12 at that value (to the table's rounding)."""
+    eps1, eps2, K12 = -0.578, 0.670, 0.1813
+    Lov = np.full((1, 1, 1), np.sqrt(K12))
+    t = oracle_lib.mp2_amplitudes(1, 1, 1, Lov, np.array([eps1, eps2]))
+    E2 = float(t[0, 0, 0, 0]) * (2.0 * K12 - K12)
+    assert t[0, 0, 0, 0] < 0 and abs(E2 - (-0.0132)) <= 1e-4
