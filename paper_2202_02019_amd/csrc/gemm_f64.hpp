@@ -38,15 +38,17 @@ struct TileMap {
     int64_t tiles_m, tiles_n;
 };
 
-// Linear workgroup id -> (tile row, tile col), XCD-contiguous and grouped.
-__device__ inline void map_tile(int64_t w, int64_t T, const TileMap& tm, int64_t& ti, int64_t& tj) {
+// Linear workgroup id -> (tile row, tile col), XCD-contiguous and grouped: the tiles an XCD
+// runs are consecutive, walked in groups of gm tile rows, column by column.
+__device__ inline void map_tile(int64_t w, int64_t T, const TileMap& tm, int64_t& ti, int64_t& tj,
+                                int gm = GROUP_M) {
     const int64_t xcd = w % NUM_XCD, local = w / NUM_XCD;
     const int64_t per = T / NUM_XCD, rem = T % NUM_XCD;
     const int64_t tile = xcd * per + (xcd < rem ? xcd : rem) + local;
-    const int64_t group = (int64_t)GROUP_M * tm.tiles_n;
+    const int64_t group = (int64_t)gm * tm.tiles_n;
     const int64_t g = tile / group;
-    const int64_t first = g * GROUP_M;
-    const int64_t gsz = (tm.tiles_m - first) < GROUP_M ? (tm.tiles_m - first) : GROUP_M;
+    const int64_t first = g * gm;
+    const int64_t gsz = (tm.tiles_m - first) < gm ? (tm.tiles_m - first) : gm;
     const int64_t in = tile - g * group;
     ti = first + in % gsz;
     tj = in / gsz;
