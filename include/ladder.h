@@ -124,9 +124,10 @@ int ladder_forward(int64_t o, int64_t v, int64_t n, const double* L, const doubl
  * ladder_forward would run if that plan's workspace fits the array, else the
  * largest virtual batch that fits; an explicit n_abatch is used as given.
  * Returns LADDER_EWORKSPACE, before any launch, when even that does not fit
- * (the packed amplitudes take about 4 o^2 v^2 bytes, 9 o^2 v^2 with their split
- * slices, and the batch tile about 16 v^3 bytes per virtual index on the default
- * +/- path).  Every call on one GPU uses that GPU's one array and leaves its
+ * (the packed amplitudes take about 4 o^2 v^2 bytes, 9 o^2 v^2 with five BF16
+ * slices and 7 o^2 v^2 with six INT8 ones, and the batch tile about 16 v^3 bytes
+ * per virtual index on the default +/- path; INT8 plans also hold up to 16 K-split
+ * partial tiles of the R update).  Every call on one GPU uses that GPU's one array and leaves its
  * contents behind (nothing in it needs clearing between calls): calls that
  * overlap on one GPU (two streams, two threads) race and must be serialised by
  * the caller.  No argument may lie inside the array.
