@@ -84,7 +84,8 @@ def gemm_source_hash():
     taken on)."""
     import hashlib
     h = hashlib.sha256()
-    for f in ("csrc/split_bf16.hpp", "csrc/gemm_f64.hpp", "csrc/pm_pack.hpp", "csrc/ladder.hip", "build.py"):
+    for f in ("csrc/split_bf16.hpp", "csrc/split_i8.hpp", "csrc/gemm_f64.hpp", "csrc/pm_pack.hpp", "csrc/ladder.hip",
+              "build.py"):
         with open(os.path.join(ROOT, "paper_2202_02019_amd", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
