@@ -418,6 +418,10 @@ def main():
                        "err_X_vs_fp64": err_max(X, X64),
                        "outputs_compared": "split outputs of warm-up step 0 (bitwise equal to the timed steps' when "
                                            "deterministic_vs_warmup is true)"}
+            # rows of the FP64 outputs kept for the BF16 leg below: R[:, :, a, :] and X[a] for three a
+            rows64 = sorted({0, v // 2, v - 1})
+            R64_rows = R64[:, :, rows64, :].clone()
+            X64_rows = X64[rows64].clone()
             del R64, X64
             torch.cuda.empty_cache()
             ws = torch.empty(wsb, dtype=torch.uint8, device=dev)
@@ -454,6 +458,44 @@ def main():
             del Lh, th, wh
             print("bench: CPU oracle sample %.1f s, %.0f s of the budget left" % (cs, left()), file=sys.stderr,
                   flush=True)
+
+    # the metric's named method beside the INT8 headline: one step of the same path with BF16 slices
+    # (5 forward / 4 adjoint, its tuned batch) on the same inputs, timed as it runs (its first
+    # launches load their code objects, well under a second), with E against the FP64 leg and the
+    # kept FP64 rows of R and X; its outputs go to R and X, which the timed steps overwrite
+    bf16 = None
+    if args.precision == "int8" and compare is not None and not args.dense:
+        if left() < 1.4 * t_step + t_step + 20.0:
+            skipped["bf16_comparison"] = "wall-clock budget"
+        else:
+            tb = tuned_batch(args.tuned if args.tuned not in (None, "none") else None, o, v, n, 1, 5, flags, 4)
+            if tb:
+                P.autotune_load(args.tuned)
+            ob = P.Options(precision=P.SPLIT_BF16, n_slices=5, n_slices_adjoint=4, n_abatch=0 if tb else 16)
+            del ws
+            torch.cuda.empty_cache()
+            wsb16 = torch.empty(P.workspace_size(o, v, n, ob), dtype=torch.uint8, device=dev)
+            Eb = torch.empty((), dtype=torch.float64, device=dev)
+            torch.cuda.synchronize()
+            ev0.record(stream)
+            P.forward(L, tau, tbar, o=o, v=v, n=n, R=R, E=Eb, ws=wsb16, opts=ob)
+            P.adjoint(L, tau, tbar, o=o, v=v, n=n, X=X, ws=wsb16, opts=ob)
+            ev1.record(stream)
+            torch.cuda.synchronize()
+            msb = ev0.elapsed_time(ev1)
+            del wsb16
+            torch.cuda.empty_cache()
+            eb = float(Eb.cpu())
+            bf16 = {"ms_per_step": msb, "n_slices": 5, "n_slices_adjoint": 4, "n_abatch": tb or 16,
+                    "timing": "one step, no warm-up of its own",
+                    "err_E_vs_fp64": abs(eb - e64) / abs(e64),
+                    "err_R_rows_vs_fp64": float((R[:, :, rows64, :] - R64_rows).abs().max() / R64_rows.abs().max()),
+                    "err_X_rows_vs_fp64": float((X[rows64] - X64_rows).abs().max() / X64_rows.abs().max()),
+                    "rows": "R[:, :, a, :] and X[a] for a in %s" % rows64,
+                    "speedup_vs_fp64": compare["fp64_ms_per_step"] / msb}
+            ws = torch.empty(wsb, dtype=torch.uint8, device=dev)
+            print("bench: bf16 comparison step %.1f s, %.0f s of the budget left" % (msb / 1e3, left()),
+                  file=sys.stderr, flush=True)
 
     # timed steps: as many as fit the rest of the budget (at most the number asked, at least one), then
     # further warm-up steps before them if there is still room
@@ -520,6 +562,11 @@ def main():
     if compare is not None:
         compare["fp64_tflops"] = executed / (compare["fp64_ms_per_step"] * 1e-3) / 1e12
         compare["speedup_vs_fp64"] = compare["fp64_ms_per_step"] / ms
+        if bf16 is not None:
+            # the same GEMM shapes: the FP64-equivalent flops executed per step are the INT8 step's
+            bf16["value"] = executed / (bf16["ms_per_step"] * 1e-3) / 1e12
+            bf16["unit"] = "TFLOP/s"
+            compare["bf16_split"] = bf16
 
     nxt = None
     if args.next_rows:
