@@ -15,11 +15,12 @@
 //           (2 W~ of Sec. II C; the factor 2 is d_pqrs = d_rspq, Appendix A)
 //
 // Precision LADDER_FP64 runs the four GEMMs on v_mfma_f64_16x16x4_f64.
-// Precision LADDER_SPLIT_BF16 first cuts every GEMM operand into S exponent-
-// aligned BF16 slices along its contraction index (inputs once per call, the g
-// and D tiles once per batch) and runs the GEMMs on BF16 MFMA with exact FP32
-// chunk sums folded into FP64 (split_bf16.hpp); R, E and X are accumulated and
-// stored in FP64.
+// Precisions LADDER_SPLIT_INT8 and LADDER_SPLIT_BF16 first cut every GEMM operand
+// into S exponent-aligned slices along its contraction index (inputs once per
+// call, the g and D tiles once per batch) and run the GEMMs on INT8 MFMA with
+// exact INT32 level sums (split_i8.hpp) or on BF16 MFMA with exact FP32 chunk
+// sums (split_bf16.hpp), folded into FP64; R, E and X are accumulated and stored
+// in FP64.
 #include <hip/hip_runtime.h>
 
 #include <stdarg.h>
@@ -1875,7 +1876,7 @@ namespace {
 //   three o^2 v^2 buffers (reordered operands and the o^2 v^2 intermediates V+Y, Yt and the
 //   amplitude matrices), B_iamn (o^3 v), the S_iacb slab of `g` occupied indices (g v^3),
 //   Zt (v^2 n), eight [o][v][n] or [o][o][n] buffers, Xvv (v^2), W_am (o v), P^K and Q^K (n).
-// Split precision adds the BF16 slices of the two operands of the o^3 v^3 GEMMs (rows
+// Split precision adds the slices of the two operands of the o^3 v^3 GEMMs (rows
 // o v, length o v; the slices of t along (mn) for S_iacb reuse the first one) and of one
 // B_i.. block (rows v, length o^2).
 struct AbicLayout {
@@ -2046,7 +2047,7 @@ int ladder_ov3_abic(int64_t o, int64_t v, int64_t n, double R0, const double* L1
         by += gemm_bytes(M, N, K);
     };
     // C(m, n) = sum_k A[m*K + k] B[n*K + k] for the (o v)^3 products: FP64 MFMA, or both
-    // operands sliced into BF16 and the split GEMM (FP64 combine, same epilogue).
+    // operands sliced (INT8 or BF16) and the split GEMM (FP64 combine, same epilogue).
     auto rows_gemm = [&](const double* A_, const double* B_, int64_t M, int64_t N, int64_t K, const auto& epi) -> int {
         acct(M, N, K);
         if (!l.slices) return hip_check(launch_gemm<true, true, LADDER_STAGE_OV3>(A_, K, B_, K, M, N, K, epi, st),
